@@ -1,0 +1,42 @@
+"""CPU oracle for the semi-discrete Monge-Ampere-Kantorovich hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark import this package; the product library and its Python
+binding never do.  It shares no code with the HIP implementation.
+
+Contents
+  cells(x, psi, L)       periodic Laguerre cell pass (C++ FP64, liboracle.so):
+                         volumes, first and second moments, faces.
+  hessian_dense / hessian_coo
+                         J = dV/dpsi from the faces (derived from Eq. SDK:
+                         the face between cells i and j moves by dpsi_j/|d|).
+  kantorovich(...)       K(psi) of Eq. SDK from the cell integrals.
+  solve(x, L, tol)       damped Newton on K (Sec. on MAK reconstruction: K is
+                         concave and C^2, maximised by Newton with the
+                         Kitagawa-Merigot-Thibert step control), dense Newton
+                         step for small N, plain CG otherwise.
+  exact                  exact-rational mini oracle (Python fractions).
+"""
+from .cells import cells, cell_faces_dict, load_library
+from .newton import (
+    hessian_dense,
+    hessian_coo,
+    kantorovich,
+    centroids_from_moments,
+    solve,
+    newton_step_dense,
+    newton_step_cg,
+)
+
+__all__ = [
+    "cells",
+    "cell_faces_dict",
+    "load_library",
+    "hessian_dense",
+    "hessian_coo",
+    "kantorovich",
+    "centroids_from_moments",
+    "solve",
+    "newton_step_dense",
+    "newton_step_cg",
+]

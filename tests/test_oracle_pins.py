@@ -1,0 +1,303 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test targets a different kind of mistake (dropped term, wrong sign or
+index, transposed operand) in the oracle's cell pass, Hessian or Newton solve.
+"""
+import json
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import exact
+from tests.closed_forms import layered_cells, layered_ot_psi
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dyadic_case(seed, n, grid=32, wgrid=1024, wspan=4):
+    rng = np.random.default_rng(seed)
+    while True:
+        xi = rng.integers(0, grid, size=(n, 3))
+        if len({tuple(r) for r in xi}) == n:
+            break
+    pi = rng.integers(-wspan, wspan + 1, size=n)
+    xf = xi / grid
+    pf = pi / wgrid
+    xq = [tuple(Fr(int(v), grid) for v in r) for r in xi]
+    pq = [Fr(int(p), wgrid) for p in pi]
+    return xf, pf, xq, pq
+
+
+# ---------------------------------------------------------------- P1 exact
+@pytest.mark.parametrize("seed,n", [(5, 8), (11, 12)])
+def test_p1_exact_rational(seed, n):
+    """FP64 oracle vs exact rational cells on dyadic inputs: volumes, first and
+    second moments and face areas to 1e-13 relative, same faces."""
+    xf, pf, xq, pq = _dyadic_case(seed, n)
+    r = oracle.cells(xf, pf, 1.0)
+    for i in range(n):
+        e = exact.cell(xq, pq, 1, i)
+        assert r["V"][i] == pytest.approx(float(e["V"]), rel=1e-13, abs=1e-16)
+        assert np.allclose(r["M"][i], [float(v) for v in e["M"]], rtol=1e-12, atol=1e-16)
+        assert r["S"][i] == pytest.approx(float(e["S"]), rel=1e-12, abs=1e-16)
+        fo = oracle.cell_faces_dict(r, i, include_box=True)
+        fe = {k: exact.area(v) for k, v in e["faces"].items()}
+        assert set(fo) == set(fe)
+        for k in fe:
+            assert fo[k][0] == pytest.approx(fe[k], rel=1e-12, abs=1e-15)
+
+
+def test_p1_golden_fixture():
+    """Stored exact cells (written by tests/golden/make_golden.py from the
+    exact oracle) still match the FP64 oracle."""
+    g = json.load(open(os.path.join(GOLDEN, "exact_cells_dyadic8.json")))
+    x = np.array(g["x"], dtype=np.float64)
+    psi = np.array(g["psi"], dtype=np.float64)
+    r = oracle.cells(x, psi, g["L"])
+    for i, c in enumerate(g["cells"]):
+        assert r["V"][i] == pytest.approx(float(Fr(c["V"])), rel=1e-13)
+        fo = oracle.cell_faces_dict(r, i)
+        fe = {tuple(f["key"]): f["area"] for f in c["faces"]}
+        assert set(fo) == set(fe)
+        for k in fe:
+            assert fo[k][0] == pytest.approx(fe[k], rel=1e-12)
+
+
+# ---------------------------------------------------------------- P2 lattice
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+@pytest.mark.parametrize("offset", [(0, 0, 0), (0.0123, -0.31, 0.077)])
+def test_p2_lattice(n, offset):
+    L = 1.0
+    D = L / n
+    x = workloads.lattice(n, L, offset=offset)
+    N = n ** 3
+    r = oracle.cells(x, np.zeros(N), L)
+    assert np.allclose(r["V"], D ** 3, rtol=1e-13)
+    assert np.allclose(r["M"], 0.0, atol=1e-15)
+    J = oracle.hessian_dense(r, N)
+    if n == 1:
+        assert J.shape == (1, 1) and J[0, 0] == 0.0
+        return
+    nbr = 6 if n >= 3 else 3
+    for i in range(N):
+        off = np.delete(J[i], i)
+        nz = off[np.abs(off) > 1e-12 * D]
+        assert len(nz) == nbr
+        assert np.allclose(nz, -D * (6 / nbr), rtol=1e-12)
+        assert J[i, i] == pytest.approx(6 * D, rel=1e-12)
+    for k in range(N):
+        faces = oracle.cell_faces_dict(r, k, min_area=1e-12 * D * D, include_box=True)
+        assert len(faces) == 6
+        assert all(a == pytest.approx(D * D, rel=1e-12) for a, _ in faces.values())
+
+
+def test_p2_lattice_solve_zero_iterations():
+    x = workloads.lattice(4, offset=(0.01, 0.02, 0.03))
+    s = oracle.solve(x, 1.0, tol=1e-10)
+    assert s["newton_iters"] == 0
+    assert np.allclose(s["disp"], 0.0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- P3 layered
+@pytest.mark.parametrize("nl", [2, 3, 5])
+def test_p3_layered_cells(nl):
+    rng = np.random.default_rng(nl)
+    L = 1.0
+    X = np.sort(rng.uniform(0, L, nl))
+    dmin = np.min(np.diff(np.append(X, X[0] + L)))
+    psi_l = rng.uniform(-1, 1, nl) * 0.1 * dmin ** 2
+    ny = nz = 4
+    x = workloads.layered(X, ny, nz, L)
+    psi = np.repeat(psi_l, ny * nz)
+    r = oracle.cells(x, psi, L)
+    V, ux, J = layered_cells(X, psi_l, ny, nz, L)
+    assert np.all(V > 0)
+    assert np.allclose(r["V"], V, rtol=1e-12, atol=1e-15)
+    u = r["M"] / r["V"][:, None]
+    assert np.allclose(u[:, 0], ux, rtol=1e-11, atol=1e-13)
+    assert np.allclose(u[:, 1:], 0.0, atol=1e-13)
+    Jo = oracle.hessian_dense(r, len(x))
+    assert np.allclose(Jo, J, rtol=1e-11, atol=1e-12)
+
+
+# ---------------------------------------------------------------- P4 layered OT
+def test_p4_layered_ot_solution():
+    rng = np.random.default_rng(7)
+    L = 1.0
+    nl, ny = 6, 4
+    X = np.sort(rng.uniform(0, L, nl))
+    psi_l, b = layered_ot_psi(X, L)
+    x = workloads.layered(X, ny, ny, L)
+    N = len(x)
+    psi = np.repeat(psi_l, ny * ny)
+    r = oracle.cells(x, psi, L)
+    assert np.allclose(r["V"], L ** 3 / N, rtol=1e-11)
+    # and Newton from psi = 0 lands on the same psi up to a constant
+    s = oracle.solve(x, L, tol=1e-10)
+    ref = psi - psi.mean()
+    assert np.allclose(s["psi"], ref, atol=1e-10)
+    cx = np.sort(np.unique(np.round(s["centroids"][:, 0], 9)))
+    assert np.allclose(np.diff(cx), L / nl, atol=1e-9)
+
+
+# ---------------------------------------------------------------- P5 invariants
+def _random_case(n=6, seed=3, wscale=0.03):
+    x = workloads.zeldovich(n, rms=0.6, smooth=1.0, seed=seed)
+    rng = np.random.default_rng(seed)
+    D = 1.0 / n
+    psi = rng.uniform(-1, 1, len(x)) * wscale * D * D
+    return x, psi
+
+
+def test_p5_volume_sum_and_pyramid_identity():
+    x, psi = _random_case()
+    r = oracle.cells(x, psi, 1.0)
+    assert r["V"].sum() == pytest.approx(1.0, rel=1e-12)
+    fp = r["face_ptr"]
+    for k in range(len(x)):
+        sl = slice(fp[k], fp[k + 1])
+        h = r["face_b"][sl] / r["face_dist"][sl]
+        assert r["V"][k] == pytest.approx(np.sum(r["face_area"][sl] * h) / 3.0, rel=1e-11)
+
+
+def test_p5_hessian_symmetric_zero_rowsum():
+    x, psi = _random_case()
+    r = oracle.cells(x, psi, 1.0)
+    J = oracle.hessian_dense(r, len(x))
+    assert np.abs(J - J.T).max() <= 1e-12 * np.abs(J).max()
+    assert np.abs(J.sum(axis=1)).max() <= 1e-13 * np.abs(J).max()
+    assert np.all(r["V"] > 0) and np.all(np.diag(J) > 0)
+
+
+def test_p5_monotone_map():
+    """(x_i - x_j')(c_i - c_j') >= 0 across every face (discrete form of the
+    convex Brenier potential: no shell crossing)."""
+    x, psi = _random_case(seed=5)
+    r = oracle.cells(x, psi, 1.0)
+    u = r["M"] / r["V"][:, None]
+    fp = r["face_ptr"]
+    for k in range(len(x)):
+        for f in range(fp[k], fp[k + 1]):
+            j = r["face_j"][f]
+            if j == k:
+                continue
+            s = r["face_shift"][f]
+            xj = x[j] + s
+            ci = x[k] + u[k]
+            cj = xj + u[j]
+            assert np.dot(x[k] - xj, ci - cj) >= -1e-15
+
+
+def test_p5_psi_shift_translation_permutation_scaling():
+    x, psi = _random_case(seed=9)
+    N = len(x)
+    r = oracle.cells(x, psi, 1.0)
+    r2 = oracle.cells(x, psi + 0.37, 1.0)
+    assert np.allclose(r2["V"], r["V"], rtol=1e-10)
+    t = np.array([0.3, -0.12, 0.71])
+    r3 = oracle.cells(workloads.wrap(x + t, 1.0), psi, 1.0)
+    assert np.allclose(r3["V"], r["V"], rtol=1e-10)
+    perm = np.random.default_rng(1).permutation(N)
+    r4 = oracle.cells(x[perm], psi[perm], 1.0)
+    assert np.allclose(r4["V"], r["V"][perm], rtol=1e-12)
+    lam = 2.5
+    r5 = oracle.cells(x * lam, psi * lam ** 2, lam)
+    assert np.allclose(r5["V"], r["V"] * lam ** 3, rtol=1e-12)
+    assert np.allclose(r5["M"], r["M"] * lam ** 4, rtol=1e-10, atol=1e-15)
+
+
+# ---------------------------------------------------------------- P6 finite differences
+def test_p6_gradient_of_K():
+    x, psi = _random_case(seed=13)
+    N = len(x)
+    m = np.full(N, 1.0 / N)
+    r = oracle.cells(x, psi, 1.0)
+    g = m - r["V"]
+    h = 1e-7
+    for i in (0, 17, 101, N - 1):
+        e = np.zeros(N)
+        e[i] = h
+        kp = oracle.kantorovich(oracle.cells(x, psi + e, 1.0), psi + e, m)
+        km = oracle.kantorovich(oracle.cells(x, psi - e, 1.0), psi - e, m)
+        assert (kp - km) / (2 * h) == pytest.approx(g[i], abs=1e-6 * np.abs(g).max())
+
+
+def test_p6_hessian_columns():
+    x, psi = _random_case(seed=17)
+    N = len(x)
+    r = oracle.cells(x, psi, 1.0)
+    J = oracle.hessian_dense(r, N)
+    h = 1e-8
+    for j in (3, 50, 150):
+        e = np.zeros(N)
+        e[j] = h
+        col = (oracle.cells(x, psi + e, 1.0)["V"] - oracle.cells(x, psi - e, 1.0)["V"]) / (2 * h)
+        assert np.allclose(col, J[:, j], atol=1e-6 * np.abs(J).max())
+
+
+# ---------------------------------------------------------------- P7 raster
+def test_p7_raster_brute_force():
+    """Assign a fine grid of sample points to the cell of smallest power
+    distance (minimum image); counts times voxel volume approach V."""
+    n = 3
+    x, psi = _random_case(n=n, seed=21, wscale=0.2)
+    r = oracle.cells(x, psi, 1.0)
+    M = 96
+    h = 1.0 / M
+    g = (np.arange(M) + 0.5) * h
+    Q = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    best = np.full(Q.shape[0], np.inf)
+    owner = np.zeros(Q.shape[0], dtype=np.int64)
+    for i in range(len(x)):
+        d = Q - x[i]
+        d -= np.round(d)
+        p = 0.5 * np.sum(d * d, axis=1) - psi[i]
+        better = p < best
+        best[better] = p[better]
+        owner[better] = i
+    V = np.bincount(owner, minlength=len(x)) * h ** 3
+    # O(h) boundary error: within 1% of the mean cell volume at h = L/96
+    assert np.max(np.abs(V - r["V"])) <= 0.01 / len(x)
+
+
+# ---------------------------------------------------------------- P8 Newton step
+def test_p8_dense_vs_cg_newton_step():
+    x, psi = _random_case(seed=23)
+    N = len(x)
+    r = oracle.cells(x, psi, 1.0)
+    g = 1.0 / N - r["V"]
+    p1 = oracle.newton_step_dense(oracle.hessian_dense(r, N), g)
+    p2 = oracle.newton_step_cg(oracle.hessian_coo(r, N), g)
+    assert np.allclose(p1 - p1.mean(), p2, atol=1e-8 * np.abs(p1).max())
+    J = oracle.hessian_dense(r, N)
+    assert np.allclose(J @ p1, g - g.mean(), atol=1e-12)
+
+
+def test_oracle_solve_small_zeldovich():
+    x = workloads.zeldovich(6, rms=0.5, smooth=1.0, seed=31)
+    s = oracle.solve(x, 1.0, tol=1e-9)
+    assert s["err"] <= 1e-9
+    # certificate: recompute the cells at the returned psi
+    r = oracle.cells(x, s["psi"], 1.0)
+    N = len(x)
+    assert np.max(np.abs(r["V"] - 1.0 / N)) * N <= 1e-9
+    # the errors fall quadratically at the end
+    e = s["errs"]
+    assert e[-1] < e[0]
+
+
+def test_oracle_flags():
+    x = workloads.lattice(2)
+    x2 = np.vstack([x, x[:1]])
+    r = oracle.cells(x2, np.zeros(9), 1.0)
+    assert r["flags"][0] & 2
+    # a very negative weight empties a cell
+    psi = np.zeros(8)
+    psi[0] = -10.0
+    r = oracle.cells(x, psi, 1.0)
+    assert r["flags"][0] & 1 and r["V"][0] == 0.0
+    assert r["V"].sum() == pytest.approx(1.0, rel=1e-12)
