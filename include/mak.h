@@ -1,0 +1,167 @@
+/*
+ * mak.h -- C-ABI of the MI355X semi-discrete optimal transport library.
+ *
+ * The library computes the hot path of semi-discrete Monge-Ampere-Kantorovich
+ * (MAK) reconstruction: the periodic Laguerre (power) diagram of N sites under
+ * weights psi (Eq. laguerrecell), the cell integrals that give the gradient
+ * and Hessian of the semi-discrete Kantorovich dual K(psi) (Eq. SDK), and the
+ * damped Newton maximisation of K (the paper's Newton method on the concave,
+ * C^2 functional K; step control of Kitagawa-Merigot-Thibert).
+ *
+ * Conventions shared by every entry point
+ *   - Domain: the flat torus [0, L)^3.  Points outside are wrapped, not
+ *     rejected.  Masses are uniform, m_i = L^3 / N (initial density 1).
+ *   - Pointers marked DEVICE are HIP device memory on the context's device;
+ *     the caller owns them.  Pointers marked HOST are host memory.
+ *   - Points are row-major (N, 3) float64 (x, y, z); weights (N,) float64.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = the default stream).
+ *     mak_laguerre_cells returns after enqueueing plus one device-to-host
+ *     read of the nonzero count; mak_solve blocks until the outputs are
+ *     written (Newton control runs on the host).
+ *   - Errors are returned as mak_status; nothing throws across the ABI.  The
+ *     message of the last failure on a context is at mak_last_error().
+ *     After an error the outputs are unspecified.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef MAK_H
+#define MAK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MAK_OK = 0,
+  MAK_EINVAL = 1,       /* N < 1, L not finite or <= 0, tol <= 0, NULL pointer,
+                           non-finite coordinate or weight */
+  MAK_ENOMEM = 2,       /* device allocation failed / memory budget exceeded */
+  MAK_EDEGENERATE = 3,  /* two sites coincide after wrapping */
+  MAK_ENOCONV = 4,      /* Newton iteration or line-search limit reached */
+  MAK_EOVERFLOW = 5,    /* a cell exceeded the largest polytope capacity */
+  MAK_EHIP = 6,         /* HIP runtime error */
+  MAK_ENOTFOUND = 7     /* unknown request id (server) */
+} mak_status;
+
+typedef enum {
+  MAK_FP64 = 0,   /* clipping, integrals and Newton all in float64 */
+  MAK_MIXED = 1   /* clipping in float32 seed-local coordinates, integrals
+                     accumulated in float64, near-degenerate cells re-run in
+                     float64; Newton, line search and CG in float64 */
+} mak_precision;
+
+typedef struct {
+  int32_t precision;       /* mak_precision, default MAK_FP64 */
+  int32_t max_newton;      /* Newton iteration cap, default 60 */
+  int32_t max_cg;          /* CG iterations per Newton step, default 4000 */
+  int32_t max_halvings;    /* line-search halvings per step, default 30 */
+  double cg_rtol;          /* CG stop: ||r|| <= cg_rtol ||g||, default 1e-3 */
+  double grid_occupancy;   /* target sites per neighbour-grid cell, default 2.5 */
+  size_t mem_budget_bytes; /* 0 = no limit (server admission uses it) */
+  int32_t verbose;         /* 1: one line per Newton iteration on stderr */
+  int32_t reserved[7];
+} mak_options;
+
+/* Fill `opt` with the defaults listed above. */
+void mak_default_options(mak_options* opt);
+
+typedef struct {
+  int32_t newton_iters;       /* accepted Newton steps */
+  int32_t cg_iters_total;     /* CG iterations over all steps */
+  int32_t ls_trials;          /* cell passes spent in the line search */
+  int32_t cell_passes;        /* all cell passes */
+  int64_t fp64_rerun_cells;   /* cells re-run in float64 (mixed precision) */
+  int64_t overflow_cells;     /* cells re-run with the large polytope capacity */
+  double final_err;           /* max_i |V_i - m_i| / m_i at exit */
+  double seconds;             /* wall time of the call */
+} mak_solve_info;
+
+typedef struct {
+  int64_t empty_cells;        /* cells with zero volume at this psi */
+  int64_t fp64_rerun_cells;   /* mixed precision: cells re-run in float64 */
+  int64_t overflow_cells;     /* cells re-run with the large polytope capacity */
+  int64_t nnz;                /* nonzeros of the Hessian (with diagonal) */
+  int64_t faces;              /* reported faces (each (i, j, image) once per side) */
+  int32_t max_faces;          /* largest face count of one cell */
+  int32_t reserved;
+} mak_cells_info;
+
+typedef struct mak_ctx mak_ctx;
+
+/* Create a context on HIP device `device` with options `opt` (NULL = the
+ * defaults).  The context owns its device workspace, grown on demand and
+ * released by mak_destroy.  *out is set on success. */
+mak_status mak_create(mak_ctx** out, int device, const mak_options* opt);
+void mak_destroy(mak_ctx* ctx);
+
+/* Message of the last error on `ctx` (or of the last mak_create failure when
+ * ctx is NULL).  Valid until the next call on the context. */
+const char* mak_last_error(const mak_ctx* ctx);
+
+/* One Laguerre cell pass (Eq. laguerrecell on the torus, integrands of
+ * Eq. SDK).
+ *   points     DEVICE (N, 3) float64, read only
+ *   psi        DEVICE (N,) float64 weights, read only
+ *   volumes    DEVICE (N,) float64 out: |V_i| (0 for an empty cell)
+ *   centroids  DEVICE (N, 3) float64 out: centroid of V_i wrapped into
+ *              [0, L)^3 (x_i for an empty cell)
+ *   info       HOST, may be NULL: counters of this pass
+ * The pass also builds the Hessian J = dV/dpsi (= minus the Hessian of K):
+ * J_ij = -sum over the faces between cell i and images of site j of
+ * area / |x_i - x_j^image|, J_ii = -sum_j J_ij; fetch it with
+ * mak_hessian_copy.  Faces of a cell with its own images do not enter J. */
+mak_status mak_laguerre_cells(mak_ctx* ctx, const double* points, const double* psi,
+                              int64_t N, double L, double* volumes, double* centroids,
+                              mak_cells_info* info, void* stream);
+
+/* Copy the Hessian of the last mak_laguerre_cells call on `ctx` as CSR with
+ * sorted columns (diagonal included):
+ *   row_ptr  DEVICE int64 [N + 1]
+ *   col      DEVICE int32 [nnz]
+ *   val      DEVICE float64 [nnz]
+ * nnz is mak_cells_info.nnz of that call. */
+mak_status mak_hessian_copy(mak_ctx* ctx, int64_t* row_ptr, int32_t* col, double* val,
+                            void* stream);
+
+/* Copy the faces of the last mak_laguerre_cells call (test and diagnostics
+ * interface; faces with the site's own images are not reported):
+ *   face_ptr   DEVICE int64 [N + 1], faces of cell i at face_ptr[i]..[i+1]
+ *   face_j     DEVICE int32 [faces]  other site
+ *   face_shift DEVICE int32 [faces, 3] periodic image of site j
+ *   face_area  DEVICE float64 [faces]
+ * `faces` is mak_cells_info.faces of that call.  Faces are sorted by
+ * (j, shift) within a cell. */
+mak_status mak_faces_copy(mak_ctx* ctx, int64_t* face_ptr, int32_t* face_j, int32_t* face_shift,
+                          double* face_area, void* stream);
+
+/* Damped Newton maximisation of K(psi) from psi = 0 until
+ * max_i |V_i - m_i| / m_i <= tol (m_i = L^3 / N).
+ *   points         DEVICE (N, 3) float64, read only
+ *   psi            DEVICE (N,) float64 out: the weights, mean zero
+ *   centroids      DEVICE (N, 3) float64 out: cell centroids (the
+ *                  Lagrangian positions), wrapped into [0, L)^3
+ *   displacements  DEVICE (N, 3) float64 out: x_i - centroid_i taken in the
+ *                  site's own frame (no wrap ambiguity)
+ *   info           HOST, may be NULL
+ * Returns MAK_ENOCONV if the Newton or line-search limit is hit (outputs then
+ * hold the last accepted iterate). */
+mak_status mak_solve(mak_ctx* ctx, const double* points, int64_t N, double L, double tol,
+                     double* psi, double* centroids, double* displacements,
+                     mak_solve_info* info, void* stream);
+
+/* As mak_solve, starting from the weights in `psi` (DEVICE, read and
+ * overwritten): resumes a solve from a saved psi (the whole solver state). */
+mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double L, double tol,
+                          double* psi, double* centroids, double* displacements,
+                          mak_solve_info* info, void* stream);
+
+/* Device memory a solve of N sites needs at most (bytes), for admission. */
+size_t mak_solve_memory_estimate(int64_t N, int32_t precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAK_H */

@@ -1,0 +1,255 @@
+"""MI355X semi-discrete optimal transport (MAK reconstruction hot path).
+
+Thin ctypes binding of libmak.so (include/mak.h): argument marshalling only.
+PyTorch provides the device memory and the stream; every step of the cell
+pass and of the Newton solve runs in the HIP kernels of the library.  There is
+no fallback: if the library is not built, or no GPU is present, the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "MakError", "Context", "load_library", "laguerre_cells", "solve", "solve_from",
+    "memory_estimate", "LIB_PATH", "EXPORTED_SYMBOLS",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmak.so")
+
+EXPORTED_SYMBOLS = [
+    "mak_default_options", "mak_create", "mak_destroy", "mak_last_error",
+    "mak_laguerre_cells", "mak_hessian_copy", "mak_faces_copy", "mak_solve",
+    "mak_solve_from", "mak_solve_memory_estimate",
+]
+
+STATUS = {0: "MAK_OK", 1: "MAK_EINVAL", 2: "MAK_ENOMEM", 3: "MAK_EDEGENERATE",
+          4: "MAK_ENOCONV", 5: "MAK_EOVERFLOW", 6: "MAK_EHIP", 7: "MAK_ENOTFOUND"}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+class MakError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        self.message = message
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+        ("max_cg", ctypes.c_int32), ("max_halvings", ctypes.c_int32),
+        ("cg_rtol", ctypes.c_double), ("grid_occupancy", ctypes.c_double),
+        ("mem_budget_bytes", ctypes.c_size_t), ("verbose", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 7),
+    ]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("newton_iters", ctypes.c_int32), ("cg_iters_total", ctypes.c_int32),
+        ("ls_trials", ctypes.c_int32), ("cell_passes", ctypes.c_int32),
+        ("fp64_rerun_cells", ctypes.c_int64), ("overflow_cells", ctypes.c_int64),
+        ("final_err", ctypes.c_double), ("seconds", ctypes.c_double),
+    ]
+
+
+class _CellsInfo(ctypes.Structure):
+    _fields_ = [
+        ("empty_cells", ctypes.c_int64), ("fp64_rerun_cells", ctypes.c_int64),
+        ("overflow_cells", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("faces", ctypes.c_int64), ("max_faces", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+def _as_dict(s) -> dict:
+    return {name: getattr(s, name) for name, _ in s._fields_ if name != "reserved"}
+
+
+_LIB = None
+
+
+def load_library():
+    """Load libmak.so (built in-tree by __graft_entry__.build())."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, D, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int32
+    lib.mak_default_options.argtypes = [P]
+    lib.mak_default_options.restype = None
+    lib.mak_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+    lib.mak_create.restype = ctypes.c_int
+    lib.mak_destroy.argtypes = [P]
+    lib.mak_destroy.restype = None
+    lib.mak_last_error.argtypes = [P]
+    lib.mak_last_error.restype = ctypes.c_char_p
+    lib.mak_laguerre_cells.argtypes = [P, P, P, I64, D, P, P, P, P]
+    lib.mak_laguerre_cells.restype = ctypes.c_int
+    lib.mak_hessian_copy.argtypes = [P, P, P, P, P]
+    lib.mak_hessian_copy.restype = ctypes.c_int
+    lib.mak_faces_copy.argtypes = [P, P, P, P, P, P]
+    lib.mak_faces_copy.restype = ctypes.c_int
+    lib.mak_solve.argtypes = [P, P, I64, D, D, P, P, P, P, P]
+    lib.mak_solve.restype = ctypes.c_int
+    lib.mak_solve_from.argtypes = [P, P, I64, D, D, P, P, P, P, P]
+    lib.mak_solve_from.restype = ctypes.c_int
+    lib.mak_solve_memory_estimate.argtypes = [I64, I32]
+    lib.mak_solve_memory_estimate.restype = ctypes.c_size_t
+    _LIB = lib
+    return lib
+
+
+def default_options() -> dict:
+    lib = load_library()
+    o = _Options()
+    lib.mak_default_options(ctypes.byref(o))
+    return _as_dict(o)
+
+
+def memory_estimate(n: int, precision: str = "fp64") -> int:
+    return int(load_library().mak_solve_memory_estimate(int(n), PRECISION[precision]))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the MAK library runs only on the device")
+    return torch
+
+
+class Context:
+    """A library context on one device (owns the device workspace)."""
+
+    def __init__(self, device: int = 0, precision: str = "fp64", **opts):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        o = _Options()
+        self.lib.mak_default_options(ctypes.byref(o))
+        o.precision = PRECISION[precision]
+        for k, v in opts.items():
+            if not hasattr(o, k):
+                raise TypeError(f"unknown option {k}")
+            setattr(o, k, v)
+        self.options = _as_dict(o)
+        h = ctypes.c_void_p()
+        torch.cuda.init()
+        st = self.lib.mak_create(ctypes.byref(h), device, ctypes.byref(o))
+        if st != 0:
+            raise MakError(st, self.lib.mak_last_error(None).decode())
+        self._h = h
+        self._last_nnz = None
+        self._last_faces = None
+        self._last_n = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.mak_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != 0:
+            raise MakError(st, self.lib.mak_last_error(self._h).decode())
+
+    def _stream(self):
+        torch = _torch()
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _dev(self, t, shape_tail=None):
+        torch = _torch()
+        t = torch.as_tensor(t)
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        if shape_tail is not None and tuple(t.shape[1:]) != shape_tail:
+            raise ValueError(f"expected shape (N,{shape_tail}), got {tuple(t.shape)}")
+        return t
+
+    def laguerre_cells(self, points, psi, L: float):
+        """Volumes (N,) and centroids (N,3) of the periodic Laguerre cells;
+        the Hessian and faces of this pass are kept for hessian()/faces()."""
+        torch = _torch()
+        x = self._dev(points, (3,))
+        n = x.shape[0]
+        w = self._dev(psi)
+        if w.shape != (n,):
+            raise ValueError("psi must have shape (N,)")
+        V = torch.empty(n, dtype=torch.float64, device=self.device)
+        C = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        info = _CellsInfo()
+        self._check(self.lib.mak_laguerre_cells(self._h, x.data_ptr(), w.data_ptr(), n, float(L),
+                                                V.data_ptr(), C.data_ptr(), ctypes.byref(info),
+                                                self._stream()))
+        self._last_n, self._last_nnz, self._last_faces = n, info.nnz, info.faces
+        return V, C, _as_dict(info)
+
+    def hessian(self):
+        """CSR (row_ptr int64, col int32, val float64) of J = dV/dpsi of the
+        last cell pass (original index order)."""
+        torch = _torch()
+        n, nnz = self._last_n, self._last_nnz
+        rp = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mak_hessian_copy(self._h, rp.data_ptr(), col.data_ptr(), val.data_ptr(),
+                                              self._stream()))
+        return rp, col[:nnz], val[:nnz]
+
+    def faces(self):
+        """Faces of the last cell pass: face_ptr (N+1), j, shift (F,3), area."""
+        torch = _torch()
+        n, nf = self._last_n, self._last_faces
+        fp = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        fj = torch.empty(max(nf, 1), dtype=torch.int32, device=self.device)
+        fs = torch.empty((max(nf, 1), 3), dtype=torch.int32, device=self.device)
+        fa = torch.empty(max(nf, 1), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mak_faces_copy(self._h, fp.data_ptr(), fj.data_ptr(), fs.data_ptr(),
+                                            fa.data_ptr(), self._stream()))
+        return {"face_ptr": fp, "face_j": fj[:nf], "face_shift": fs[:nf], "face_area": fa[:nf]}
+
+    def _solve(self, fn, points, L, tol, psi0):
+        torch = _torch()
+        x = self._dev(points, (3,))
+        n = x.shape[0]
+        if psi0 is None:
+            psi = torch.empty(n, dtype=torch.float64, device=self.device)
+        else:
+            psi = self._dev(psi0).clone()
+        C = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        D = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        info = _SolveInfo()
+        st = fn(self._h, x.data_ptr(), n, float(L), float(tol), psi.data_ptr(), C.data_ptr(),
+                D.data_ptr(), ctypes.byref(info), self._stream())
+        self._check(st)
+        return psi, C, D, _as_dict(info)
+
+    def solve(self, points, L: float, tol: float = 1e-6):
+        """Damped Newton OT solve from psi = 0: (psi, centroids, displacements, info)."""
+        return self._solve(self.lib.mak_solve, points, L, tol, None)
+
+    def solve_from(self, points, psi0, L: float, tol: float = 1e-6):
+        """Resume a solve from saved weights psi0."""
+        return self._solve(self.lib.mak_solve_from, points, L, tol, psi0)
+
+
+def laguerre_cells(points, psi, L: float, device: int = 0, precision: str = "fp64"):
+    return Context(device, precision).laguerre_cells(points, psi, L)
+
+
+def solve(points, L: float, tol: float = 1e-6, device: int = 0, precision: str = "fp64", **opts):
+    return Context(device, precision, **opts).solve(points, L, tol)
+
+
+def solve_from(points, psi0, L: float, tol: float = 1e-6, device: int = 0, precision: str = "fp64",
+               **opts):
+    return Context(device, precision, **opts).solve_from(points, psi0, L, tol)

@@ -1,0 +1,356 @@
+// C-ABI entry points (include/mak.h) and the host driver of the damped Newton
+// iteration on the semi-discrete Kantorovich dual.
+//
+// Newton (the paper's method: K concave and C^2, maximised with first and
+// second derivatives): g = m - V(psi), solve J p = g by Jacobi-PCG, then the
+// Kitagawa-Merigot-Thibert step control: eps0 = 1/2 min(min m, min V(psi^0));
+// accept psi + alpha p for the largest alpha in {1, 1/2, ...} with
+// min V >= eps0 and ||m - V|| <= (1 - alpha/2) ||g||.  The trial passes are
+// full passes (faces included), so an accepted trial's Hessian is reused.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <utility>
+
+#include "engine.h"
+
+using namespace mak;
+
+namespace mak {
+
+void swap_buf(DevBuf& a, DevBuf& b) {
+  std::swap(a.p, b.p);
+  std::swap(a.cap, b.cap);
+}
+
+void swap_pass(CellPass& a, CellPass& b) {
+  swap_buf(a.vol, b.vol);
+  swap_buf(a.mom, b.mom);
+  swap_buf(a.cflags, b.cflags);
+  swap_buf(a.nface, b.nface);
+  swap_buf(a.faces, b.faces);
+  swap_buf(a.fbase, b.fbase);
+  swap_buf(a.ovf, b.ovf);
+  swap_buf(a.counters, b.counters);
+  swap_buf(a.retry, b.retry);
+  swap_buf(a.scan_tmp, b.scan_tmp);
+  std::swap(a.fslot, b.fslot);
+  std::swap(a.ovf_cap, b.ovf_cap);
+}
+
+namespace {
+
+__global__ void k_flag_stats(const int32_t* __restrict__ cf, const int32_t* __restrict__ nface,
+                             unsigned long long* out, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  unsigned long long e = 0, c = 0, nm = 0, mf = 0;
+  if (i < n) {
+    e = (cf[i] & CF_EMPTY) ? 1 : 0;
+    c = (cf[i] & CF_COINCIDENT) ? 1 : 0;
+    nm = (cf[i] & CF_NONMANIFOLD) ? 1 : 0;
+    mf = (unsigned long long)nface[i];
+  }
+  // wave-aggregated atomics
+  e = (unsigned long long)wave_sum_i(int(e));
+  c = (unsigned long long)wave_sum_i(int(c));
+  nm = (unsigned long long)wave_sum_i(int(nm));
+  int m = int(mf);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+  if (lane_id() == 0) {
+    if (e) atomicAdd(&out[0], e);
+    if (c) atomicAdd(&out[1], c);
+    if (nm) atomicAdd(&out[2], nm);
+    atomicMax(&out[3], (unsigned long long)m);
+  }
+}
+
+struct FlagStats {
+  int64_t empty, coincident, nonmanifold, max_faces;
+};
+
+FlagStats flag_stats(const PointSet& ps, const CellPass& cp, DevBuf& tmp, hipStream_t st) {
+  tmp.ensure(8 * sizeof(unsigned long long));
+  MAK_HIP(hipMemsetAsync(tmp.p, 0, 8 * sizeof(unsigned long long), st));
+  hipLaunchKernelGGL(k_flag_stats, dim3(unsigned(ceil_div(ps.N, 256))), dim3(256), 0, st,
+                     cp.cflags.as<int32_t>(), cp.nface.as<int32_t>(),
+                     tmp.as<unsigned long long>(), ps.N);
+  MAK_HIP(hipGetLastError());
+  unsigned long long h[4];
+  MAK_HIP(hipMemcpyAsync(h, tmp.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  return {int64_t(h[0]), int64_t(h[1]), int64_t(h[2]), int64_t(h[3])};
+}
+
+}  // namespace
+}  // namespace mak
+
+struct mak_ctx {
+  int device = 0;
+  mak_options opt{};
+  std::string err;
+  // last mak_laguerre_cells
+  PointSet ps;
+  CellPass cp;
+  Csr J;
+  DevBuf face_ptr;
+  int64_t nfaces = 0;
+  bool cells_valid = false;
+  // solver
+  PointSet sps;
+  CellPass scp, scp_trial;
+  Csr sJ;
+  PcgWork pw;
+  DevBuf psi_s, psi_t, g, pstep, tmp;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F>
+mak_status guarded(mak_ctx* ctx, F&& f) {
+  try {
+    f();
+    return MAK_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->err = e.msg;
+    return e.status;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->err = e.what();
+    return MAK_EHIP;
+  }
+}
+
+void check_args(int64_t N, double L) {
+  if (N < 1) MAK_FAIL(MAK_EINVAL, "N must be >= 1");
+  if (N >= (int64_t(1) << 31)) MAK_FAIL(MAK_EINVAL, "N must be < 2^31");
+  if (!std::isfinite(L) || !(L > 0)) MAK_FAIL(MAK_EINVAL, "L must be finite and > 0");
+}
+
+void set_device(const mak_ctx* ctx) { MAK_HIP(hipSetDevice(ctx->device)); }
+
+}  // namespace
+
+extern "C" {
+
+void mak_default_options(mak_options* opt) {
+  if (!opt) return;
+  std::memset(opt, 0, sizeof(*opt));
+  opt->precision = MAK_FP64;
+  opt->max_newton = 60;
+  opt->max_cg = 4000;
+  opt->max_halvings = 30;
+  opt->cg_rtol = 1e-3;
+  opt->grid_occupancy = 2.5;
+  opt->mem_budget_bytes = 0;
+  opt->verbose = 0;
+}
+
+mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
+  if (!out) return MAK_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device";
+    return MAK_EHIP;
+  }
+  if (device < 0 || device >= count) {
+    g_create_error = "device index out of range";
+    return MAK_EINVAL;
+  }
+  mak_ctx* c = new mak_ctx();
+  c->device = device;
+  mak_default_options(&c->opt);
+  if (opt) c->opt = *opt;
+  if (c->opt.precision != MAK_FP64 && c->opt.precision != MAK_MIXED) {
+    delete c;
+    g_create_error = "unknown precision";
+    return MAK_EINVAL;
+  }
+  if (!(c->opt.cg_rtol > 0) || c->opt.max_newton < 0 || c->opt.max_cg < 1 || c->opt.max_halvings < 0) {
+    delete c;
+    g_create_error = "invalid options";
+    return MAK_EINVAL;
+  }
+  *out = c;
+  return MAK_OK;
+}
+
+void mak_destroy(mak_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  delete ctx;
+}
+
+const char* mak_last_error(const mak_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+mak_status mak_laguerre_cells(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
+                              double L, double* volumes, double* centroids, mak_cells_info* info,
+                              void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    check_args(N, L);
+    if (!points || !psi || !volumes || !centroids) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    set_device(ctx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ctx->cells_valid = false;
+    build_pointset(ctx->ps, points, psi, N, L, ctx->opt.grid_occupancy, st);
+    ClipStats cs = run_cells(ctx->ps, ctx->cp, ctx->opt.precision, true, st);
+    FlagStats fs = flag_stats(ctx->ps, ctx->cp, ctx->tmp, st);
+    if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
+    build_csr(ctx->ps, ctx->cp, ctx->J, true, st);
+    ctx->nfaces = count_faces(ctx->ps, ctx->cp, ctx->J, ctx->face_ptr, st);
+    scatter_cells_outputs(ctx->ps, ctx->cp.vol.as<double>(), ctx->cp.mom.as<double>(), volumes,
+                          centroids, st);
+    ctx->cells_valid = true;
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->empty_cells = fs.empty;
+      info->overflow_cells = cs.retried;
+      info->nnz = ctx->J.nnz;
+      info->faces = ctx->nfaces;
+      info->max_faces = int32_t(fs.max_faces);
+    }
+  });
+}
+
+mak_status mak_hessian_copy(mak_ctx* ctx, int64_t* row_ptr, int32_t* col, double* val, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    if (!ctx->cells_valid) MAK_FAIL(MAK_EINVAL, "no cell pass to copy from");
+    if (!row_ptr || !col || !val) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    set_device(ctx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Csr& J = ctx->J;
+    MAK_HIP(hipMemcpyAsync(row_ptr, J.row_ptr.p, size_t(J.n + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, st));
+    MAK_HIP(hipMemcpyAsync(col, J.col.p, size_t(J.nnz) * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    MAK_HIP(hipMemcpyAsync(val, J.val.p, size_t(J.nnz) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  });
+}
+
+mak_status mak_faces_copy(mak_ctx* ctx, int64_t* face_ptr, int32_t* face_j, int32_t* face_shift,
+                          double* face_area, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    if (!ctx->cells_valid) MAK_FAIL(MAK_EINVAL, "no cell pass to copy from");
+    if (!face_ptr || (ctx->nfaces > 0 && (!face_j || !face_shift || !face_area)))
+      MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    set_device(ctx);
+    copy_faces(ctx->ps, ctx->cp, ctx->face_ptr, face_ptr, face_j, face_shift, face_area,
+               static_cast<hipStream_t>(stream));
+  });
+}
+
+static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, double L, double tol,
+                             const double* psi0, double* psi, double* centroids, double* displacements,
+                             mak_solve_info* info, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  mak_solve_info si{};
+  mak_status status = guarded(ctx, [&] {
+    check_args(N, L);
+    if (!(tol > 0)) MAK_FAIL(MAK_EINVAL, "tol must be > 0");
+    if (!points || !psi || !centroids || !displacements) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    set_device(ctx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const mak_options& o = ctx->opt;
+    PointSet& ps = ctx->sps;
+    build_pointset(ps, points, psi0, N, L, o.grid_occupancy, st);
+    ctx->psi_s.ensure(size_t(N) * sizeof(double));
+    ctx->psi_t.ensure(size_t(N) * sizeof(double));
+    ctx->g.ensure(size_t(N) * sizeof(double));
+    ctx->pstep.ensure(size_t(N) * sizeof(double));
+    double* psi_s = ctx->psi_s.as<double>();
+    if (psi0)
+      gather_sorted(ps, psi0, psi_s, st);
+    else
+      MAK_HIP(hipMemsetAsync(psi_s, 0, size_t(N) * sizeof(double), st));
+    const double m = L * L * L / double(N);
+
+    set_psi_sorted(ps, psi_s, st);
+    ClipStats cs = run_cells(ps, ctx->scp, o.precision, true, st);
+    si.cell_passes = 1;
+    si.overflow_cells += cs.retried;
+    FlagStats fs = flag_stats(ps, ctx->scp, ctx->tmp, st);
+    if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
+    build_csr(ps, ctx->scp, ctx->sJ, false, st);
+    double err = 0, vmin = 0;
+    double gn = residual_stats(ctx->scp.vol.as<double>(), m, N, ctx->tmp, &err, &vmin, st);
+    const double eps0 = 0.5 * std::min(m, vmin);
+    if (o.verbose) fprintf(stderr, "[mak] N=%lld it=0 err=%.3e minV/m=%.3e\n", (long long)N, err, vmin / m);
+    for (int it = 0;; ++it) {
+      if (err <= tol) break;
+      if (it >= o.max_newton) MAK_FAIL(MAK_ENOCONV, "Newton iteration limit reached, err=" + std::to_string(err));
+      newton_residual(ctx->scp.vol.as<double>(), m, ctx->g.as<double>(), N, st);
+      const int cgi = pcg_solve(ctx->sJ, ctx->g.as<double>(), ctx->pstep.as<double>(), N, o.cg_rtol,
+                                o.max_cg, ctx->pw, st);
+      si.cg_iters_total += cgi;
+      double alpha = 1.0;
+      bool accepted = false;
+      for (int ls = 0; ls <= o.max_halvings; ++ls) {
+        axpy_into(ctx->psi_s.as<double>(), ctx->pstep.as<double>(), alpha, ctx->psi_t.as<double>(), N, st);
+        set_psi_sorted(ps, ctx->psi_t.as<double>(), st);
+        ClipStats ct = run_cells(ps, ctx->scp_trial, o.precision, true, st);
+        si.cell_passes += 1;
+        si.ls_trials += 1;
+        si.overflow_cells += ct.retried;
+        double e2 = 0, v2 = 0;
+        const double g2 = residual_stats(ctx->scp_trial.vol.as<double>(), m, N, ctx->tmp, &e2, &v2, st);
+        if (v2 >= eps0 && g2 <= (1.0 - 0.5 * alpha) * gn) {
+          swap_buf(ctx->psi_s, ctx->psi_t);
+          swap_pass(ctx->scp, ctx->scp_trial);
+          build_csr(ps, ctx->scp, ctx->sJ, false, st);
+          err = e2;
+          gn = g2;
+          vmin = v2;
+          accepted = true;
+          break;
+        }
+        alpha *= 0.5;
+      }
+      if (!accepted) {
+        set_psi_sorted(ps, ctx->psi_s.as<double>(), st);
+        MAK_FAIL(MAK_ENOCONV, "line search failed");
+      }
+      si.newton_iters += 1;
+      if (o.verbose)
+        fprintf(stderr, "[mak] it=%d err=%.3e alpha=%g cg=%d minV/m=%.3e\n", it + 1, err, alpha, cgi,
+                vmin / m);
+    }
+    si.final_err = err;
+    finalize_outputs(ps, ctx->psi_s.as<double>(), 0.0, ctx->scp.vol.as<double>(),
+                     ctx->scp.mom.as<double>(), psi, centroids, displacements, st);
+    MAK_HIP(hipStreamSynchronize(st));
+  });
+  si.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = si;
+  return status;
+}
+
+mak_status mak_solve(mak_ctx* ctx, const double* points, int64_t N, double L, double tol, double* psi,
+                     double* centroids, double* displacements, mak_solve_info* info, void* stream) {
+  return solve_impl(ctx, points, N, L, tol, nullptr, psi, centroids, displacements, info, stream);
+}
+
+mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double L, double tol,
+                          double* psi, double* centroids, double* displacements, mak_solve_info* info,
+                          void* stream) {
+  if (!psi) return MAK_EINVAL;
+  return solve_impl(ctx, points, N, L, tol, psi, psi, centroids, displacements, info, stream);
+}
+
+size_t mak_solve_memory_estimate(int64_t N, int32_t precision) {
+  (void)precision;
+  const int64_t fslot = N <= (int64_t(1) << 24) ? 32 : 20;
+  const int64_t per_site = 80 + 2 * (60 + fslot * int64_t(sizeof(FaceRec)) + 16) + 232 + 80;
+  return size_t(N) * size_t(per_site) + (size_t(64) << 20);
+}
+
+}  // extern "C"

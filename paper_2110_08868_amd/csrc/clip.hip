@@ -1,0 +1,795 @@
+// Laguerre cell pass: one wavefront per site clips a convex polytope by power
+// bisectors (Eq. laguerrecell on the torus) and integrates it (Eq. SDK
+// integrands: volume, first moment, face areas -> Hessian rows).
+//
+// Polytope representation (per wave):
+//   planes    LDS  (n, b): u . n <= b inside, u = q - x_i seed-local; planes
+//             0..5 are the box [-L/2, L/2]^3 of the site's own images.
+//   vertices  one per "triangle" (a, b, c) of plane indices, the dual of the
+//             polytope; a simple vertex is the intersection of three planes,
+//             stored counter-clockwise seen from outside.  Each lane holds TPL
+//             triangle slots in registers (slot = k * 64 + lane) with their
+//             coordinates; LDS keeps a staging copy for compaction.
+// Cutting by a new plane p:
+//   - every lane tests its vertices; a ballot gives the removed set
+//     (strictly outside by more than a tolerance eps: a plane that only
+//     touches the polytope makes no face);
+//   - the removed triangles mark their directed dual edges in an LDS bitmap;
+//     a directed edge x->y of a removed triangle whose reverse y->x is not
+//     marked lies on the boundary of the removed region and yields the new
+//     vertex (x, y, p) (three-plane intersection);
+//   - kept and new triangles are compacted through LDS by ballot prefix
+//     counts.
+// Candidates: the 27 grid cells around the site, then shells of 4x4x4-cell
+// blocks.  Blocks, cells and sites are pruned lane-parallel with a bound on
+// what a plane can cut from the ball (c, rho) around the polytope, using the
+// per-block / per-cell maximum weight; a shell is only visited while its
+// distance is below  R + sqrt(R^2 + 2 (psi_max - psi_i)),  R = |c| + rho
+// (a bisector at distance t >= that from the site lies beyond the ball).
+// Surviving sites of each batch of 64 are sorted by the distance of their
+// plane from c (wave bitonic sort) and clipped in that order.
+// Integrals: for every triangle T and each of its planes f, the next vertex
+// around face f is the other triangle holding planes f and pred_T(f)
+// (membership bitmasks in LDS); with v0 a fixed vertex of face f, the
+// tetrahedra (site, v0, T, next) give volume and first moment, their face-f
+// triangles (v0, T, next) the face areas.
+#include <cfloat>
+
+#include "engine.h"
+#include "gridkey.h"
+
+namespace mak {
+
+namespace {
+
+struct ClipArgs {
+  const double4* pts;
+  const int32_t* cell_start;
+  const double* cell_psimax;
+  const double* block_psimax;
+  const double* gmax;
+  int32_t Gn, Gb;
+  double L, h;
+  const int32_t* work;
+  int64_t nwork, per_xcd;
+  double* vol;
+  double* mom;
+  int32_t* cflags;
+  int32_t* nface;
+  FaceRec* faces;
+  int64_t* fbase;
+  FaceRec* ovf;
+  unsigned long long* ovf_used;     // faces placed in the overflow region
+  unsigned long long* retry_count;  // cells appended to `retry`
+  int32_t* retry;
+  int64_t ovf_cap;
+  int32_t fslot;
+  int32_t write_faces;
+  double area_min;
+  double eps_rel;
+};
+
+template <int TPL>
+struct ClipLDS {
+  static constexpr int PCAP = 64 * TPL;
+  static constexpr int TCAP = 64 * TPL;
+  double4 pl[PCAP];
+  int32_t pj[PCAP];
+  int32_t ps[PCAP];
+  uint32_t stri[TCAP];
+  double sx[TCAP], sy[TCAP], sz[TCAP];
+  uint32_t bits[PCAP * PCAP / 32];
+  uint32_t sbits[PCAP / 32];
+  int32_t cstart[64];
+  int32_t cpre[64];
+  int32_t cshift[64];
+};
+
+__device__ __forceinline__ uint32_t tri_pack(int a, int b, int c) {
+  return uint32_t(a) | (uint32_t(b) << 8) | (uint32_t(c) << 16);
+}
+__device__ __forceinline__ int tri_a(uint32_t t) { return int(t & 255u); }
+__device__ __forceinline__ int tri_b(uint32_t t) { return int((t >> 8) & 255u); }
+__device__ __forceinline__ int tri_c(uint32_t t) { return int((t >> 16) & 255u); }
+
+// Ascending bitonic sort of one 32-bit key per lane across the wave.
+__device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t other = uint32_t(__shfl_xor(int(key), j));
+      const bool take_min = ((lane & j) == 0) == ((lane & k) == 0);
+      key = take_min ? min(key, other) : max(key, other);
+    }
+  }
+  return key;
+}
+
+// Offset of the t-th block of the Chebyshev shell of radius r (r >= 1).
+__device__ __forceinline__ void shell_offset(int r, int t, int& ox, int& oy, int& oz) {
+  if (r == 0) {
+    ox = oy = oz = 0;
+    return;
+  }
+  const int S = 2 * r + 1, I = 2 * r - 1;
+  if (t < 2 * S * S) {
+    const int side = t / (S * S), rem = t % (S * S);
+    ox = side ? r : -r;
+    oy = rem / S - r;
+    oz = rem % S - r;
+    return;
+  }
+  t -= 2 * S * S;
+  if (t < 2 * S * I) {
+    const int side = t / (S * I), rem = t % (S * I);
+    oy = side ? r : -r;
+    ox = rem / S - (r - 1);
+    oz = rem % S - r;
+    return;
+  }
+  t -= 2 * S * I;
+  const int side = t / (I * I), rem = t % (I * I);
+  oz = side ? r : -r;
+  ox = rem / I - (r - 1);
+  oy = rem % I - (r - 1);
+}
+
+template <int TPL>
+__global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
+  constexpr int PCAP = ClipLDS<TPL>::PCAP;
+  constexpr int TCAP = ClipLDS<TPL>::TCAP;
+  constexpr int TW = TCAP / 32;   // words of one membership mask
+  constexpr int PW = PCAP / 32;   // words of one bitmap row
+  __shared__ ClipLDS<TPL> S;
+
+  const int lane = threadIdx.x;
+  const int64_t blk = blockIdx.x;
+  const int64_t item = (blk & 7) * A.per_xcd + (blk >> 3);
+  if (item >= A.nwork) return;
+  const int32_t p = A.work ? A.work[item] : int32_t(item);
+
+  const double4 me = A.pts[p];
+  const double xi = me.x, yi = me.y, zi = me.z, wi = me.w;
+  const double L = A.L, h = A.h;
+  const int Gn = A.Gn, Gb = A.Gb;
+  const int cx = cell_coord(xi, h, Gn), cy = cell_coord(yi, h, Gn), cz = cell_coord(zi, h, Gn);
+  const double gmax = *A.gmax;
+  const double mtol = 1e-12 * L * L;
+  const double eps_rel = A.eps_rel;
+
+  int32_t flags = 0;
+  bool dead = false;
+
+  // ---------------------------------------------------------------- box
+  if (lane < 6) {
+    const int ax = lane >> 1;
+    const double sg = (lane & 1) ? -1.0 : 1.0;
+    S.pl[lane] = make_double4(ax == 0 ? sg * L : 0.0, ax == 1 ? sg * L : 0.0,
+                              ax == 2 ? sg * L : 0.0, 0.5 * L * L);
+    S.pj[lane] = -1;
+    const int is = (lane & 1) ? -1 : 1;
+    S.ps[lane] = pack_shift(ax == 0 ? is : 0, ax == 1 ? is : 0, ax == 2 ? is : 0);
+  }
+  uint32_t tri[TPL];
+  double vx[TPL], vy[TPL], vz[TPL];
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    tri[k] = 0;
+    vx[k] = vy[k] = vz[k] = 0.0;
+  }
+  if (lane < 8) {
+    const int px = lane & 1, py = 2 + ((lane >> 1) & 1), pz = 4 + ((lane >> 2) & 1);
+    const int sx = (lane & 1) ? -1 : 1, sy = ((lane >> 1) & 1) ? -1 : 1, sz = ((lane >> 2) & 1) ? -1 : 1;
+    tri[0] = (sx * sy * sz > 0) ? tri_pack(px, py, pz) : tri_pack(px, pz, py);
+    vx[0] = sx * 0.5 * L;
+    vy[0] = sy * 0.5 * L;
+    vz[0] = sz * 0.5 * L;
+    S.stri[lane] = tri[0];
+    S.sx[lane] = vx[0];
+    S.sy[lane] = vy[0];
+    S.sz[lane] = vz[0];
+  }
+  int nT = 8, nP = 6;
+  float bcx = 0.f, bcy = 0.f, bcz = 0.f;
+  float brho = float(0.8660254037844386 * L) * 1.0001f;
+  for (int w = lane; w < PCAP * PW; w += 64) S.bits[w] = 0u;
+  if (lane < PW) S.sbits[lane] = 0u;
+  __syncthreads();
+
+  auto setbit = [&](int a, int b) {
+    const int idx = a * PCAP + b;
+    atomicOr(&S.bits[idx >> 5], 1u << (idx & 31));
+  };
+  auto getbit = [&](int a, int b) -> bool {
+    const int idx = a * PCAP + b;
+    return (S.bits[idx >> 5] >> (idx & 31)) & 1u;
+  };
+  auto clearword = [&](int a, int b) {
+    const int idx = a * PCAP + b;
+    S.bits[idx >> 5] = 0u;
+  };
+
+  auto update_ball = [&]() {
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (k * 64 + lane < nT) {
+        sx += float(vx[k]);
+        sy += float(vy[k]);
+        sz += float(vz[k]);
+      }
+    }
+    const float inv = 1.0f / float(nT);
+    sx = wave_sum_f(sx) * inv;
+    sy = wave_sum_f(sy) * inv;
+    sz = wave_sum_f(sz) * inv;
+    float r2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (k * 64 + lane < nT) {
+        const float ex = float(vx[k]) - sx, ey = float(vy[k]) - sy, ez = float(vz[k]) - sz;
+        r2 = fmaxf(r2, ex * ex + ey * ey + ez * ez);
+      }
+    }
+    r2 = wave_max_f(r2);
+    bcx = sx;
+    bcy = sy;
+    bcz = sz;
+    const float cn = sqrtf(sx * sx + sy * sy + sz * sz);
+    brho = sqrtf(r2) * 1.0001f + 1e-6f * (cn + float(h));
+  };
+
+  // Clip by u . d <= bb (plane tag jj / ss).
+  auto clip_one = [&](double dx, double dy, double dz, double bb, int32_t jj, int32_t ss) {
+    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+    const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
+    if (cd + double(brho) * dn <= bb - mtol) return;  // cannot reach the ball
+    const double rb = sqrt(double(bcx) * bcx + double(bcy) * bcy + double(bcz) * bcz) + double(brho);
+    const double eps = eps_rel * dn * rb;
+    uint64_t om[TPL];
+    int nout = 0;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      bool out = false;
+      if (k == 0 || nT > k * 64)
+        out = (k * 64 + lane < nT) && (vx[k] * dx + vy[k] * dy + vz[k] * dz - bb > eps);
+      om[k] = ballot(out);
+      nout += __popcll(om[k]);
+    }
+    if (nout == 0) return;
+    if (nout == nT) {
+      flags |= CF_EMPTY;
+      dead = true;
+      return;
+    }
+    if (nP >= PCAP) {
+      flags |= CF_CAPACITY;
+      dead = true;
+      return;
+    }
+    const int pn = nP;
+    if (lane == 0) {
+      S.pl[pn] = make_double4(dx, dy, dz, bb);
+      S.pj[pn] = jj;
+      S.ps[pn] = ss;
+    }
+    // 1. mark the directed dual edges of the removed triangles
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if ((om[k] >> lane) & 1ull) {
+        const int a = tri_a(tri[k]), b = tri_b(tri[k]), c = tri_c(tri[k]);
+        setbit(a, b);
+        setbit(b, c);
+        setbit(c, a);
+      }
+    }
+    __syncthreads();
+    // 2. boundary edges: reverse edge not removed
+    int bm[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      bm[k] = 0;
+      if ((om[k] >> lane) & 1ull) {
+        const int a = tri_a(tri[k]), b = tri_b(tri[k]), c = tri_c(tri[k]);
+        if (!getbit(b, a)) bm[k] |= 1;
+        if (!getbit(c, b)) bm[k] |= 2;
+        if (!getbit(a, c)) bm[k] |= 4;
+      }
+    }
+    __syncthreads();
+    // 3. clear the marks; each plane may start at most one boundary edge
+    bool nm = false;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if ((om[k] >> lane) & 1ull) {
+        const int a = tri_a(tri[k]), b = tri_b(tri[k]), c = tri_c(tri[k]);
+        clearword(a, b);
+        clearword(b, c);
+        clearword(c, a);
+        const int st[3] = {a, b, c};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (bm[k] & (1 << e)) {
+            const int x = st[e];
+            const uint32_t old = atomicOr(&S.sbits[x >> 5], 1u << (x & 31));
+            if ((old >> (x & 31)) & 1u) nm = true;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (lane < PW) S.sbits[lane] = 0u;
+    if (ballot(nm)) {
+      flags |= CF_NONMANIFOLD;
+      dead = true;
+      return;
+    }
+    const int nkept = nT - nout;
+    int mynew = 0;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) mynew += __popc(bm[k]);
+    const int nTn = nkept + wave_sum_i(mynew);
+    if (nTn > TCAP) {
+      flags |= CF_CAPACITY;
+      dead = true;
+      return;
+    }
+    // 4. compaction: kept triangles first (slot order), then the new ones
+    const double4 Pn = make_double4(dx, dy, dz, bb);
+    int krun = 0, nrun = 0;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const int slot = k * 64 + lane;
+      const bool kept = slot < nT && !((om[k] >> lane) & 1ull);
+      const uint64_t km = ballot(kept);
+      if (kept) {
+        const int dst = krun + lanes_below(km);
+        S.stri[dst] = tri[k];
+        S.sx[dst] = vx[k];
+        S.sy[dst] = vy[k];
+        S.sz[dst] = vz[k];
+      }
+      krun += __popcll(km);
+      const int nb = __popc(bm[k]);
+      const uint64_t b0 = ballot(nb & 1), b1 = ballot(nb & 2);
+      int pos = nkept + nrun + lanes_below(b0) + 2 * lanes_below(b1);
+      nrun += __popcll(b0) + 2 * __popcll(b1);
+      if (bm[k]) {
+        const int st[3] = {tri_a(tri[k]), tri_b(tri[k]), tri_c(tri[k])};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          if (bm[k] & (1 << e)) {
+            const int x = st[e], y = st[(e + 1) % 3];
+            const double4 P1 = S.pl[x], P2 = S.pl[y];
+            // intersection of planes x, y, pn (Cramer's rule)
+            const double c23x = P2.y * Pn.z - P2.z * Pn.y, c23y = P2.z * Pn.x - P2.x * Pn.z,
+                         c23z = P2.x * Pn.y - P2.y * Pn.x;
+            const double c31x = Pn.y * P1.z - Pn.z * P1.y, c31y = Pn.z * P1.x - Pn.x * P1.z,
+                         c31z = Pn.x * P1.y - Pn.y * P1.x;
+            const double c12x = P1.y * P2.z - P1.z * P2.y, c12y = P1.z * P2.x - P1.x * P2.z,
+                         c12z = P1.x * P2.y - P1.y * P2.x;
+            const double det = P1.x * c23x + P1.y * c23y + P1.z * c23z;
+            const double inv = 1.0 / det;
+            S.stri[pos] = tri_pack(x, y, pn);
+            S.sx[pos] = (P1.w * c23x + P2.w * c31x + Pn.w * c12x) * inv;
+            S.sy[pos] = (P1.w * c23y + P2.w * c31y + Pn.w * c12y) * inv;
+            S.sz[pos] = (P1.w * c23z + P2.w * c31z + Pn.w * c12z) * inv;
+            ++pos;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    nT = nTn;
+    nP = pn + 1;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      const int slot = k * 64 + lane;
+      if (slot < nT) {
+        tri[k] = S.stri[slot];
+        vx[k] = S.sx[slot];
+        vy[k] = S.sy[slot];
+        vz[k] = S.sz[slot];
+      } else {
+        tri[k] = 0;
+      }
+    }
+    update_ball();
+  };
+
+  // Could a site with weight <= wmax inside the seed-local box [lo, hi] cut
+  // the ball (c, rho)?  Needs c.d + rho|d| > |d|^2/2 + psi_i - psi_j.
+  auto box_may_cut = [&](double lx, double ly, double lz, double hx, double hy, double hz,
+                         double wmax) -> bool {
+    const double mx = lx > 0 ? lx : (hx < 0 ? -hx : 0.0);
+    const double my = ly > 0 ? ly : (hy < 0 ? -hy : 0.0);
+    const double mz = lz > 0 ? lz : (hz < 0 ? -hz : 0.0);
+    const double m = sqrt(mx * mx + my * my + mz * mz);
+    const double r = double(brho);
+    const double f = m >= r ? 0.5 * m * m - r * m : -0.5 * r * r;
+    const double cmax = fmax(double(bcx) * lx, double(bcx) * hx) + fmax(double(bcy) * ly, double(bcy) * hy) +
+                        fmax(double(bcz) * lz, double(bcz) * hz);
+    return f - cmax < wmax - wi + mtol;
+  };
+
+  // Scan the sites of a list of cells (one cell per lane where `act`).
+  auto process_list = [&](bool act, int32_t start, int32_t cnt, int32_t sh) {
+    const bool has = act && cnt > 0;
+    const uint64_t am = ballot(has);
+    const int ncl = __popcll(am);
+    if (ncl == 0) return;
+    const int c_ = has ? cnt : 0;
+    const int incl = wave_incl_scan_i(c_);
+    const int total = readlane_i(incl, 63);
+    if (has) {
+      const int idx = lanes_below(am);
+      S.cstart[idx] = start;
+      S.cpre[idx] = incl - c_;
+      S.cshift[idx] = sh;
+    }
+    __syncthreads();
+    for (int base = 0; base < total && !dead; base += 64) {
+      const int t = base + lane;
+      int lo = 0, hi = ncl - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.cpre[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      const int q = S.cstart[lo] + (t - S.cpre[lo]);
+      const int32_t shv = S.cshift[lo];
+      double dx = 0, dy = 0, dz = 0, bb = 0;
+      bool may = false, coinc = false;
+      uint32_t key = 0xffffffffu;
+      if (t < total && q != p) {
+        const double4 P = A.pts[q];
+        dx = P.x + unpack_shift(shv, 0) * L - xi;
+        dy = P.y + unpack_shift(shv, 1) * L - yi;
+        dz = P.z + unpack_shift(shv, 2) * L - zi;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 == 0.0) {
+          coinc = true;
+        } else {
+          bb = 0.5 * d2 + wi - P.w;
+          const double dn = sqrt(d2);
+          const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
+          may = cd + double(brho) * dn > bb - mtol;
+          if (may) key = (float_key(float((bb - cd) / dn)) & ~63u) | uint32_t(lane);
+        }
+      }
+      if (ballot(coinc)) flags |= CF_COINCIDENT;
+      const int ns = __popcll(ballot(may));
+      if (ns == 0) continue;
+      key = wave_sort_u32(key);
+      for (int r = 0; r < ns && !dead; ++r) {
+        const int src = int(readlane_u(key, r) & 63u);
+        clip_one(readlane_d(dx, src), readlane_d(dy, src), readlane_d(dz, src),
+                 readlane_d(bb, src), readlane_i(q, src), readlane_i(shv, src));
+      }
+    }
+    __syncthreads();
+  };
+
+  // ---------------------------------------------------------------- phase A
+  {
+    const bool act = lane < 27;
+    const int ux = cx + lane / 9 - 1, uy = cy + (lane / 3) % 3 - 1, uz = cz + lane % 3 - 1;
+    const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+    int32_t st = 0, cnt = 0;
+    if (act) {
+      const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
+      st = A.cell_start[g];
+      cnt = A.cell_start[g + 1] - st;
+    }
+    process_list(act, st, cnt, pack_shift(sx, sy, sz));
+  }
+
+  // ---------------------------------------------------------------- phase B
+  {
+    const int bx0 = cx >> 2, by0 = cy >> 2, bz0 = cz >> 2;
+    const double bh = BLOCK_SIDE * h;
+    double mb = fmin(fmin(xi - bx0 * bh, (bx0 + 1) * bh - xi),
+                     fmin(fmin(yi - by0 * bh, (by0 + 1) * bh - yi), fmin(zi - bz0 * bh, (bz0 + 1) * bh - zi)));
+    mb = fmax(mb, 0.0);
+    const int rb_max = 4 * Gb + 4;
+    for (int rb = 0; !dead; ++rb) {
+      if (rb >= 1) {
+        const double dlb = (rb - 1) * bh + mb - 1e-12 * L;
+        const double R = sqrt(double(bcx) * bcx + double(bcy) * bcy + double(bcz) * bcz) + double(brho);
+        const double Rs = R + sqrt(R * R + 2.0 * fmax(0.0, gmax - wi));
+        if (dlb >= Rs) break;
+        if (rb > rb_max) {
+          flags |= CF_CAPACITY;
+          dead = true;
+          break;
+        }
+      }
+      const int S1 = 2 * rb + 1, I1 = 2 * rb - 1;
+      const int count = rb == 0 ? 1 : S1 * S1 * S1 - I1 * I1 * I1;
+      for (int base = 0; base < count && !dead; base += 64) {
+        const int t = base + lane;
+        bool ok = false;
+        int ubx = 0, uby = 0, ubz = 0;
+        if (t < count) {
+          int ox, oy, oz;
+          shell_offset(rb, t, ox, oy, oz);
+          ubx = bx0 + ox;
+          uby = by0 + oy;
+          ubz = bz0 + oz;
+          const int wbx = ubx - floor_div(ubx, Gb) * Gb, wby = uby - floor_div(uby, Gb) * Gb,
+                    wbz = ubz - floor_div(ubz, Gb) * Gb;
+          const double lx = ubx * bh - xi - 1e-12 * L, ly = uby * bh - yi - 1e-12 * L,
+                       lz = ubz * bh - zi - 1e-12 * L;
+          const double hx = lx + bh + 2e-12 * L, hy = ly + bh + 2e-12 * L, hz = lz + bh + 2e-12 * L;
+          ok = box_may_cut(lx, ly, lz, hx, hy, hz, A.block_psimax[block_key(wbx, wby, wbz, Gb)]);
+        }
+        uint64_t bmask = ballot(ok);
+        while (bmask && !dead) {
+          const int l = __ffsll((unsigned long long)bmask) - 1;
+          bmask &= bmask - 1;
+          const int qbx = readlane_i(ubx, l), qby = readlane_i(uby, l), qbz = readlane_i(ubz, l);
+          const int ux = qbx * BLOCK_SIDE + (lane >> 4), uy = qby * BLOCK_SIDE + ((lane >> 2) & 3),
+                    uz = qbz * BLOCK_SIDE + (lane & 3);
+          const bool inA = abs(ux - cx) <= 1 && abs(uy - cy) <= 1 && abs(uz - cz) <= 1;
+          const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+          const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
+          const int32_t st = A.cell_start[g];
+          const int32_t cnt = A.cell_start[g + 1] - st;
+          bool act = !inA && cnt > 0;
+          if (act) {
+            const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
+                         lz = uz * h - zi - 1e-12 * L;
+            act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L,
+                              A.cell_psimax[g]);
+          }
+          process_list(act, st, cnt, pack_shift(sx, sy, sz));
+        }
+      }
+    }
+  }
+
+  if (dead) {
+    if (lane == 0) {
+      if (flags & (CF_CAPACITY | CF_NONMANIFOLD)) {
+        const unsigned long long r = atomicAdd(A.retry_count, 1ull);
+        A.retry[r] = p;
+      }
+      A.vol[p] = 0.0;
+      A.mom[3 * p] = A.mom[3 * p + 1] = A.mom[3 * p + 2] = 0.0;
+      A.nface[p] = 0;
+      A.cflags[p] = flags;
+    }
+    return;
+  }
+
+  // ---------------------------------------------------------------- integrals
+  // membership masks: bit t of mask f is set when triangle t contains plane f
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    const int slot = k * 64 + lane;
+    if (slot < nT) {
+      const uint32_t bit = 1u << (slot & 31);
+      const int w = slot >> 5;
+      atomicOr(&S.bits[tri_a(tri[k]) * TW + w], bit);
+      atomicOr(&S.bits[tri_b(tri[k]) * TW + w], bit);
+      atomicOr(&S.bits[tri_c(tri[k]) * TW + w], bit);
+    }
+  }
+  __syncthreads();
+  double v6 = 0, m0 = 0, m1 = 0, m2 = 0;
+  double ar[TPL][3];
+  bool broken = false;
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    ar[k][0] = ar[k][1] = ar[k][2] = 0.0;
+    const int slot = k * 64 + lane;
+    if (slot >= nT) continue;
+    const int fa[3] = {tri_a(tri[k]), tri_b(tri[k]), tri_c(tri[k])};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int f = fa[e], pr = fa[(e + 2) % 3];
+      int tw = -1;
+#pragma unroll
+      for (int w = 0; w < TW; ++w) {
+        uint32_t m = S.bits[f * TW + w] & S.bits[pr * TW + w];
+        if (w == (slot >> 5)) m &= ~(1u << (slot & 31));
+        if (m && tw < 0) tw = w * 32 + __ffs(int(m)) - 1;
+      }
+      if (tw < 0) {
+        broken = true;
+        continue;
+      }
+      const double tx = S.sx[tw], ty = S.sy[tw], tz = S.sz[tw];
+      const double4 P = S.pl[f];
+      const double nn = P.x * P.x + P.y * P.y + P.z * P.z;
+      // fan apex: the lowest-slot vertex of face f (on the plane, close to
+      // the face, so small faces keep their relative precision)
+      int t0 = 0;
+#pragma unroll
+      for (int w = TW - 1; w >= 0; --w) {
+        const uint32_t m = S.bits[f * TW + w];
+        if (m) t0 = w * 32 + __ffs(int(m)) - 1;
+      }
+      const double px = S.sx[t0], py = S.sy[t0], pz = S.sz[t0];
+      const double det = px * (vy[k] * tz - vz[k] * ty) + py * (vz[k] * tx - vx[k] * tz) +
+                         pz * (vx[k] * ty - vy[k] * tx);
+      v6 += det;
+      m0 += det * (px + vx[k] + tx);
+      m1 += det * (py + vy[k] + ty);
+      m2 += det * (pz + vz[k] + tz);
+      const double ax = vx[k] - px, ay = vy[k] - py, az = vz[k] - pz;
+      const double bx = tx - px, by = ty - py, bz = tz - pz;
+      const double crx = ay * bz - az * by, cry = az * bx - ax * bz, crz = ax * by - ay * bx;
+      ar[k][e] = 0.5 * (crx * P.x + cry * P.y + crz * P.z) / sqrt(nn);
+    }
+  }
+  v6 = wave_sum_d(v6);
+  m0 = wave_sum_d(m0);
+  m1 = wave_sum_d(m1);
+  m2 = wave_sum_d(m2);
+  if (ballot(broken)) flags |= CF_NONMANIFOLD;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    const int slot = k * 64 + lane;
+    if (slot < nT) {
+      S.sx[slot] = ar[k][0];
+      S.sy[slot] = ar[k][1];
+      S.sz[slot] = ar[k][2];
+    }
+  }
+  __syncthreads();
+  // per-face areas: one lane per plane (box planes 0..5 are not faces of J)
+  double Af[TPL];
+  int nf = 0;
+#pragma unroll
+  for (int c = 0; c < TPL; ++c) {
+    const int f = 6 + c * 64 + lane;
+    double a = 0.0;
+    if (f < nP) {
+#pragma unroll
+      for (int w = 0; w < TW; ++w) {
+        uint32_t m = S.bits[f * TW + w];
+        while (m) {
+          const int t = w * 32 + __ffs(int(m)) - 1;
+          m &= m - 1;
+          const uint32_t tr = S.stri[t];
+          a += tri_a(tr) == f ? S.sx[t] : (tri_b(tr) == f ? S.sy[t] : S.sz[t]);
+        }
+      }
+    }
+    Af[c] = (f < nP && a > A.area_min) ? a : 0.0;
+    nf += __popcll(ballot(Af[c] > 0.0));
+  }
+  if (A.write_faces) {
+    FaceRec* dst = A.faces + int64_t(p) * A.fslot;
+    if (nf > A.fslot) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(A.ovf_used, (unsigned long long)nf);
+      base = readlane_u64(base, 0);
+      if (int64_t(base) + nf > A.ovf_cap) {
+        flags |= CF_CAPACITY;
+        dst = nullptr;
+      } else {
+        dst = A.ovf + base;
+        if (lane == 0) A.fbase[p] = int64_t(base);
+      }
+    }
+    int run = 0;
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) {
+      const int f = 6 + c * 64 + lane;
+      const bool rep = Af[c] > 0.0;
+      const uint64_t rm = ballot(rep);
+      if (rep && dst) {
+        const double4 P = S.pl[f];
+        FaceRec fr;
+        fr.j = S.pj[f];
+        fr.shift = S.ps[f];
+        fr.area = Af[c];
+        fr.dist = sqrt(P.x * P.x + P.y * P.y + P.z * P.z);
+        dst[run + lanes_below(rm)] = fr;
+      }
+      run += __popcll(rm);
+    }
+  }
+  if (lane == 0) {
+    A.vol[p] = v6 / 6.0;
+    A.mom[3 * p] = m0 / 24.0;
+    A.mom[3 * p + 1] = m1 / 24.0;
+    A.mom[3 * p + 2] = m2 / 24.0;
+    A.nface[p] = nf;
+    A.cflags[p] = flags;
+  }
+}
+
+}  // namespace
+
+ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st) {
+  (void)precision;
+  const int64_t N = ps.N;
+  out.fslot = N <= (int64_t(1) << 24) ? 32 : 20;
+  out.vol.ensure(size_t(N) * sizeof(double));
+  out.mom.ensure(size_t(N) * 3 * sizeof(double));
+  out.cflags.ensure(size_t(N) * sizeof(int32_t));
+  out.nface.ensure(size_t(N) * sizeof(int32_t));
+  out.retry.ensure(size_t(N) * 2 * sizeof(int32_t));
+  out.counters.ensure(16 * sizeof(unsigned long long));
+  if (faces) {
+    out.faces.ensure(size_t(N) * out.fslot * sizeof(FaceRec));
+    out.fbase.ensure(size_t(N) * sizeof(int64_t));
+    if (out.ovf_cap < 4096 + N / 8) out.ovf_cap = 4096 + N / 8;
+    out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
+  }
+  ClipStats cs;
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    MAK_HIP(hipMemsetAsync(out.counters.p, 0, 16 * sizeof(unsigned long long), st));
+    ClipArgs a{};
+    a.pts = ps.pts.as<double4>();
+    a.cell_start = ps.cell_start.as<int32_t>();
+    a.cell_psimax = ps.cell_psimax.as<double>();
+    a.block_psimax = ps.block_psimax.as<double>();
+    a.gmax = ps.scal.as<double>();
+    a.Gn = ps.g.Gn;
+    a.Gb = ps.g.Gb;
+    a.L = ps.g.L;
+    a.h = ps.g.h;
+    a.work = nullptr;
+    a.nwork = N;
+    a.per_xcd = ceil_div(N, 8);
+    a.vol = out.vol.as<double>();
+    a.mom = out.mom.as<double>();
+    a.cflags = out.cflags.as<int32_t>();
+    a.nface = out.nface.as<int32_t>();
+    a.faces = faces ? out.faces.as<FaceRec>() : nullptr;
+    a.fbase = faces ? out.fbase.as<int64_t>() : nullptr;
+    a.ovf = faces ? out.ovf.as<FaceRec>() : nullptr;
+    a.ovf_used = out.counters.as<unsigned long long>();
+    a.retry_count = out.counters.as<unsigned long long>() + 1;
+    a.retry = out.retry.as<int32_t>();
+    a.ovf_cap = faces ? out.ovf_cap : 0;
+    a.fslot = out.fslot;
+    a.write_faces = faces ? 1 : 0;
+    const double spacing = ps.g.L / std::cbrt(double(N));
+    a.area_min = 1e-12 * spacing * spacing;
+    a.eps_rel = 1e-13;
+    hipLaunchKernelGGL(k_clip<2>, dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
+    MAK_HIP(hipGetLastError());
+    unsigned long long hc[4];
+    MAK_HIP(hipMemcpyAsync(hc, out.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+    MAK_HIP(hipStreamSynchronize(st));
+    if (faces && int64_t(hc[0]) > out.ovf_cap) {
+      out.ovf_cap = int64_t(hc[0]) * 2 + 4096;
+      out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
+      continue;
+    }
+    cs.retried = int64_t(hc[1]);
+    if (hc[1] > 0) {
+      // Large-capacity kernel with a wider tie tolerance on the listed cells.
+      a.work = out.retry.as<int32_t>();
+      a.nwork = int64_t(hc[1]);
+      a.per_xcd = ceil_div(a.nwork, 8);
+      a.retry_count = out.counters.as<unsigned long long>() + 2;
+      a.retry = out.retry.as<int32_t>() + a.nwork;  // failures land after the list
+      a.eps_rel = 1e-11;
+      hipLaunchKernelGGL(k_clip<4>, dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
+      MAK_HIP(hipGetLastError());
+      MAK_HIP(hipMemcpyAsync(hc, out.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+      MAK_HIP(hipStreamSynchronize(st));
+      if (faces && int64_t(hc[0]) > out.ovf_cap) {
+        out.ovf_cap = int64_t(hc[0]) * 2 + 4096;
+        out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
+        continue;
+      }
+      if (hc[2] > 0) {
+        cs.overflow = int64_t(hc[2]);
+        MAK_FAIL(MAK_EOVERFLOW, std::to_string(hc[2]) + " cells exceeded the polytope capacity");
+      }
+    }
+    return cs;
+  }
+  MAK_FAIL(MAK_ENOMEM, "face overflow buffer could not be sized");
+}
+
+}  // namespace mak

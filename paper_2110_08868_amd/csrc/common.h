@@ -1,0 +1,119 @@
+// Shared definitions of the HIP implementation (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/mak.h"
+
+namespace mak {
+
+constexpr int WAVE = 64;
+
+// Error raised inside the host driver; converted to a status at the ABI.
+struct Error {
+  mak_status status;
+  std::string msg;
+};
+
+#define MAK_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::mak::Error{MAK_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define MAK_FAIL(code, text) throw ::mak::Error{code, text}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- device side
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` below the calling lane.
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t readlane_u(uint32_t v, int l) {
+  return uint32_t(__builtin_amdgcn_readlane(int(v), l));
+}
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(uint32_t(b)), l);
+  const int hi = __builtin_amdgcn_readlane(int(uint32_t(uint64_t(b) >> 32)), l);
+  return __longlong_as_double(int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)));
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
+  const uint32_t lo = readlane_u(uint32_t(v), l);
+  const uint32_t hi = readlane_u(uint32_t(v >> 32), l);
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Butterfly reductions over the 64 lanes (fixed order: deterministic).
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+// Inclusive prefix sum over lanes.
+__device__ __forceinline__ int wave_incl_scan_i(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+// Order-preserving map of a float to uint32 (for sort keys).
+__device__ __forceinline__ uint32_t float_key(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ int floor_div(int a, int b) {
+  const int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// Packed periodic image shift: three signed 10-bit fields.
+__host__ __device__ __forceinline__ int32_t pack_shift(int sx, int sy, int sz) {
+  return int32_t((uint32_t(sx & 1023) << 20) | (uint32_t(sy & 1023) << 10) | uint32_t(sz & 1023));
+}
+__host__ __device__ __forceinline__ int unpack_shift(int32_t p, int axis) {
+  const int v = int((uint32_t(p) >> (20 - 10 * axis)) & 1023u);
+  return v >= 512 ? v - 1024 : v;
+}
+
+}  // namespace mak

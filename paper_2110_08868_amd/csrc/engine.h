@@ -1,0 +1,163 @@
+// Host-side engine: device workspace of one point set and the launchers of the
+// pass kernels (grid build, clip, CSR assembly, PCG).
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+
+namespace mak {
+
+// A growable device buffer owned by the engine.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  void ensure(size_t bytes) {
+    if (bytes <= cap && p) return;
+    release();
+    size_t want = bytes < 256 ? 256 : bytes;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      MAK_FAIL(MAK_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    cap = want;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// One face of a cell as written by the clip kernel.
+struct FaceRec {
+  int32_t j;      // other site, sorted index
+  int32_t shift;  // packed periodic image of site j
+  double area;
+  double dist;    // |x_j + shift L - x_i|
+};
+
+// Per-cell flag bits written by the clip kernel.
+enum : int32_t {
+  CF_EMPTY = 1,
+  CF_COINCIDENT = 2,
+  CF_CAPACITY = 4,     // polytope capacity exceeded: re-run with the large kernel
+  CF_NONMANIFOLD = 8,  // inconsistent cut (rounding): re-run in float64 / reported
+  CF_NEARDEG = 16,     // ill-conditioned vertex (mixed precision: re-run in float64)
+};
+
+constexpr int BLOCK_SIDE = 4;  // neighbour-grid cells per block side
+
+struct GridDesc {
+  int32_t Gn = 0;   // cells per axis (multiple of BLOCK_SIDE)
+  int32_t Gb = 0;   // blocks per axis
+  double h = 0;     // cell side
+  double L = 0;
+  int64_t G() const { return int64_t(Gn) * Gn * Gn; }
+  int64_t GB() const { return int64_t(Gb) * Gb * Gb; }
+};
+
+GridDesc make_grid(int64_t N, double L, double occupancy);
+
+// Device state of one point set (sorted by neighbour-grid cell).
+struct PointSet {
+  int64_t N = 0;
+  GridDesc g;
+  DevBuf pts;          // double4 [N]: x, y, z (wrapped), psi      (sorted order)
+  DevBuf perm;         // int32 [N]: sorted -> original index
+  DevBuf cell_start;   // int32 [G + 1]
+  DevBuf cell_psimax;  // double [G]
+  DevBuf block_psimax; // double [GB]
+  DevBuf scal;         // double [8]: [0] global psi max, [1] global psi min
+  DevBuf key, rank, count, status, tmp;  // build temporaries
+};
+
+// Output of one cell pass (sorted order).
+struct CellPass {
+  DevBuf vol;        // double [N]
+  DevBuf mom;        // double [3N] first moment, seed-local
+  DevBuf cflags;     // int32 [N]
+  DevBuf nface;      // int32 [N]
+  DevBuf faces;      // FaceRec [N * fslot]
+  DevBuf fbase;      // int64 [N]: start in `ovf` of a cell with more than fslot faces
+  DevBuf ovf;        // FaceRec [ovf_cap]
+  DevBuf counters;   // uint64 [16]: [0] overflow faces used, [1] retries, [2] failures
+  DevBuf retry;      // int32 [N]
+  DevBuf scan_tmp;
+  int32_t fslot = 0;
+  int64_t ovf_cap = 0;
+};
+
+struct Csr {
+  int64_t n = 0, nnz = 0;
+  DevBuf row_ptr;  // int64 [n + 1]
+  DevBuf col;      // int32 [nnz]
+  DevBuf val;      // double [nnz]
+  DevBuf rowcnt;   // int64 [n]
+};
+
+// --- grid.hip
+// Wrap, validate and sort `points` (original order, device) into `ps`; psi may
+// be NULL (zeros).  Returns MAK_OK / EINVAL through exceptions.
+void build_pointset(PointSet& ps, const double* points, const double* psi, int64_t N, double L,
+                    double occupancy, hipStream_t st);
+// psi (sorted order, device) -> pts[].w and the per-cell / per-block / global
+// maxima used by the search bounds.
+void set_psi_sorted(PointSet& ps, const double* psi_sorted, hipStream_t st);
+void update_psi_bounds(PointSet& ps, hipStream_t st);
+
+// --- clip.hip
+struct ClipStats {
+  int64_t retried = 0, overflow = 0, nonmanifold = 0, empty = 0, coincident = 0, neardeg = 0;
+};
+// Full cell pass at the psi stored in ps.pts[].w.  precision: MAK_FP64 or
+// MAK_MIXED.  Throws on capacity overflow past the large kernel.
+ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st);
+
+// --- csr.hip
+// Assemble J (sorted index space, or original space when perm != NULL).
+void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hipStream_t st);
+// Faces (original space) for mak_faces_copy; returns the face count.
+int64_t count_faces(const PointSet& ps, CellPass& cp, Csr& J, DevBuf& face_ptr, hipStream_t st);
+void copy_faces(const PointSet& ps, CellPass& cp, const DevBuf& face_ptr, int64_t* out_ptr,
+                int32_t* fj, int32_t* fshift, double* farea, hipStream_t st);
+
+// --- pcg.hip / reductions
+double dev_reduce_max(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
+double dev_reduce_min(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
+double dev_reduce_sum(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
+void dev_max_to(const double* x, int64_t n, double* out, DevBuf& tmp, hipStream_t st);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
+
+struct PcgWork {
+  DevBuf r, z, p, q, dinv, part, scal;
+};
+// Solve J x = b (b mean-free) with Jacobi-preconditioned CG; x is overwritten
+// (start from 0).  Returns the iteration count.
+int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
+              PcgWork& w, hipStream_t st);
+
+// Elementwise helpers for the Newton driver.
+void newton_residual(const double* vol, double m, double* g, int64_t n, hipStream_t st);
+void axpy_into(const double* psi, const double* p, double alpha, double* out, int64_t n,
+               hipStream_t st);
+double residual_stats(const double* vol, double m, int64_t n, DevBuf& tmp, double* max_rel,
+                      double* min_vol, hipStream_t st);
+void finalize_outputs(const PointSet& ps, const double* psi_sorted, double psi_mean,
+                      const double* vol, const double* mom, double* psi_out, double* cent_out,
+                      double* disp_out, hipStream_t st);
+void scatter_cells_outputs(const PointSet& ps, const double* vol_s, const double* mom_s,
+                           double* vol_out, double* cent_out, hipStream_t st);
+void gather_sorted(const PointSet& ps, const double* orig, double* sorted, hipStream_t st);
+
+}  // namespace mak

@@ -1,0 +1,171 @@
+// Neighbour grid: wrap + validate + counting sort of the sites into
+// block-major cell order, and the weight bounds used by the search.
+#include <cfloat>
+#include <cmath>
+
+#include "engine.h"
+#include "gridkey.h"
+
+namespace mak {
+
+GridDesc make_grid(int64_t N, double L, double occupancy) {
+  GridDesc g;
+  if (occupancy <= 0) occupancy = 2.5;
+  const double side = std::cbrt(double(N) / occupancy) / BLOCK_SIDE;
+  int64_t gb = int64_t(std::llround(side));
+  if (gb < 1) gb = 1;
+  if (gb > 1024) gb = 1024;
+  g.Gb = int32_t(gb);
+  g.Gn = int32_t(gb * BLOCK_SIDE);
+  g.L = L;
+  g.h = L / double(g.Gn);
+  return g;
+}
+
+namespace {
+
+// Wrap into [0, L), check finiteness, compute the cell key, count the cell.
+__global__ void k_stage(const double* __restrict__ points, const double* __restrict__ psi,
+                        int64_t n, double L, double h, int Gn, int Gb, double4* __restrict__ xw,
+                        int32_t* __restrict__ key, int32_t* __restrict__ rank,
+                        int32_t* __restrict__ count, int32_t* __restrict__ status) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double c[3];
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double v = points[3 * i + a];
+    ok = ok && isfinite(v);
+    v = fmod(v, L);
+    if (v < 0) v += L;
+    if (!(v < L) || !(v >= 0)) v = 0.0;
+    c[a] = v;
+  }
+  const double w = psi ? psi[i] : 0.0;
+  ok = ok && isfinite(w);
+  if (!ok) {
+    atomicOr(status, 1);
+    c[0] = c[1] = c[2] = 0.0;
+  }
+  xw[i] = make_double4(c[0], c[1], c[2], ok ? w : 0.0);
+  const int cx = cell_coord(c[0], h, Gn), cy = cell_coord(c[1], h, Gn), cz = cell_coord(c[2], h, Gn);
+  const int32_t k = int32_t(cell_key(cx, cy, cz, Gb));
+  key[i] = k;
+  rank[i] = atomicAdd(&count[k], 1);
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
+                          const int32_t* __restrict__ start, int32_t* __restrict__ perm, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  perm[start[key[i]] + rank[i]] = int32_t(i);
+}
+
+// Order the sites of each cell by original index (the atomic ranks above are
+// not reproducible; this makes the sorted order deterministic).
+__global__ void k_cell_sort(const int32_t* __restrict__ start, int32_t* __restrict__ perm, int64_t G) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const int32_t b = start[g], e = start[g + 1];
+  for (int32_t k = b + 1; k < e; ++k) {
+    const int32_t v = perm[k];
+    int32_t m = k - 1;
+    while (m >= b && perm[m] > v) {
+      perm[m + 1] = perm[m];
+      --m;
+    }
+    perm[m + 1] = v;
+  }
+}
+
+__global__ void k_gather(const double4* __restrict__ xw, const int32_t* __restrict__ perm,
+                         double4* __restrict__ pts, int64_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  pts[p] = xw[perm[p]];
+}
+
+__global__ void k_set_psi(const double* __restrict__ psi_sorted, double4* __restrict__ pts, int64_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  pts[p].w = psi_sorted[p];
+}
+
+__global__ void k_cell_max(const int32_t* __restrict__ start, const double4* __restrict__ pts,
+                           double* __restrict__ cmax, int64_t G) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  double m = -DBL_MAX;
+  for (int32_t k = start[g]; k < start[g + 1]; ++k) m = fmax(m, pts[k].w);
+  cmax[g] = m;
+}
+
+// One wave per block of 64 cells.
+__global__ __launch_bounds__(64) void k_block_max(const double* __restrict__ cmax,
+                                                  double* __restrict__ bmax, int64_t GB) {
+  const int64_t b = blockIdx.x;
+  if (b >= GB) return;
+  const double v = wave_max_d(cmax[b * 64 + threadIdx.x]);
+  if (threadIdx.x == 0) bmax[b] = v;
+}
+
+}  // namespace
+
+void build_pointset(PointSet& ps, const double* points, const double* psi, int64_t N, double L,
+                    double occupancy, hipStream_t st) {
+  ps.N = N;
+  ps.g = make_grid(N, L, occupancy);
+  const int64_t G = ps.g.G();
+  ps.pts.ensure(size_t(N) * sizeof(double4));
+  ps.perm.ensure(size_t(N) * sizeof(int32_t));
+  ps.cell_start.ensure(size_t(G + 1) * sizeof(int32_t));
+  ps.cell_psimax.ensure(size_t(G) * sizeof(double));
+  ps.block_psimax.ensure(size_t(ps.g.GB()) * sizeof(double));
+  ps.scal.ensure(8 * sizeof(double));
+  ps.key.ensure(size_t(N) * sizeof(int32_t));
+  ps.rank.ensure(size_t(N) * sizeof(int32_t));
+  ps.count.ensure(size_t(G) * sizeof(int32_t));
+  ps.status.ensure(size_t(N) * sizeof(double4) + 64);  // xw staging + status word
+  double4* xw = ps.status.as<double4>();
+  int32_t* status = reinterpret_cast<int32_t*>(ps.status.as<char>() + size_t(N) * sizeof(double4));
+
+  MAK_HIP(hipMemsetAsync(ps.count.p, 0, size_t(G) * sizeof(int32_t), st));
+  MAK_HIP(hipMemsetAsync(status, 0, sizeof(int32_t), st));
+  const unsigned nb = unsigned(ceil_div(N, 256));
+  hipLaunchKernelGGL(k_stage, dim3(nb), dim3(256), 0, st, points, psi, N, L, ps.g.h, ps.g.Gn,
+                     ps.g.Gb, xw, ps.key.as<int32_t>(), ps.rank.as<int32_t>(),
+                     ps.count.as<int32_t>(), status);
+  exclusive_scan_i32(ps.count.as<int32_t>(), ps.cell_start.as<int32_t>(), G, ps.tmp, st);
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, ps.key.as<int32_t>(),
+                     ps.rank.as<int32_t>(), ps.cell_start.as<int32_t>(), ps.perm.as<int32_t>(), N);
+  hipLaunchKernelGGL(k_cell_sort, dim3(unsigned(ceil_div(G, 256))), dim3(256), 0, st,
+                     ps.cell_start.as<int32_t>(), ps.perm.as<int32_t>(), G);
+  hipLaunchKernelGGL(k_gather, dim3(nb), dim3(256), 0, st, xw, ps.perm.as<int32_t>(),
+                     ps.pts.as<double4>(), N);
+  MAK_HIP(hipGetLastError());
+  int32_t hs = 0;
+  MAK_HIP(hipMemcpyAsync(&hs, status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  if (hs) MAK_FAIL(MAK_EINVAL, "non-finite coordinate or weight");
+  update_psi_bounds(ps, st);
+}
+
+void set_psi_sorted(PointSet& ps, const double* psi_sorted, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_psi, dim3(unsigned(ceil_div(ps.N, 256))), dim3(256), 0, st, psi_sorted,
+                     ps.pts.as<double4>(), ps.N);
+  MAK_HIP(hipGetLastError());
+  update_psi_bounds(ps, st);
+}
+
+void update_psi_bounds(PointSet& ps, hipStream_t st) {
+  const int64_t G = ps.g.G(), GB = ps.g.GB();
+  hipLaunchKernelGGL(k_cell_max, dim3(unsigned(ceil_div(G, 256))), dim3(256), 0, st,
+                     ps.cell_start.as<int32_t>(), ps.pts.as<double4>(), ps.cell_psimax.as<double>(), G);
+  hipLaunchKernelGGL(k_block_max, dim3(unsigned(GB)), dim3(64), 0, st, ps.cell_psimax.as<double>(),
+                     ps.block_psimax.as<double>(), GB);
+  MAK_HIP(hipGetLastError());
+  dev_max_to(ps.block_psimax.as<double>(), GB, ps.scal.as<double>(), ps.tmp, st);
+}
+
+}  // namespace mak

@@ -1,0 +1,397 @@
+// Jacobi-preconditioned conjugate gradients for the Newton system J p = g
+// (J = dV/dpsi, a graph Laplacian: positive semi-definite with the constants
+// as null space; g has zero mean, so CG stays in the range of J), plus the
+// elementwise kernels of the Newton driver.  All reductions use a fixed grid
+// and a fixed tree, so results are reproducible run to run.
+#include <cfloat>
+
+#include "engine.h"
+
+namespace mak {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAXB = 1024;  // blocks of the grid-stride vector kernels
+
+// scalar slots (device doubles)
+enum { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6 };
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum_d(v);
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < TPB / WAVE; ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+unsigned vec_blocks(int64_t n) {
+  const int64_t b = ceil_div(n, TPB);
+  return unsigned(b < MAXB ? (b < 1 ? 1 : b) : MAXB);
+}
+
+// q = J p (16 lanes per row) and per-block partial of p . q
+__global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ p, double* __restrict__ q,
+                                                  double* __restrict__ part, int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  const int sub = threadIdx.x & 15;
+  double acc = 0.0;
+  for (int64_t row = int64_t(blockIdx.x) * (TPB / 16) + (threadIdx.x >> 4); row < n;
+       row += int64_t(gridDim.x) * (TPB / 16)) {
+    const int64_t b = rp[row], e = rp[row + 1];
+    double s = 0.0;
+    for (int64_t k = b + sub; k < e; k += 16) s += val[k] * p[col[k]];
+    s += __shfl_xor(s, 8);
+    s += __shfl_xor(s, 4);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 1);
+    if (sub == 0) {
+      q[row] = s;
+      acc += s * p[row];
+    }
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// sum of part[0..np) (columns `ncol` interleaved) into scal[dst + c]
+__global__ __launch_bounds__(TPB) void k_final(const double* __restrict__ part, int np, int ncol,
+                                               double* __restrict__ scal, int dst0, int dst1) {
+  __shared__ double sh[TPB / WAVE];
+  for (int c = 0; c < ncol; ++c) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < np; i += TPB) v += part[i * ncol + c];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) scal[c == 0 ? dst0 : dst1] = v;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_update(double* __restrict__ x, double* __restrict__ r,
+                                                double* __restrict__ z, const double* __restrict__ p,
+                                                const double* __restrict__ q,
+                                                const double* __restrict__ dinv,
+                                                const double* __restrict__ scal, int rz_cur,
+                                                double* __restrict__ part, int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  const double alpha = scal[rz_cur] / scal[S_PQ];
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    const double zi = dinv[i] * ri;
+    z[i] = zi;
+    arz += ri * zi;
+    arr += ri * ri;
+  }
+  arz = block_sum(arz, sh);
+  arr = block_sum(arr, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = arz;
+    part[2 * blockIdx.x + 1] = arr;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_pupdate(double* __restrict__ p, const double* __restrict__ z,
+                                                 const double* __restrict__ scal, int rz_new, int rz_old,
+                                                 int64_t n) {
+  const double beta = scal[rz_new] / scal[rz_old];
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
+    p[i] = z[i] + beta * p[i];
+}
+
+__global__ void k_diag_inv(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                           const double* __restrict__ val, double* __restrict__ dinv, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double d = 0.0;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+    if (col[k] == i) d = val[k];
+  dinv[i] = d > 0.0 ? 1.0 / d : 1.0;
+}
+
+__global__ __launch_bounds__(TPB) void k_sum_part(const double* __restrict__ x, double* __restrict__ part,
+                                                  int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  double a = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
+    a += x[i];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+// r = b - mean; x = 0; z = dinv r; p = z; partials of r.z and r.r
+__global__ __launch_bounds__(TPB) void k_init(const double* __restrict__ b, const double* __restrict__ scal,
+                                              double* __restrict__ x, double* __restrict__ r,
+                                              double* __restrict__ z, double* __restrict__ p,
+                                              const double* __restrict__ dinv, double* __restrict__ part,
+                                              int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  const double mean = scal[S_MEAN] / double(n);
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+    const double ri = b[i] - mean;
+    r[i] = ri;
+    x[i] = 0.0;
+    const double zi = dinv[i] * ri;
+    z[i] = zi;
+    p[i] = zi;
+    arz += ri * zi;
+    arr += ri * ri;
+  }
+  arz = block_sum(arz, sh);
+  arr = block_sum(arr, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = arz;
+    part[2 * blockIdx.x + 1] = arr;
+  }
+}
+
+__global__ void k_sub_mean(double* __restrict__ x, const double* __restrict__ scal, int slot, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] -= scal[slot] / double(n);
+}
+
+}  // namespace
+
+int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
+              PcgWork& w, hipStream_t st) {
+  w.r.ensure(size_t(n) * sizeof(double));
+  w.z.ensure(size_t(n) * sizeof(double));
+  w.p.ensure(size_t(n) * sizeof(double));
+  w.q.ensure(size_t(n) * sizeof(double));
+  w.dinv.ensure(size_t(n) * sizeof(double));
+  w.part.ensure(size_t(2 * MAXB + 16) * sizeof(double));
+  w.scal.ensure(16 * sizeof(double));
+  double* r = w.r.as<double>();
+  double* z = w.z.as<double>();
+  double* p = w.p.as<double>();
+  double* q = w.q.as<double>();
+  double* dinv = w.dinv.as<double>();
+  double* part = w.part.as<double>();
+  double* scal = w.scal.as<double>();
+  const unsigned nb = vec_blocks(n);
+  const unsigned nbe = unsigned(ceil_div(n, 256));
+  const unsigned nbs = unsigned(std::min<int64_t>(ceil_div(n, TPB / 16), MAXB));
+
+  hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
+                     J.col.as<int32_t>(), J.val.as<double>(), dinv, n);
+  hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, b, part, n);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_MEAN), 0);
+  hipLaunchKernelGGL(k_init, dim3(nb), dim3(TPB), 0, st, b, scal, x, r, z, p, dinv, part, n);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_RZ0), int(S_BB));
+  MAK_HIP(hipGetLastError());
+  double hb[8];
+  MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  const double bb = hb[S_BB];
+  if (!(bb > 0.0)) return 0;
+  const double stop = rtol * rtol * bb;
+  int it = 0;
+  for (; it < max_iter; ++it) {
+    const int cur = (it & 1) ? S_RZ1 : S_RZ0, nxt = (it & 1) ? S_RZ0 : S_RZ1;
+    hipLaunchKernelGGL(k_spmv_dot, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
+                       J.col.as<int32_t>(), J.val.as<double>(), p, q, part, n);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nbs), 1, scal, int(S_PQ), 0);
+    hipLaunchKernelGGL(k_update, dim3(nb), dim3(TPB), 0, st, x, r, z, p, q, dinv, scal, cur, part, n);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, nxt, int(S_RR));
+    if ((it & 7) == 7 || it + 1 == max_iter) {
+      double rr = 0;
+      MAK_HIP(hipMemcpyAsync(&rr, scal + S_RR, sizeof(double), hipMemcpyDeviceToHost, st));
+      MAK_HIP(hipStreamSynchronize(st));
+      if (rr <= stop) {
+        ++it;
+        break;
+      }
+    }
+    hipLaunchKernelGGL(k_pupdate, dim3(nb), dim3(TPB), 0, st, p, z, scal, nxt, cur, n);
+  }
+  MAK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, x, part, n);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_TMP), 0);
+  hipLaunchKernelGGL(k_sub_mean, dim3(nbe), dim3(256), 0, st, x, scal, int(S_TMP), n);
+  MAK_HIP(hipGetLastError());
+  return it;
+}
+
+// ---------------------------------------------------------------- Newton helpers
+namespace {
+
+__global__ void k_axpy_into(const double* __restrict__ a, const double* __restrict__ b, double alpha,
+                            double* __restrict__ out, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + alpha * b[i];
+}
+
+__global__ void k_residual(const double* __restrict__ vol, double m, double* __restrict__ g, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) g[i] = m - vol[i];
+}
+
+// partials: max |m - V|, min V, sum (m - V)^2
+__global__ __launch_bounds__(TPB) void k_res_stats(const double* __restrict__ vol, double m,
+                                                   double* __restrict__ part, int64_t n) {
+  __shared__ double sh[TPB];
+  double amax = 0.0, vmin = DBL_MAX, ss = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+    const double g = m - vol[i];
+    amax = fmax(amax, fabs(g));
+    vmin = fmin(vmin, vol[i]);
+    ss += g * g;
+  }
+  amax = wave_max_d(amax);
+  vmin = -wave_max_d(-vmin);
+  ss = wave_sum_d(ss);
+  const int w = threadIdx.x / WAVE;
+  if (lane_id() == 0) {
+    sh[3 * w] = amax;
+    sh[3 * w + 1] = vmin;
+    sh[3 * w + 2] = ss;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < TPB / WAVE; ++k) {
+      sh[0] = fmax(sh[0], sh[3 * k]);
+      sh[1] = fmin(sh[1], sh[3 * k + 1]);
+      sh[2] += sh[3 * k + 2];
+    }
+    part[3 * blockIdx.x] = sh[0];
+    part[3 * blockIdx.x + 1] = sh[1];
+    part[3 * blockIdx.x + 2] = sh[2];
+  }
+}
+
+__global__ void k_res_final(const double* __restrict__ part, int np, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double a = 0.0, v = DBL_MAX, s = 0.0;
+  for (int k = 0; k < np; ++k) {
+    a = fmax(a, part[3 * k]);
+    v = fmin(v, part[3 * k + 1]);
+    s += part[3 * k + 2];
+  }
+  out[0] = a;
+  out[1] = v;
+  out[2] = s;
+}
+
+__device__ __forceinline__ double wrap1(double v, double L) {
+  v = fmod(v, L);
+  if (v < 0) v += L;
+  if (!(v < L)) v = 0.0;
+  return v;
+}
+
+__global__ void k_finalize(const double4* __restrict__ pts, const int32_t* __restrict__ perm,
+                           const double* __restrict__ psi_s, const double* __restrict__ mean_slot,
+                           const double* __restrict__ vol, const double* __restrict__ mom, double L,
+                           double* __restrict__ psi_out, double* __restrict__ cent,
+                           double* __restrict__ disp, int64_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int64_t o = perm[p];
+  const double4 x = pts[p];
+  const double v = vol[p];
+  double u0 = 0.0, u1 = 0.0, u2 = 0.0;
+  if (v > 0.0) {
+    u0 = mom[3 * p] / v;
+    u1 = mom[3 * p + 1] / v;
+    u2 = mom[3 * p + 2] / v;
+  }
+  if (psi_out) psi_out[o] = psi_s[p] - mean_slot[0] / double(n);
+  cent[3 * o] = wrap1(x.x + u0, L);
+  cent[3 * o + 1] = wrap1(x.y + u1, L);
+  cent[3 * o + 2] = wrap1(x.z + u2, L);
+  if (disp) {
+    disp[3 * o] = -u0;
+    disp[3 * o + 1] = -u1;
+    disp[3 * o + 2] = -u2;
+  }
+}
+
+__global__ void k_scatter_vol(const int32_t* __restrict__ perm, const double* __restrict__ vs,
+                              double* __restrict__ vo, int64_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) vo[perm[p]] = vs[p];
+}
+
+__global__ void k_gather(const int32_t* __restrict__ perm, const double* __restrict__ orig,
+                         double* __restrict__ sorted, int64_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) sorted[p] = orig[perm[p]];
+}
+
+}  // namespace
+
+void axpy_into(const double* a, const double* b, double alpha, double* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_into, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st, a, b, alpha, out, n);
+  MAK_HIP(hipGetLastError());
+}
+
+void newton_residual(const double* vol, double m, double* g, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st, vol, m, g, n);
+  MAK_HIP(hipGetLastError());
+}
+
+double residual_stats(const double* vol, double m, int64_t n, DevBuf& tmp, double* max_rel,
+                      double* min_vol, hipStream_t st) {
+  tmp.ensure(size_t(3 * MAXB + 8) * sizeof(double));
+  double* part = tmp.as<double>();
+  const unsigned nb = vec_blocks(n);
+  hipLaunchKernelGGL(k_res_stats, dim3(nb), dim3(TPB), 0, st, vol, m, part, n);
+  hipLaunchKernelGGL(k_res_final, dim3(1), dim3(64), 0, st, part, int(nb), part + 3 * MAXB);
+  MAK_HIP(hipGetLastError());
+  double h[3];
+  MAK_HIP(hipMemcpyAsync(h, part + 3 * MAXB, sizeof(h), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  *max_rel = h[0] / m;
+  *min_vol = h[1];
+  return std::sqrt(h[2]);
+}
+
+void finalize_outputs(const PointSet& ps, const double* psi_sorted, double psi_mean_unused,
+                      const double* vol, const double* mom, double* psi_out, double* cent_out,
+                      double* disp_out, hipStream_t st) {
+  (void)psi_mean_unused;
+  const int64_t n = ps.N;
+  // mean of psi (device), then the permuted outputs
+  DevBuf& tmp = const_cast<PointSet&>(ps).tmp;
+  tmp.ensure(size_t(MAXB + 16) * sizeof(double));
+  double* part = tmp.as<double>();
+  const unsigned nb = vec_blocks(n);
+  if (psi_out) {
+    hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, psi_sorted, part, n);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, part + MAXB, 0, 0);
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st,
+                     ps.pts.as<double4>(), ps.perm.as<int32_t>(), psi_sorted, part + MAXB, vol, mom,
+                     ps.g.L, psi_out, cent_out, disp_out, n);
+  MAK_HIP(hipGetLastError());
+}
+
+void scatter_cells_outputs(const PointSet& ps, const double* vol_s, const double* mom_s,
+                           double* vol_out, double* cent_out, hipStream_t st) {
+  const int64_t n = ps.N;
+  hipLaunchKernelGGL(k_scatter_vol, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st,
+                     ps.perm.as<int32_t>(), vol_s, vol_out, n);
+  if (cent_out)
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st,
+                       ps.pts.as<double4>(), ps.perm.as<int32_t>(), nullptr, nullptr, vol_s, mom_s,
+                       ps.g.L, nullptr, cent_out, nullptr, n);
+  MAK_HIP(hipGetLastError());
+}
+
+void gather_sorted(const PointSet& ps, const double* orig, double* sorted, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(unsigned(ceil_div(ps.N, 256))), dim3(256), 0, st,
+                     ps.perm.as<int32_t>(), orig, sorted, ps.N);
+  MAK_HIP(hipGetLastError());
+}
+
+}  // namespace mak

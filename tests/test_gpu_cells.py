@@ -1,0 +1,192 @@
+"""GPU parity of mak_laguerre_cells with the CPU oracle (through the C-ABI)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.parity import compare_cells, csr_to_dense, gpu_faces, spacing
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2110_08868_amd as mak
+    c = mak.Context(0)
+    yield c
+    c.close()
+
+
+def run(ctx, x, psi, L):
+    import torch
+    V, C, info = ctx.laguerre_cells(torch.from_numpy(x), torch.from_numpy(psi), L)
+    F = gpu_faces(ctx)
+    return V.cpu().numpy(), C.cpu().numpy(), F, info
+
+
+def check(ctx, x, psi, L, hessian=True, **kw):
+    print(f"case N={x.shape[0]} L={L}", flush=True)
+    V, C, F, info = run(ctx, x, psi, L)
+    res = oracle.cells(x, psi, L)
+    rep = compare_cells(x, psi, L, V, C, F, res=res, **kw)
+    if hessian and x.shape[0] <= 4096:
+        rp, col, val = (t.cpu().numpy() for t in ctx.hessian())
+        if x.shape[0] <= 1024:
+            Jg = csr_to_dense(rp, col, val, x.shape[0])
+            Jo = oracle.hessian_dense(res, x.shape[0])
+            assert np.abs(Jg - Jo).max() <= 1e-9 * max(np.abs(Jo).max(), 1e-300)
+        else:
+            import scipy.sparse as sp
+            Jg = sp.csr_matrix((val, col, rp), shape=(x.shape[0],) * 2)
+            Jo = oracle.hessian_coo(res, x.shape[0])
+            assert abs(Jg - Jo).max() <= 1e-9 * abs(Jo).max()
+        # columns sorted, zero row sums
+        for i in range(min(x.shape[0], 200)):
+            c = col[rp[i]:rp[i + 1]]
+            assert np.all(np.diff(c) > 0)
+        rs = np.add.reduceat(val, rp[:-1]) if len(val) else np.zeros(0)
+        assert np.abs(rs).max() <= 1e-12 * max(np.abs(val).max(), 1e-300)
+    print(f"  {rep} nnz={info['nnz']} faces={info['faces']} max_faces={info['max_faces']}",
+          flush=True)
+    return V, C, F, info, rep
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_lattice(ctx, n):
+    x = workloads.lattice(n)
+    V, C, F, info, rep = check(ctx, x, np.zeros(n ** 3), 1.0)
+    assert np.allclose(V, 1.0 / n ** 3, rtol=1e-13)
+    assert rep["straddling_faces"] == 0
+
+
+def test_lattice_translated(ctx):
+    x = workloads.lattice(4, offset=(0.0123, -0.31, 0.077))
+    check(ctx, x, np.zeros(64), 1.0)
+
+
+def test_golden_exact(ctx):
+    g = json.load(open(os.path.join(GOLDEN, "exact_cells_dyadic8.json")))
+    from fractions import Fraction as Fr
+    x = np.array(g["x"])
+    psi = np.array(g["psi"])
+    V, C, F, info = run(ctx, x, psi, g["L"])
+    for i, c in enumerate(g["cells"]):
+        assert V[i] == pytest.approx(float(Fr(c["V"])), rel=1e-12)
+
+
+@pytest.mark.parametrize("seed,wscale", [(1, 0.0), (2, 0.02), (3, 0.05)])
+def test_zeldovich_16(ctx, seed, wscale):
+    n = 16
+    x = workloads.zeldovich(n, rms=0.3, smooth=2.0, seed=seed)
+    rng = np.random.default_rng(seed)
+    psi = rng.uniform(-1, 1, n ** 3) * wscale / n ** 2
+    check(ctx, x, psi, 1.0)
+
+
+def test_strong_displacement_weights(ctx):
+    n = 8
+    x = workloads.zeldovich(n, rms=1.5, smooth=1.0, seed=7)
+    rng = np.random.default_rng(7)
+    psi = rng.uniform(-1, 1, n ** 3) * 0.3 / n ** 2
+    check(ctx, x, psi, 1.0)
+
+
+def test_ragged_uniform_and_box_size(ctx):
+    rng = np.random.default_rng(5)
+    x = rng.uniform(0, 2.5, size=(1000, 3))
+    psi = rng.uniform(-1, 1, 1000) * 0.01
+    check(ctx, x, psi, 2.5)
+
+
+def test_clustered(ctx):
+    n = 12
+    x = workloads.clustered(n, rms=2.0, smooth=1.0, frac=0.2, n_clumps=10, a=0.5, seed=4)
+    check(ctx, x, np.zeros(n ** 3), 1.0)
+
+
+def test_layered_closed_form(ctx):
+    from tests.closed_forms import layered_cells
+    rng = np.random.default_rng(3)
+    X = np.sort(rng.uniform(0, 1, 5))
+    dmin = np.min(np.diff(np.append(X, X[0] + 1)))
+    psi_l = rng.uniform(-1, 1, 5) * 0.1 * dmin ** 2
+    x = workloads.layered(X, 4, 4)
+    psi = np.repeat(psi_l, 16)
+    V, C, F, info, rep = check(ctx, x, psi, 1.0)
+    Vc, ux, J = layered_cells(X, psi_l, 4, 4, 1.0)
+    assert np.allclose(V, Vc, rtol=1e-12)
+
+
+def test_points_outside_box_are_wrapped(ctx):
+    x = workloads.zeldovich(6, rms=0.4, smooth=1.0, seed=8)
+    shift = np.random.default_rng(8).integers(-3, 4, size=x.shape).astype(np.float64)
+    V1, C1, _, _ = run(ctx, x, np.zeros(216), 1.0)
+    V2, C2, _, _ = run(ctx, x + shift, np.zeros(216), 1.0)
+    assert np.allclose(V1, V2, rtol=1e-12)
+
+
+def test_empty_cell(ctx):
+    x = workloads.zeldovich(5, rms=0.3, smooth=1.0, seed=9)
+    psi = np.zeros(125)
+    psi[7] = -0.5
+    V, C, F, info, rep = check(ctx, x, psi, 1.0)
+    assert V[7] == 0.0 and info["empty_cells"] == 1
+    assert V.sum() == pytest.approx(1.0, rel=1e-12)
+
+
+def test_deterministic(ctx):
+    x = workloads.zeldovich(10, rms=0.8, smooth=1.0, seed=12)
+    psi = np.random.default_rng(12).uniform(-1, 1, 1000) * 0.003
+    V1, C1, F1, _ = run(ctx, x, psi, 1.0)
+    V2, C2, F2, _ = run(ctx, x, psi, 1.0)
+    assert np.array_equal(V1, V2) and np.array_equal(C1, C2)
+    assert np.array_equal(F1["face_area"], F2["face_area"])
+
+
+def test_errors(ctx):
+    import torch
+
+    import paper_2110_08868_amd as mak
+    x = workloads.lattice(2)
+    dup = np.vstack([x, x[:1]])
+    with pytest.raises(mak.MakError) as e:
+        ctx.laguerre_cells(torch.from_numpy(dup), torch.zeros(9, dtype=torch.float64), 1.0)
+    assert e.value.name == "MAK_EDEGENERATE"
+    bad = x.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(mak.MakError) as e:
+        ctx.laguerre_cells(torch.from_numpy(bad), torch.zeros(8, dtype=torch.float64), 1.0)
+    assert e.value.name == "MAK_EINVAL"
+    with pytest.raises(mak.MakError) as e:
+        ctx.laguerre_cells(torch.from_numpy(x), torch.zeros(8, dtype=torch.float64), -1.0)
+    assert e.value.name == "MAK_EINVAL"
+    # the context still works after errors
+    check(ctx, x, np.zeros(8), 1.0)
+
+
+def test_full_size_64_sampled(ctx):
+    """64^3 (the mid-size workload) at psi = 0 and at random weights: sampled
+    cells against the oracle's one-cell computation, plus global invariants."""
+    import torch
+    n = 64
+    x = workloads.zeldovich(n, rms=1.0, smooth=1.0, seed=2)
+    N = n ** 3
+    rng = np.random.default_rng(2)
+    for psi in (np.zeros(N), rng.uniform(-1, 1, N) * 0.05 / n ** 2):
+        V, C, info = ctx.laguerre_cells(torch.from_numpy(x), torch.from_numpy(psi), 1.0)
+        V = V.cpu().numpy()
+        C = C.cpu().numpy()
+        F = gpu_faces(ctx)
+        assert V.sum() == pytest.approx(1.0, rel=1e-11)
+        idx = rng.choice(N, 64, replace=False)
+        res = oracle.cells(x, psi, 1.0, idx=idx)
+        rep = compare_cells(x, psi, 1.0, V, C, F, res=res)
+        print(f"  64^3 sampled: {rep} nnz={info['nnz']} max_faces={info['max_faces']}", flush=True)
+        rp, col, val = (t.cpu().numpy() for t in ctx.hessian())
+        rs = np.add.reduceat(val, rp[:-1])
+        assert np.abs(rs).max() <= 1e-12 * np.abs(val).max()

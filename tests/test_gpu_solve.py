@@ -1,0 +1,84 @@
+"""GPU damped-Newton solve (mak_solve) against the oracle: certificate by the
+oracle's own cells at the returned weights, and closed-form solutions."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2110_08868_amd as mak
+    c = mak.Context(0, cg_rtol=1e-6)
+    yield c
+    c.close()
+
+
+def gsolve(ctx, x, L, tol):
+    import torch
+    psi, C, D, info = ctx.solve(torch.from_numpy(x), L, tol)
+    print(f"  solve N={x.shape[0]}: {info}", flush=True)
+    return psi.cpu().numpy(), C.cpu().numpy(), D.cpu().numpy(), info
+
+
+def certificate(x, psi, L, tol):
+    r = oracle.cells(x, psi, L)
+    N = x.shape[0]
+    err = float(np.max(np.abs(r["V"] - L ** 3 / N)) / (L ** 3 / N))
+    assert err <= tol * 1.001, f"oracle volume error at GPU psi: {err:.3e}"
+    return r, err
+
+
+def test_lattice_zero_iterations(ctx):
+    x = workloads.lattice(6, offset=(0.01, 0.02, 0.03))
+    psi, C, D, info = gsolve(ctx, x, 1.0, 1e-10)
+    assert info["newton_iters"] == 0
+    assert np.allclose(psi, 0.0) and np.allclose(D, 0.0, atol=1e-15)
+
+
+def test_layered_solution(ctx):
+    from tests.closed_forms import layered_ot_psi
+    rng = np.random.default_rng(7)
+    X = np.sort(rng.uniform(0, 1, 6))
+    psi_l, _ = layered_ot_psi(X, 1.0)
+    x = workloads.layered(X, 4, 4)
+    psi, C, D, info = gsolve(ctx, x, 1.0, 1e-11)
+    ref = np.repeat(psi_l, 16)
+    ref -= ref.mean()
+    assert np.allclose(psi, ref, atol=1e-11)
+    certificate(x, psi, 1.0, 1e-11)
+
+
+def test_c1_solve_vs_oracle(ctx):
+    """16^3 lattice, Zel'dovich rms 0.3 spacing, smoothing 2 spacings, seed 1,
+    tol 1e-6: certificate and agreement with the oracle's own solve."""
+    n = 16
+    x = workloads.zeldovich(n, rms=0.3, smooth=2.0, seed=1)
+    psi, C, D, info = gsolve(ctx, x, 1.0, 1e-6)
+    r, err = certificate(x, psi, 1.0, 1e-6)
+    s = oracle.solve(x, 1.0, tol=1e-9)
+    dpsi = psi - s["psi"]
+    dpsi -= dpsi.mean()
+    D2 = (1.0 / n) ** 2
+    print(f"  certificate err={err:.3e}  psi rms diff={np.sqrt(np.mean(dpsi ** 2)) / D2:.3e} D^2",
+          flush=True)
+    assert np.sqrt(np.mean(dpsi ** 2)) <= 1e-4 * D2
+    dd = D - s["disp"]
+    assert np.abs(dd).max() <= 1e-4 / n
+    # displacements are minus the seed-local centroid offsets
+    assert np.abs(D).max() < 2.0 / n
+
+
+def test_resume_from_saved_psi(ctx):
+    import torch
+    n = 8
+    x = workloads.zeldovich(n, rms=0.6, smooth=1.0, seed=5)
+    psi1, C1, D1, i1 = gsolve(ctx, x, 1.0, 1e-3)
+    psi2, C2, D2, i2 = ctx.solve_from(torch.from_numpy(x), torch.from_numpy(psi1), 1.0, 1e-9)
+    psi2 = psi2.cpu().numpy()
+    certificate(x, psi2, 1.0, 1e-9)
+    psi3, C3, D3, i3 = gsolve(ctx, x, 1.0, 1e-9)
+    assert np.allclose(psi2, psi3, atol=1e-9 / n ** 2)
