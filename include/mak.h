@@ -157,6 +157,33 @@ mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double 
                           double* psi, double* centroids, double* displacements,
                           mak_solve_info* info, void* stream);
 
+/* ---- kernel profile (diagnostics; used by the benchmark) ----
+ * When timing is enabled, the library brackets its main kernels with HIP
+ * events on the stream each is launched on and accumulates their durations;
+ * with work counting it also reads device work counters after every clip
+ * launch (this adds a host synchronisation per launch, so time and count in
+ * separate runs). */
+typedef struct {
+  char name[32];       /* "clip", "clip_large", "spmv", "pcg_update", "pcg_solve",
+                          "csr_assembly", "grid_build" */
+  int64_t launches;
+  double total_ms;     /* summed event durations */
+  double units;        /* work items processed (cells, rows) */
+  double flops;        /* counted arithmetic (work counting only for clip) */
+  double bytes;        /* compulsory HBM bytes of the algorithm */
+} mak_kernel_profile;
+
+/* flags: bit 0 = time kernels, bit 1 = count clip work.  Clears the
+ * accumulated profile. */
+mak_status mak_profile_enable(mak_ctx* ctx, int32_t flags);
+/* Writes up to max_entries entries (HOST array, may be NULL) and returns the
+ * number of entries available, or -1 on error.  Waits for pending events. */
+int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entries);
+/* HOST double[16]: summed clip work counters (sites scanned, planes tested,
+ * vertex tests, cuts, new vertices, ball-update vertices, box tests, final
+ * vertices, faces, cells). */
+mak_status mak_profile_counters(mak_ctx* ctx, double* out);
+
 /* Device memory a solve of N sites needs at most (bytes), for admission. */
 size_t mak_solve_memory_estimate(int64_t N, int32_t precision);
 

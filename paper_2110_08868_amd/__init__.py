@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmak.so")
 EXPORTED_SYMBOLS = [
     "mak_default_options", "mak_create", "mak_destroy", "mak_last_error",
     "mak_laguerre_cells", "mak_hessian_copy", "mak_faces_copy", "mak_solve",
-    "mak_solve_from", "mak_solve_memory_estimate",
+    "mak_solve_from", "mak_solve_memory_estimate", "mak_profile_enable", "mak_profile_read",
+    "mak_profile_counters",
 ]
 
 STATUS = {0: "MAK_OK", 1: "MAK_EINVAL", 2: "MAK_ENOMEM", 3: "MAK_EDEGENERATE",
@@ -65,6 +66,17 @@ class _CellsInfo(ctypes.Structure):
     ]
 
 
+class _KernelProfile(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+        ("units", ctypes.c_double), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+    ]
+
+
+COUNTER_NAMES = ["sites_scanned", "planes_tested", "vertex_tests", "cuts", "new_vertices",
+                 "ball_vertices", "box_tests", "final_vertices", "faces", "cells"]
+
+
 def _as_dict(s) -> dict:
     return {name: getattr(s, name) for name, _ in s._fields_ if name != "reserved"}
 
@@ -101,6 +113,12 @@ def load_library():
     lib.mak_solve_from.restype = ctypes.c_int
     lib.mak_solve_memory_estimate.argtypes = [I64, I32]
     lib.mak_solve_memory_estimate.restype = ctypes.c_size_t
+    lib.mak_profile_enable.argtypes = [P, I32]
+    lib.mak_profile_enable.restype = ctypes.c_int
+    lib.mak_profile_read.argtypes = [P, P, I32]
+    lib.mak_profile_read.restype = I32
+    lib.mak_profile_counters.argtypes = [P, P]
+    lib.mak_profile_counters.restype = ctypes.c_int
     _LIB = lib
     return lib
 
@@ -216,6 +234,26 @@ class Context:
         self._check(self.lib.mak_faces_copy(self._h, fp.data_ptr(), fj.data_ptr(), fs.data_ptr(),
                                             fa.data_ptr(), self._stream()))
         return {"face_ptr": fp, "face_j": fj[:nf], "face_shift": fs[:nf], "face_area": fa[:nf]}
+
+    def profile_enable(self, timing: bool = True, counting: bool = False):
+        """Start (and clear) the kernel profile: event timing and/or counted work."""
+        self._check(self.lib.mak_profile_enable(self._h, (1 if timing else 0) | (2 if counting else 0)))
+
+    def profile_read(self) -> dict:
+        """{kernel name: {launches, total_ms, units, flops, bytes}} since profile_enable."""
+        n = self.lib.mak_profile_read(self._h, None, 0)
+        if n < 0:
+            raise MakError(6, self.lib.mak_last_error(self._h).decode())
+        arr = (_KernelProfile * max(n, 1))()
+        self.lib.mak_profile_read(self._h, arr, n)
+        out = {}
+        for k in range(n):
+            d = _as_dict(arr[k])
+            out[d.pop("name").decode()] = d
+        c = (ctypes.c_double * 16)()
+        self._check(self.lib.mak_profile_counters(self._h, c))
+        out["_counters"] = {name: c[i] for i, name in enumerate(COUNTER_NAMES)}
+        return out
 
     def _solve(self, fn, points, L, tol, psi0):
         torch = _torch()

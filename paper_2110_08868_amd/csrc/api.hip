@@ -15,10 +15,13 @@
 #include <utility>
 
 #include "engine.h"
+#include "profile.h"
 
 using namespace mak;
 
 namespace mak {
+
+thread_local Profiler* g_prof = nullptr;
 
 void swap_buf(DevBuf& a, DevBuf& b) {
   std::swap(a.p, b.p);
@@ -104,14 +107,23 @@ struct mak_ctx {
   Csr sJ;
   PcgWork pw;
   DevBuf psi_s, psi_t, g, pstep, tmp;
+  Profiler prof;
 };
 
 namespace {
 
 thread_local std::string g_create_error;
 
+struct ProfBind {
+  explicit ProfBind(mak_ctx* c) {
+    g_prof = (c && (c->prof.timing || c->prof.counting)) ? &c->prof : nullptr;
+  }
+  ~ProfBind() { g_prof = nullptr; }
+};
+
 template <class F>
 mak_status guarded(mak_ctx* ctx, F&& f) {
+  ProfBind bind(ctx);
   try {
     f();
     return MAK_OK;
@@ -285,9 +297,13 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
     double gn = residual_stats(ctx->scp.vol.as<double>(), m, N, ctx->tmp, &err, &vmin, st);
     const double eps0 = 0.5 * std::min(m, vmin);
     if (o.verbose) fprintf(stderr, "[mak] N=%lld it=0 err=%.3e minV/m=%.3e\n", (long long)N, err, vmin / m);
+    std::string noconv;
     for (int it = 0;; ++it) {
       if (err <= tol) break;
-      if (it >= o.max_newton) MAK_FAIL(MAK_ENOCONV, "Newton iteration limit reached, err=" + std::to_string(err));
+      if (it >= o.max_newton) {
+        noconv = "Newton iteration limit reached, err=" + std::to_string(err);
+        break;
+      }
       newton_residual(ctx->scp.vol.as<double>(), m, ctx->g.as<double>(), N, st);
       const int cgi = pcg_solve(ctx->sJ, ctx->g.as<double>(), ctx->pstep.as<double>(), N, o.cg_rtol,
                                 o.max_cg, ctx->pw, st);
@@ -297,10 +313,14 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       for (int ls = 0; ls <= o.max_halvings; ++ls) {
         axpy_into(ctx->psi_s.as<double>(), ctx->pstep.as<double>(), alpha, ctx->psi_t.as<double>(), N, st);
         set_psi_sorted(ps, ctx->psi_t.as<double>(), st);
-        ClipStats ct = run_cells(ps, ctx->scp_trial, o.precision, true, st);
+        ClipStats ct = run_cells(ps, ctx->scp_trial, o.precision, true, st, true);
         si.cell_passes += 1;
         si.ls_trials += 1;
         si.overflow_cells += ct.retried;
+        if (ct.overflow > 0) {  // cells beyond the polytope capacity: reject the trial
+          alpha *= 0.5;
+          continue;
+        }
         double e2 = 0, v2 = 0;
         const double g2 = residual_stats(ctx->scp_trial.vol.as<double>(), m, N, ctx->tmp, &e2, &v2, st);
         if (v2 >= eps0 && g2 <= (1.0 - 0.5 * alpha) * gn) {
@@ -317,7 +337,8 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       }
       if (!accepted) {
         set_psi_sorted(ps, ctx->psi_s.as<double>(), st);
-        MAK_FAIL(MAK_ENOCONV, "line search failed");
+        noconv = "line search failed";
+        break;
       }
       si.newton_iters += 1;
       if (o.verbose)
@@ -325,8 +346,13 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
                 vmin / m);
     }
     si.final_err = err;
+    // outputs of the last accepted iterate (also when the limits were hit)
     finalize_outputs(ps, ctx->psi_s.as<double>(), 0.0, ctx->scp.vol.as<double>(),
                      ctx->scp.mom.as<double>(), psi, centroids, displacements, st);
+    if (!noconv.empty()) {
+      MAK_HIP(hipStreamSynchronize(st));
+      MAK_FAIL(MAK_ENOCONV, noconv);
+    }
     MAK_HIP(hipStreamSynchronize(st));
   });
   si.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -344,6 +370,45 @@ mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double 
                           void* stream) {
   if (!psi) return MAK_EINVAL;
   return solve_impl(ctx, points, N, L, tol, psi, psi, centroids, displacements, info, stream);
+}
+
+mak_status mak_profile_enable(mak_ctx* ctx, int32_t flags) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    set_device(ctx);
+    ctx->prof.clear();
+    ctx->prof.timing = (flags & 1) != 0;
+    ctx->prof.counting = (flags & 2) != 0;
+  });
+}
+
+int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entries) {
+  if (!ctx) return -1;
+  int32_t n = 0;
+  const mak_status st = guarded(ctx, [&] {
+    set_device(ctx);
+    ctx->prof.resolve();
+    for (const auto& kv : ctx->prof.acc) {
+      if (out && n < max_entries) {
+        mak_kernel_profile& o = out[n];
+        std::memset(&o, 0, sizeof(o));
+        std::strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+        o.launches = kv.second.launches;
+        o.total_ms = kv.second.ms;
+        o.units = kv.second.units;
+        o.flops = kv.second.flops;
+        o.bytes = kv.second.bytes;
+      }
+      ++n;
+    }
+  });
+  return st == MAK_OK ? n : -1;
+}
+
+mak_status mak_profile_counters(mak_ctx* ctx, double* out) {
+  if (!ctx || !out) return MAK_EINVAL;
+  for (int k = 0; k < 16; ++k) out[k] = ctx->prof.counters[k];
+  return MAK_OK;
 }
 
 size_t mak_solve_memory_estimate(int64_t N, int32_t precision) {

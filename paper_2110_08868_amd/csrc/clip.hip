@@ -37,6 +37,7 @@
 
 #include "engine.h"
 #include "gridkey.h"
+#include "profile.h"
 
 namespace mak {
 
@@ -61,13 +62,20 @@ struct ClipArgs {
   FaceRec* ovf;
   unsigned long long* ovf_used;     // faces placed in the overflow region
   unsigned long long* retry_count;  // cells appended to `retry`
+  unsigned long long* cause;        // [0] capacity, [1] inconsistent cut
   int32_t* retry;
   int64_t ovf_cap;
   int32_t fslot;
   int32_t write_faces;
   double area_min;
   double eps_rel;
+  unsigned long long* stats;  // optional work counters (see CLIP_STATS)
 };
+
+// Work counters of the clip kernel (optional): sites scanned, planes tested
+// against the vertices, vertex tests, cuts, new vertices, ball updates (in
+// vertices), box tests, final vertices, reported faces, cells.
+enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS, ST_N };
 
 template <int TPL>
 struct ClipLDS {
@@ -161,6 +169,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
 
   int32_t flags = 0;
   bool dead = false;
+  uint32_t c_cand = 0, c_test = 0, c_vt = 0, c_cut = 0, c_newv = 0, c_ball = 0, c_box = 0;
 
   // ---------------------------------------------------------------- box
   if (lane < 6) {
@@ -241,6 +250,66 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     brho = sqrtf(r2) * 1.0001f + 1e-6f * (cn + float(h));
   };
 
+  // Drop the planes no vertex refers to any more (cut away by later planes)
+  // and renumber the rest; the table fills up when many sites cut the cell
+  // in turn (dense clumps).
+  auto compact_planes = [&]() {
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (k * 64 + lane < nT) {
+        const int a = tri_a(tri[k]), b = tri_b(tri[k]), c = tri_c(tri[k]);
+        atomicOr(&S.sbits[a >> 5], 1u << (a & 31));
+        atomicOr(&S.sbits[b >> 5], 1u << (b & 31));
+        atomicOr(&S.sbits[c >> 5], 1u << (c & 31));
+      }
+    }
+    __syncthreads();
+    double4 cpl[TPL];
+    int32_t cj[TPL], cs[TPL], cnew[TPL];
+    bool calive[TPL];
+    int alive_total = 0;
+#pragma unroll
+    for (int w = 0; w < PW; ++w) alive_total += __popc(S.sbits[w]);
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) {
+      const int f = c * 64 + lane;
+      calive[c] = f < nP && ((S.sbits[f >> 5] >> (f & 31)) & 1u);
+      int below = __popc(S.sbits[f >> 5] & ((1u << (f & 31)) - 1u));
+      for (int w = 0; w < (f >> 5); ++w) below += __popc(S.sbits[w]);
+      cnew[c] = below;
+      if (calive[c]) {
+        cpl[c] = S.pl[f];
+        cj[c] = S.pj[f];
+        cs[c] = S.ps[f];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < TPL; ++c) {
+      if (calive[c]) {
+        const int f = c * 64 + lane;
+        S.pl[cnew[c]] = cpl[c];
+        S.pj[cnew[c]] = cj[c];
+        S.ps[cnew[c]] = cs[c];
+        S.bits[f] = uint32_t(cnew[c]);  // old -> new index (bitmap is idle here)
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (k * 64 + lane < nT) {
+        const uint32_t t = tri[k];
+        tri[k] = tri_pack(int(S.bits[tri_a(t)]), int(S.bits[tri_b(t)]), int(S.bits[tri_c(t)]));
+        S.stri[k * 64 + lane] = tri[k];
+      }
+    }
+    __syncthreads();
+    for (int w = lane; w < PCAP; w += 64) S.bits[w] = 0u;
+    if (lane < PW) S.sbits[lane] = 0u;
+    nP = alive_total;
+    __syncthreads();
+  };
+
   // Clip by u . d <= bb (plane tag jj / ss).
   auto clip_one = [&](double dx, double dy, double dz, double bb, int32_t jj, int32_t ss) {
     const double dn = sqrt(dx * dx + dy * dy + dz * dz);
@@ -248,6 +317,8 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     if (cd + double(brho) * dn <= bb - mtol) return;  // cannot reach the ball
     const double rb = sqrt(double(bcx) * bcx + double(bcy) * bcy + double(bcz) * bcz) + double(brho);
     const double eps = eps_rel * dn * rb;
+    c_test += 1;
+    c_vt += uint32_t(nT);
     uint64_t om[TPL];
     int nout = 0;
 #pragma unroll
@@ -265,9 +336,12 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       return;
     }
     if (nP >= PCAP) {
-      flags |= CF_CAPACITY;
-      dead = true;
-      return;
+      compact_planes();
+      if (nP >= PCAP) {
+        flags |= CF_CAPACITY;
+        dead = true;
+        return;
+      }
     }
     const int pn = nP;
     if (lane == 0) {
@@ -382,6 +456,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       }
     }
     __syncthreads();
+    c_cut += 1;
+    c_newv += uint32_t(nTn - nkept);
+    c_ball += uint32_t(nTn);
     nT = nTn;
     nP = pn + 1;
 #pragma unroll
@@ -432,6 +509,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     __syncthreads();
     for (int base = 0; base < total && !dead; base += 64) {
       const int t = base + lane;
+      c_cand += uint32_t(min(64, total - base));
       int lo = 0, hi = ncl - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -509,6 +587,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       const int count = rb == 0 ? 1 : S1 * S1 * S1 - I1 * I1 * I1;
       for (int base = 0; base < count && !dead; base += 64) {
         const int t = base + lane;
+        c_box += uint32_t(min(64, count - base));
         bool ok = false;
         int ubx = 0, uby = 0, ubz = 0;
         if (t < count) {
@@ -529,6 +608,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
           const int l = __ffsll((unsigned long long)bmask) - 1;
           bmask &= bmask - 1;
           const int qbx = readlane_i(ubx, l), qby = readlane_i(uby, l), qbz = readlane_i(ubz, l);
+          c_box += 64;
           const int ux = qbx * BLOCK_SIDE + (lane >> 4), uy = qby * BLOCK_SIDE + ((lane >> 2) & 3),
                     uz = qbz * BLOCK_SIDE + (lane & 3);
           const bool inA = abs(ux - cx) <= 1 && abs(uy - cy) <= 1 && abs(uz - cz) <= 1;
@@ -549,9 +629,27 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     }
   }
 
+  auto flush_stats = [&](int ntri, int nfaces) {
+    if (A.stats && lane == 0) {
+      unsigned long long* st = A.stats;
+      atomicAdd(&st[ST_CAND], (unsigned long long)c_cand);
+      atomicAdd(&st[ST_TEST], (unsigned long long)c_test);
+      atomicAdd(&st[ST_VTEST], (unsigned long long)c_vt);
+      atomicAdd(&st[ST_CUT], (unsigned long long)c_cut);
+      atomicAdd(&st[ST_NEWV], (unsigned long long)c_newv);
+      atomicAdd(&st[ST_BALL], (unsigned long long)c_ball);
+      atomicAdd(&st[ST_BOX], (unsigned long long)c_box);
+      atomicAdd(&st[ST_TRI], (unsigned long long)ntri);
+      atomicAdd(&st[ST_FACES], (unsigned long long)nfaces);
+      atomicAdd(&st[ST_CELLS], 1ull);
+    }
+  };
+
   if (dead) {
+    flush_stats(0, 0);
     if (lane == 0) {
       if (flags & (CF_CAPACITY | CF_NONMANIFOLD)) {
+        atomicAdd(&A.cause[(flags & CF_CAPACITY) ? 0 : 1], 1ull);
         const unsigned long long r = atomicAdd(A.retry_count, 1ull);
         A.retry[r] = p;
       }
@@ -640,14 +738,16 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     }
   }
   __syncthreads();
-  // per-face areas: one lane per plane (box planes 0..5 are not faces of J)
+  // per-face areas: one lane per plane (faces of the own-image box, tagged
+  // j < 0, are not faces of J)
   double Af[TPL];
   int nf = 0;
 #pragma unroll
   for (int c = 0; c < TPL; ++c) {
-    const int f = 6 + c * 64 + lane;
+    const int f = c * 64 + lane;
     double a = 0.0;
-    if (f < nP) {
+    const bool real = f < nP && S.pj[f] >= 0;
+    if (real) {
 #pragma unroll
       for (int w = 0; w < TW; ++w) {
         uint32_t m = S.bits[f * TW + w];
@@ -659,7 +759,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
         }
       }
     }
-    Af[c] = (f < nP && a > A.area_min) ? a : 0.0;
+    Af[c] = (real && a > A.area_min) ? a : 0.0;
     nf += __popcll(ballot(Af[c] > 0.0));
   }
   if (A.write_faces) {
@@ -679,7 +779,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     int run = 0;
 #pragma unroll
     for (int c = 0; c < TPL; ++c) {
-      const int f = 6 + c * 64 + lane;
+      const int f = c * 64 + lane;
       const bool rep = Af[c] > 0.0;
       const uint64_t rm = ballot(rep);
       if (rep && dst) {
@@ -694,6 +794,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       run += __popcll(rm);
     }
   }
+  flush_stats(nT, nf);
   if (lane == 0) {
     A.vol[p] = v6 / 6.0;
     A.mom[3 * p] = m0 / 24.0;
@@ -704,9 +805,50 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
   }
 }
 
+// Counted arithmetic per work event (float64 ops, FMA = 2): scanning a site
+// (image offset, |d|^2, plane offset, ball test, sort key) 26; re-testing a
+// plane against the ball 21; one vertex-side test 7; one new vertex (three
+// cross products, determinant, solve) 50; one vertex of a ball update 11;
+// one box test 30; integrals per final vertex (three face triangles:
+// determinant, moment, area) 135.
+double clip_flops(const unsigned long long* c) {
+  return 26.0 * c[ST_CAND] + 21.0 * c[ST_TEST] + 7.0 * c[ST_VTEST] + 50.0 * c[ST_NEWV] +
+         11.0 * c[ST_BALL] + 30.0 * c[ST_BOX] + 135.0 * c[ST_TRI];
+}
+// Compulsory HBM bytes: read own site (32), write volume, moment, flags and
+// face count (40), write the reported faces (24 each).  Neighbour reads are
+// served by the caches.
+double clip_bytes(const unsigned long long* c) {
+  return 72.0 * c[ST_CELLS] + 24.0 * c[ST_FACES];
+}
+
+template <int TPL>
+void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
+  Profiler* pr = g_prof;
+  const bool counting = pr && pr->counting;
+  if (counting) {
+    a.stats = out.counters.as<unsigned long long>() + 4;
+    MAK_HIP(hipMemsetAsync(a.stats, 0, ST_N * sizeof(unsigned long long), st));
+  }
+  ProfScope ps(TPL == 2 ? "clip" : "clip_large", st, double(items));
+  hipLaunchKernelGGL(k_clip<TPL>, dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
+  MAK_HIP(hipGetLastError());
+  if (counting) {
+    unsigned long long c[ST_N];
+    MAK_HIP(hipMemcpyAsync(c, a.stats, sizeof(c), hipMemcpyDeviceToHost, st));
+    MAK_HIP(hipStreamSynchronize(st));
+    ps.flops = clip_flops(c);
+    ps.bytes = clip_bytes(c);
+    for (int k = 0; k < ST_N; ++k) pr->counters[k] += double(c[k]);
+  }
+  ps.stop();
+  a.stats = nullptr;
+}
+
 }  // namespace
 
-ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st) {
+ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
+                    bool tolerate_failure) {
   (void)precision;
   const int64_t N = ps.N;
   out.fslot = N <= (int64_t(1) << 24) ? 32 : 20;
@@ -715,7 +857,7 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
   out.cflags.ensure(size_t(N) * sizeof(int32_t));
   out.nface.ensure(size_t(N) * sizeof(int32_t));
   out.retry.ensure(size_t(N) * 2 * sizeof(int32_t));
-  out.counters.ensure(16 * sizeof(unsigned long long));
+  out.counters.ensure(32 * sizeof(unsigned long long));
   if (faces) {
     out.faces.ensure(size_t(N) * out.fslot * sizeof(FaceRec));
     out.fbase.ensure(size_t(N) * sizeof(int64_t));
@@ -724,7 +866,7 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
   }
   ClipStats cs;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    MAK_HIP(hipMemsetAsync(out.counters.p, 0, 16 * sizeof(unsigned long long), st));
+    MAK_HIP(hipMemsetAsync(out.counters.p, 0, 32 * sizeof(unsigned long long), st));
     ClipArgs a{};
     a.pts = ps.pts.as<double4>();
     a.cell_start = ps.cell_start.as<int32_t>();
@@ -747,6 +889,7 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
     a.ovf = faces ? out.ovf.as<FaceRec>() : nullptr;
     a.ovf_used = out.counters.as<unsigned long long>();
     a.retry_count = out.counters.as<unsigned long long>() + 1;
+    a.cause = out.counters.as<unsigned long long>() + 16;
     a.retry = out.retry.as<int32_t>();
     a.ovf_cap = faces ? out.ovf_cap : 0;
     a.fslot = out.fslot;
@@ -754,8 +897,8 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
     const double spacing = ps.g.L / std::cbrt(double(N));
     a.area_min = 1e-12 * spacing * spacing;
     a.eps_rel = 1e-13;
-    hipLaunchKernelGGL(k_clip<2>, dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
-    MAK_HIP(hipGetLastError());
+    a.stats = nullptr;
+    launch_clip<2>(a, out, N, st);
     unsigned long long hc[4];
     MAK_HIP(hipMemcpyAsync(hc, out.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
     MAK_HIP(hipStreamSynchronize(st));
@@ -771,10 +914,10 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
       a.nwork = int64_t(hc[1]);
       a.per_xcd = ceil_div(a.nwork, 8);
       a.retry_count = out.counters.as<unsigned long long>() + 2;
+      a.cause = out.counters.as<unsigned long long>() + 18;
       a.retry = out.retry.as<int32_t>() + a.nwork;  // failures land after the list
       a.eps_rel = 1e-11;
-      hipLaunchKernelGGL(k_clip<4>, dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
-      MAK_HIP(hipGetLastError());
+      launch_clip<4>(a, out, a.nwork, st);
       MAK_HIP(hipMemcpyAsync(hc, out.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
       MAK_HIP(hipStreamSynchronize(st));
       if (faces && int64_t(hc[0]) > out.ovf_cap) {
@@ -784,7 +927,12 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
       }
       if (hc[2] > 0) {
         cs.overflow = int64_t(hc[2]);
-        MAK_FAIL(MAK_EOVERFLOW, std::to_string(hc[2]) + " cells exceeded the polytope capacity");
+        if (tolerate_failure) return cs;
+        unsigned long long cz[2];
+        MAK_HIP(hipMemcpy(cz, out.counters.as<unsigned long long>() + 18, sizeof(cz),
+                          hipMemcpyDeviceToHost));
+        MAK_FAIL(MAK_EOVERFLOW, std::to_string(cz[0]) + " cells exceeded the polytope capacity, " +
+                                    std::to_string(cz[1]) + " had inconsistent cuts");
       }
     }
     return cs;

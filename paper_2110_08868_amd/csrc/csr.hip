@@ -4,6 +4,7 @@
 // per-cell face lists written by the clip kernel, sorted by column and merged
 // over periodic images.
 #include "engine.h"
+#include "profile.h"
 
 namespace mak {
 
@@ -109,6 +110,7 @@ __global__ void k_face_copy(const FaceRec* faces, const FaceRec* ovf, const int6
 
 void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hipStream_t st) {
   const int64_t n = ps.N;
+  ProfScope scope("csr_assembly", st, double(n));
   J.n = n;
   J.rowcnt.ensure(size_t(n) * 2 * sizeof(int64_t));
   J.row_ptr.ensure(size_t(n + 1) * sizeof(int64_t));

@@ -121,7 +121,11 @@ struct ClipStats {
 };
 // Full cell pass at the psi stored in ps.pts[].w.  precision: MAK_FP64 or
 // MAK_MIXED.  Throws on capacity overflow past the large kernel.
-ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st);
+// With `tolerate_failure`, cells the large kernel cannot represent are
+// reported in ClipStats::overflow instead of throwing (a line-search trial
+// is then rejected).
+ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
+                    bool tolerate_failure = false);
 
 // --- csr.hip
 // Assemble J (sorted index space, or original space when perm != NULL).

@@ -5,6 +5,7 @@
 
 #include "engine.h"
 #include "gridkey.h"
+#include "profile.h"
 
 namespace mak {
 
@@ -114,6 +115,7 @@ __global__ __launch_bounds__(64) void k_block_max(const double* __restrict__ cma
 
 void build_pointset(PointSet& ps, const double* points, const double* psi, int64_t N, double L,
                     double occupancy, hipStream_t st) {
+  ProfScope scope("grid_build", st, double(N));
   ps.N = N;
   ps.g = make_grid(N, L, occupancy);
   const int64_t G = ps.g.G();

@@ -6,6 +6,7 @@
 #include <cfloat>
 
 #include "engine.h"
+#include "profile.h"
 
 namespace mak {
 
@@ -164,6 +165,7 @@ __global__ void k_sub_mean(double* __restrict__ x, const double* __restrict__ sc
 
 int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
               PcgWork& w, hipStream_t st) {
+  ProfScope whole("pcg_solve", st, double(n));
   w.r.ensure(size_t(n) * sizeof(double));
   w.z.ensure(size_t(n) * sizeof(double));
   w.p.ensure(size_t(n) * sizeof(double));
@@ -198,10 +200,19 @@ int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, 
   int it = 0;
   for (; it < max_iter; ++it) {
     const int cur = (it & 1) ? S_RZ1 : S_RZ0, nxt = (it & 1) ? S_RZ0 : S_RZ1;
-    hipLaunchKernelGGL(k_spmv_dot, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
-                       J.col.as<int32_t>(), J.val.as<double>(), p, q, part, n);
+    {
+      // compulsory bytes: row_ptr, col, val, p (own row), q; flops 2 per nonzero + dot
+      ProfScope ps("spmv", st, double(n), 24.0 * double(n) + 12.0 * double(J.nnz));
+      ps.flops = 2.0 * double(J.nnz) + 2.0 * double(n);
+      hipLaunchKernelGGL(k_spmv_dot, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
+                         J.col.as<int32_t>(), J.val.as<double>(), p, q, part, n);
+    }
     hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nbs), 1, scal, int(S_PQ), 0);
-    hipLaunchKernelGGL(k_update, dim3(nb), dim3(TPB), 0, st, x, r, z, p, q, dinv, scal, cur, part, n);
+    {
+      ProfScope ps("pcg_update", st, double(n), 72.0 * double(n));
+      ps.flops = 10.0 * double(n);
+      hipLaunchKernelGGL(k_update, dim3(nb), dim3(TPB), 0, st, x, r, z, p, q, dinv, scal, cur, part, n);
+    }
     hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, nxt, int(S_RR));
     if ((it & 7) == 7 || it + 1 == max_iter) {
       double rr = 0;

@@ -109,6 +109,18 @@ def test_clustered(ctx):
     check(ctx, x, np.zeros(n ** 3), 1.0)
 
 
+def test_dense_clump(ctx):
+    """A few hundred sites in one Plummer clump inside a lattice: the cells
+    around the clump are cut by many sites in turn (plane-table compaction)."""
+    n = 8
+    x = workloads.zeldovich(n, rms=0.3, smooth=1.0, seed=21)
+    x = np.vstack([x, workloads.plummer_redraw(np.zeros((400, 3)), frac=1.0, n_clumps=1, a=0.4,
+                                               n=n, seed=21)])
+    workloads.assert_distinct(x)
+    V, C, F, info, rep = check(ctx, x, np.zeros(len(x)), 1.0)
+    assert info["max_faces"] > 20
+
+
 def test_layered_closed_form(ctx):
     from tests.closed_forms import layered_cells
     rng = np.random.default_rng(3)
