@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="clustered_128", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
-    ap.add_argument("--compare", default=None, choices=["fp64", "mixed", "none"],
+    ap.add_argument("--compare", default="mixed", choices=["fp64", "mixed", "none"],
                     help="also time the other precision path (default: the other one if built)")
     ap.add_argument("--cg-rtol", type=float, default=1e-3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

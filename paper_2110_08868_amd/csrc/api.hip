@@ -224,7 +224,8 @@ mak_status mak_laguerre_cells(mak_ctx* ctx, const double* points, const double* 
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->empty_cells = fs.empty;
-      info->overflow_cells = cs.retried;
+      info->overflow_cells = cs.retried - cs.fp64_rerun;
+      info->fp64_rerun_cells = cs.fp64_rerun;
       info->nnz = ctx->J.nnz;
       info->faces = ctx->nfaces;
       info->max_faces = int32_t(fs.max_faces);
@@ -289,7 +290,8 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
     set_psi_sorted(ps, psi_s, st);
     ClipStats cs = run_cells(ps, ctx->scp, o.precision, true, st);
     si.cell_passes = 1;
-    si.overflow_cells += cs.retried;
+    si.overflow_cells += cs.retried - cs.fp64_rerun;
+    si.fp64_rerun_cells += cs.fp64_rerun;
     FlagStats fs = flag_stats(ps, ctx->scp, ctx->tmp, st);
     if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
     build_csr(ps, ctx->scp, ctx->sJ, false, st);
@@ -316,7 +318,8 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
         ClipStats ct = run_cells(ps, ctx->scp_trial, o.precision, true, st, true);
         si.cell_passes += 1;
         si.ls_trials += 1;
-        si.overflow_cells += ct.retried;
+        si.overflow_cells += ct.retried - ct.fp64_rerun;
+        si.fp64_rerun_cells += ct.fp64_rerun;
         if (ct.overflow > 0) {  // cells beyond the polytope capacity: reject the trial
           alpha *= 0.5;
           continue;

@@ -48,6 +48,7 @@ struct ClipArgs {
   const int32_t* cell_start;
   const double* cell_psimax;
   const double* block_psimax;
+  const double* block_suffix;
   const double* gmax;
   int32_t Gn, Gb;
   double L, h;
@@ -68,7 +69,8 @@ struct ClipArgs {
   int32_t fslot;
   int32_t write_faces;
   double area_min;
-  double eps_rel;
+  double eps_rel;  // float64 tie tolerance (relative to the grid cell side)
+  double tol_rel;  // float32 ambiguity band (relative to |v||d| + |b|)
   unsigned long long* stats;  // optional work counters (see CLIP_STATS)
 };
 
@@ -77,20 +79,37 @@ struct ClipArgs {
 // vertices), box tests, final vertices, reported faces, cells.
 enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS, ST_N };
 
-template <int TPL>
+// Final vertices in float64 (the float32 path recomputes them from their
+// three planes before integrating; the float64 path integrates its own).
+template <typename R, int N>
+struct FinalCoords {
+  double x[N], y[N], z[N];
+};
+template <int N>
+struct FinalCoords<double, N> {};
+
+template <int TPL, typename R>
 struct ClipLDS {
-  static constexpr int PCAP = 64 * TPL;
+  // Live planes of a cell are few (faces plus recently cut-away planes): the
+  // table holds 64 (128 for the large kernel) and is compacted when full;
+  // vertices 64 * TPL.
+  static constexpr int PCAP = TPL <= 2 ? 64 : 128;
   static constexpr int TCAP = 64 * TPL;
-  double4 pl[PCAP];
+  double4 pl[PCAP];  // planes in float64 on both paths
   int32_t pj[PCAP];
   int32_t ps[PCAP];
   uint32_t stri[TCAP];
-  double sx[TCAP], sy[TCAP], sz[TCAP];
-  uint32_t bits[PCAP * PCAP / 32];
+  R sx[TCAP], sy[TCAP], sz[TCAP];
+  FinalCoords<R, TCAP> fin;
+  uint32_t bits[PCAP * PCAP / 32];   // directed dual edges of removed vertices
+  uint32_t mem[PCAP * TCAP / 32];    // plane -> vertex membership (integrals)
   uint32_t sbits[PCAP / 32];
   int32_t cstart[64];
   int32_t cpre[64];
   int32_t cshift[64];
+  double4 cand[64];   // planes of the current batch of sites (by lane)
+  int32_t candj[64];
+  int32_t cands[64];
 };
 
 __device__ __forceinline__ uint32_t tri_pack(int a, int b, int c) {
@@ -144,13 +163,19 @@ __device__ __forceinline__ void shell_offset(int r, int t, int& ox, int& oy, int
   oy = rem % I - (r - 1);
 }
 
-template <int TPL>
-__global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
-  constexpr int PCAP = ClipLDS<TPL>::PCAP;
-  constexpr int TCAP = ClipLDS<TPL>::TCAP;
+// The 27 neighbour cells (code = (ox+1)*9 + (oy+1)*3 + (oz+1)) by distance class.
+__constant__ int kNearOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1, 7, 19, 25, 3, 5, 21, 23,
+                                   9, 11, 15, 17, 0, 2, 6, 8, 18, 20, 24, 26};
+
+template <int TPL, typename R, bool STATS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_clip(ClipArgs A) {
+  constexpr bool kF64 = sizeof(R) == 8;
+  constexpr int PCAP = ClipLDS<TPL, R>::PCAP;
+  constexpr int TCAP = ClipLDS<TPL, R>::TCAP;
   constexpr int TW = TCAP / 32;   // words of one membership mask
   constexpr int PW = PCAP / 32;   // words of one bitmap row
-  __shared__ ClipLDS<TPL> S;
+  constexpr int NPC = (PCAP + 63) / 64;  // plane chunks of 64 lanes
+  __shared__ ClipLDS<TPL, R> S;
 
   const int lane = threadIdx.x;
   const int64_t blk = blockIdx.x;
@@ -165,11 +190,17 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
   const int cx = cell_coord(xi, h, Gn), cy = cell_coord(yi, h, Gn), cz = cell_coord(zi, h, Gn);
   const double gmax = *A.gmax;
   const double mtol = 1e-12 * L * L;
-  const double eps_rel = A.eps_rel;
 
   int32_t flags = 0;
   bool dead = false;
-  uint32_t c_cand = 0, c_test = 0, c_vt = 0, c_cut = 0, c_newv = 0, c_ball = 0, c_box = 0;
+  // work counters (compiled in only for the counting variant)
+  uint32_t c_cand = 0, c_test = 0, c_vt = 0, c_cut = 0, c_newv = 0, c_ball = 0, c_box = 0, c_pre = 0;
+#define CNT(stmt)  \
+  do {             \
+    if (STATS) {   \
+      stmt;        \
+    }              \
+  } while (0)
 
   // ---------------------------------------------------------------- box
   if (lane < 6) {
@@ -182,7 +213,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     S.ps[lane] = pack_shift(ax == 0 ? is : 0, ax == 1 ? is : 0, ax == 2 ? is : 0);
   }
   uint32_t tri[TPL];
-  double vx[TPL], vy[TPL], vz[TPL];
+  R vx[TPL], vy[TPL], vz[TPL];
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
     tri[k] = 0;
@@ -192,9 +223,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     const int px = lane & 1, py = 2 + ((lane >> 1) & 1), pz = 4 + ((lane >> 2) & 1);
     const int sx = (lane & 1) ? -1 : 1, sy = ((lane >> 1) & 1) ? -1 : 1, sz = ((lane >> 2) & 1) ? -1 : 1;
     tri[0] = (sx * sy * sz > 0) ? tri_pack(px, py, pz) : tri_pack(px, pz, py);
-    vx[0] = sx * 0.5 * L;
-    vy[0] = sy * 0.5 * L;
-    vz[0] = sz * 0.5 * L;
+    vx[0] = R(sx * 0.5 * L);
+    vy[0] = R(sy * 0.5 * L);
+    vz[0] = R(sz * 0.5 * L);
     S.stri[lane] = tri[0];
     S.sx[lane] = vx[0];
     S.sy[lane] = vy[0];
@@ -203,7 +234,15 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
   int nT = 8, nP = 6;
   float bcx = 0.f, bcy = 0.f, bcz = 0.f;
   float brho = float(0.8660254037844386 * L) * 1.0001f;
+  bool ball_dirty = false;
+  float rvert = float(0.8660254037844386 * L) * 1.0001f;  // max vertex distance from x_i
+  // tie tolerance of the vertex-side test: eps = eps_scale |d| (float64); the
+  // float32 path uses tol = tol_rel (rvert |d| + |b|) and treats any vertex
+  // with |u.d - b| <= tol as ambiguous (the cell is then re-run in float64)
+  const double eps_scale = A.eps_rel * h;
+  const R tol_rel = R(A.tol_rel);
   for (int w = lane; w < PCAP * PW; w += 64) S.bits[w] = 0u;
+  for (int w = lane; w < PCAP * (TCAP / 32); w += 64) S.mem[w] = 0u;
   if (lane < PW) S.sbits[lane] = 0u;
   __syncthreads();
 
@@ -231,23 +270,27 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       }
     }
     const float inv = 1.0f / float(nT);
-    sx = wave_sum_f(sx) * inv;
-    sy = wave_sum_f(sy) * inv;
-    sz = wave_sum_f(sz) * inv;
-    float r2 = 0.f;
+    // wave-uniform results are moved to scalar registers
+    sx = uniform_f(wave_sum_f(sx) * inv);
+    sy = uniform_f(wave_sum_f(sy) * inv);
+    sz = uniform_f(wave_sum_f(sz) * inv);
+    float r2 = 0.f, v2 = 0.f;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       if (k * 64 + lane < nT) {
         const float ex = float(vx[k]) - sx, ey = float(vy[k]) - sy, ez = float(vz[k]) - sz;
         r2 = fmaxf(r2, ex * ex + ey * ey + ez * ez);
+        v2 = fmaxf(v2, float(double(vx[k]) * vx[k] + double(vy[k]) * vy[k] + double(vz[k]) * vz[k]));
       }
     }
-    r2 = wave_max_f(r2);
+    r2 = uniform_f(wave_max_f(r2));
+    v2 = uniform_f(wave_max_f(v2));
     bcx = sx;
     bcy = sy;
     bcz = sz;
     const float cn = sqrtf(sx * sx + sy * sy + sz * sz);
     brho = sqrtf(r2) * 1.0001f + 1e-6f * (cn + float(h));
+    rvert = sqrtf(v2) * 1.0001f + 1e-6f * float(h);
   };
 
   // Drop the planes no vertex refers to any more (cut away by later planes)
@@ -264,18 +307,21 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       }
     }
     __syncthreads();
-    double4 cpl[TPL];
-    int32_t cj[TPL], cs[TPL], cnew[TPL];
-    bool calive[TPL];
+    double4 cpl[NPC];
+    int32_t cj[NPC], cs[NPC], cnew[NPC];
+    bool calive[NPC];
     int alive_total = 0;
 #pragma unroll
     for (int w = 0; w < PW; ++w) alive_total += __popc(S.sbits[w]);
 #pragma unroll
-    for (int c = 0; c < TPL; ++c) {
+    for (int c = 0; c < NPC; ++c) {
       const int f = c * 64 + lane;
       calive[c] = f < nP && ((S.sbits[f >> 5] >> (f & 31)) & 1u);
-      int below = __popc(S.sbits[f >> 5] & ((1u << (f & 31)) - 1u));
-      for (int w = 0; w < (f >> 5); ++w) below += __popc(S.sbits[w]);
+      int below = 0;
+      if (f < nP) {
+        below = __popc(S.sbits[f >> 5] & ((1u << (f & 31)) - 1u));
+        for (int w = 0; w < (f >> 5); ++w) below += __popc(S.sbits[w]);
+      }
       cnew[c] = below;
       if (calive[c]) {
         cpl[c] = S.pl[f];
@@ -285,7 +331,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < TPL; ++c) {
+    for (int c = 0; c < NPC; ++c) {
       if (calive[c]) {
         const int f = c * 64 + lane;
         S.pl[cnew[c]] = cpl[c];
@@ -306,28 +352,40 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     __syncthreads();
     for (int w = lane; w < PCAP; w += 64) S.bits[w] = 0u;
     if (lane < PW) S.sbits[lane] = 0u;
-    nP = alive_total;
+    nP = __builtin_amdgcn_readfirstlane(alive_total);
     __syncthreads();
   };
 
   // Clip by u . d <= bb (plane tag jj / ss).
-  auto clip_one = [&](double dx, double dy, double dz, double bb, int32_t jj, int32_t ss) {
-    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-    const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
-    if (cd + double(brho) * dn <= bb - mtol) return;  // cannot reach the ball
-    const double rb = sqrt(double(bcx) * bcx + double(bcy) * bcy + double(bcz) * bcz) + double(brho);
-    const double eps = eps_rel * dn * rb;
-    c_test += 1;
-    c_vt += uint32_t(nT);
+  auto clip_one = [&](double ddx, double ddy, double ddz, double dbb, int32_t jj, int32_t ss) {
+    const double dnd = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+    const double cd = double(bcx) * ddx + double(bcy) * ddy + double(bcz) * ddz;
+    if (cd + double(brho) * dnd <= dbb - mtol) return;  // cannot reach the ball
+    const R dx = R(ddx), dy = R(ddy), dz = R(ddz), bb = R(dbb);
+    // float64: out iff s > eps.  float32: out iff s > tol; |s| <= tol is
+    // ambiguous at this precision and sends the cell to the float64 kernel.
+    const R eps = kF64 ? R(eps_scale * dnd) : tol_rel * (R(rvert) * R(dnd) + fabs(bb));
+    CNT(c_test += 1);
+    CNT(c_vt += uint32_t(nT));
     uint64_t om[TPL];
     int nout = 0;
+    bool amb = false;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       bool out = false;
-      if (k == 0 || nT > k * 64)
-        out = (k * 64 + lane < nT) && (vx[k] * dx + vy[k] * dy + vz[k] * dz - bb > eps);
+      if (k == 0 || nT > k * 64) {
+        const bool valid = k * 64 + lane < nT;
+        const R sv = vx[k] * dx + vy[k] * dy + vz[k] * dz - bb;
+        out = valid && sv > eps;
+        if (!kF64) amb = amb || (valid && sv > -eps && sv <= eps);
+      }
       om[k] = ballot(out);
       nout += __popcll(om[k]);
+    }
+    if (!kF64 && ballot(amb)) {
+      flags |= CF_NEARDEG;
+      dead = true;
+      return;
     }
     if (nout == 0) return;
     if (nout == nT) {
@@ -345,7 +403,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     }
     const int pn = nP;
     if (lane == 0) {
-      S.pl[pn] = make_double4(dx, dy, dz, bb);
+      S.pl[pn] = make_double4(ddx, ddy, ddz, dbb);
       S.pj[pn] = jj;
       S.ps[pn] = ss;
     }
@@ -404,14 +462,14 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     int mynew = 0;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) mynew += __popc(bm[k]);
-    const int nTn = nkept + wave_sum_i(mynew);
+    const int nTn = __builtin_amdgcn_readfirstlane(nkept + wave_sum_i(mynew));
     if (nTn > TCAP) {
       flags |= CF_CAPACITY;
       dead = true;
       return;
     }
     // 4. compaction: kept triangles first (slot order), then the new ones
-    const double4 Pn = make_double4(dx, dy, dz, bb);
+    const double4 Pn = make_double4(ddx, ddy, ddz, dbb);
     int krun = 0, nrun = 0;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -432,12 +490,13 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       nrun += __popcll(b0) + 2 * __popcll(b1);
       if (bm[k]) {
         const int st[3] = {tri_a(tri[k]), tri_b(tri[k]), tri_c(tri[k])};
-#pragma unroll
+#pragma unroll 1
         for (int e = 0; e < 3; ++e) {
           if (bm[k] & (1 << e)) {
             const int x = st[e], y = st[(e + 1) % 3];
             const double4 P1 = S.pl[x], P2 = S.pl[y];
-            // intersection of planes x, y, pn (Cramer's rule)
+            // intersection of planes x, y, pn (Cramer's rule, float64 on both
+            // paths; the float32 path stores the vertex rounded)
             const double c23x = P2.y * Pn.z - P2.z * Pn.y, c23y = P2.z * Pn.x - P2.x * Pn.z,
                          c23z = P2.x * Pn.y - P2.y * Pn.x;
             const double c31x = Pn.y * P1.z - Pn.z * P1.y, c31y = Pn.z * P1.x - Pn.x * P1.z,
@@ -456,9 +515,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       }
     }
     __syncthreads();
-    c_cut += 1;
-    c_newv += uint32_t(nTn - nkept);
-    c_ball += uint32_t(nTn);
+    CNT(c_cut += 1);
+    CNT(c_newv += uint32_t(nTn - nkept));
+    CNT(c_ball += uint32_t(nTn));
     nT = nTn;
     nP = pn + 1;
 #pragma unroll
@@ -473,7 +532,14 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
         tri[k] = 0;
       }
     }
-    update_ball();
+    ball_dirty = true;  // the ball is refreshed lazily (a stale ball is still a bound)
+  };
+
+  auto refresh_ball = [&]() {
+    if (ball_dirty) {
+      update_ball();
+      ball_dirty = false;
+    }
   };
 
   // Could a site with weight <= wmax inside the seed-local box [lo, hi] cut
@@ -509,7 +575,8 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     __syncthreads();
     for (int base = 0; base < total && !dead; base += 64) {
       const int t = base + lane;
-      c_cand += uint32_t(min(64, total - base));
+      CNT(c_cand += uint32_t(min(64, total - base)));
+      refresh_ball();
       int lo = 0, hi = ncl - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -517,7 +584,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       }
       const int q = S.cstart[lo] + (t - S.cpre[lo]);
       const int32_t shv = S.cshift[lo];
-      double dx = 0, dy = 0, dz = 0, bb = 0;
+      double dx = 0, dy = 0, dz = 0, bb = 0, dn = 0;
       bool may = false, coinc = false;
       uint32_t key = 0xffffffffu;
       if (t < total && q != p) {
@@ -530,40 +597,58 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
           coinc = true;
         } else {
           bb = 0.5 * d2 + wi - P.w;
-          const double dn = sqrt(d2);
+          dn = sqrt(d2);
           const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
           may = cd + double(brho) * dn > bb - mtol;
           if (may) key = (float_key(float((bb - cd) / dn)) & ~63u) | uint32_t(lane);
         }
       }
       if (ballot(coinc)) flags |= CF_COINCIDENT;
-      const int ns = __popcll(ballot(may));
+      int ns = __popcll(ballot(may));
       if (ns == 0) continue;
+      // the plane in the working precision (seed-local, so float32 keeps the
+      // relative precision of |d|)
+      const R rx = R(dx), ry = R(dy), rz = R(dz), rbb = R(bb);
+      if (ns > 2) {
+        // Exact filter, one candidate per lane against every current vertex
+        // (LDS broadcast reads).  A plane that removes no vertex now cannot
+        // remove one from any later, smaller polytope.  (float32: planes with
+        // a vertex within the ambiguity band are kept for the serial test.)
+        const R eps = kF64 ? R(eps_scale * dn) : -tol_rel * (R(rvert) * R(dn) + fabs(rbb));
+        bool cut = false;
+#pragma unroll 1
+        for (int v = 0; v < nT; ++v) {
+          const R ux = S.sx[v], uy = S.sy[v], uz = S.sz[v];
+          cut |= ux * rx + uy * ry + uz * rz - rbb > eps;
+        }
+        CNT(c_pre += uint32_t(nT));
+        may = may && cut;
+        if (!may) key = 0xffffffffu;
+        ns = __popcll(ballot(may));
+        if (ns == 0) continue;
+      }
       key = wave_sort_u32(key);
+      // park the batch in LDS: the serial loop reads one plane at a time
+      S.cand[lane] = make_double4(dx, dy, dz, bb);
+      S.candj[lane] = q;
+      S.cands[lane] = shv;
+      __syncthreads();
       for (int r = 0; r < ns && !dead; ++r) {
         const int src = int(readlane_u(key, r) & 63u);
-        clip_one(readlane_d(dx, src), readlane_d(dy, src), readlane_d(dz, src),
-                 readlane_d(bb, src), readlane_i(q, src), readlane_i(shv, src));
+        const double4 C = S.cand[src];
+        clip_one(C.x, C.y, C.z, C.w, S.candj[src], S.cands[src]);
       }
+      __syncthreads();
     }
     __syncthreads();
   };
 
-  // ---------------------------------------------------------------- phase A
-  {
-    const bool act = lane < 27;
-    const int ux = cx + lane / 9 - 1, uy = cy + (lane / 3) % 3 - 1, uz = cz + lane % 3 - 1;
-    const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
-    int32_t st = 0, cnt = 0;
-    if (act) {
-      const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
-      st = A.cell_start[g];
-      cnt = A.cell_start[g + 1] - st;
-    }
-    process_list(act, st, cnt, pack_shift(sx, sy, sz));
-  }
-
-  // ---------------------------------------------------------------- phase B
+  // ---------------------------------------------------------------- candidates
+  // A generator yields lists of neighbour-grid cells (one per lane) to one
+  // call site of process_list: first the 27 cells around the site (nearest
+  // first), then the 98 cells of the second ring, then the surviving blocks
+  // of Chebyshev shells of 4^3-cell blocks (cells already visited skipped),
+  // until what is left lies beyond the reach R + sqrt(R^2 + 2 (psi_max - psi_i)).
   {
     const int bx0 = cx >> 2, by0 = cy >> 2, bz0 = cz >> 2;
     const double bh = BLOCK_SIDE * h;
@@ -571,70 +656,154 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
                      fmin(fmin(yi - by0 * bh, (by0 + 1) * bh - yi), fmin(zi - bz0 * bh, (bz0 + 1) * bh - zi)));
     mb = fmax(mb, 0.0);
     const int rb_max = 4 * Gb + 4;
-    for (int rb = 0; !dead; ++rb) {
-      if (rb >= 1) {
-        const double dlb = (rb - 1) * bh + mb - 1e-12 * L;
-        const double R = sqrt(double(bcx) * bcx + double(bcy) * bcy + double(bcz) * bcz) + double(brho);
-        const double Rs = R + sqrt(R * R + 2.0 * fmax(0.0, gmax - wi));
-        if (dlb >= Rs) break;
-        if (rb > rb_max) {
-          flags |= CF_CAPACITY;
-          dead = true;
-          break;
-        }
+    // distance from the site to the faces of its own grid cell (cell units)
+    double mc = fmin(fmin(xi / h - cx, cx + 1 - xi / h),
+                     fmin(fmin(yi / h - cy, cy + 1 - yi / h), fmin(zi / h - cz, cz + 1 - zi / h)));
+    mc = fmax(mc, 0.0);
+    // Reach of the polytope for sites of weight <= w: the bisector with such
+    // a site at distance t from x_i lies at distance >= t/2 - (w - psi_i)/t
+    // from x_i, beyond every vertex once t >= R + sqrt(R^2 + 2 (w - psi_i)),
+    // R = the largest vertex distance from x_i.
+    auto reach_w = [&](double w) {
+      const double Rv = double(rvert);
+      return Rv + sqrt(Rv * Rv + 2.0 * fmax(0.0, w - wi));
+    };
+    const double* bsuf = A.block_suffix + block_key(bx0, by0, bz0, Gb) * (SHELL_MAX + 1);
+    // sites in blocks farther than SHELL_MAX block shells (bounded by the
+    // global maximum weight) are out of reach
+    auto far_ok = [&]() { return SHELL_MAX * bh + mb - 1e-12 * L >= reach_w(gmax); };
+    // Every site at distance >= t from x_i that lies in a block of shell
+    // >= r is out of reach: the sites of shell q are farther than
+    // max(t, (q - 1) bh + mb) and weigh at most bsuf[q] (the shell's maximum).
+    auto beyond = [&](double t, int r) {
+      for (int q = r; q <= SHELL_MAX; ++q) {
+        const double dq = fmax(t, q >= 1 ? (q - 1) * bh + mb : 0.0);
+        if (dq - 1e-12 * L < reach_w(bsuf[q])) return false;
       }
-      const int S1 = 2 * rb + 1, I1 = 2 * rb - 1;
-      const int count = rb == 0 ? 1 : S1 * S1 * S1 - I1 * I1 * I1;
-      for (int base = 0; base < count && !dead; base += 64) {
-        const int t = base + lane;
-        c_box += uint32_t(min(64, count - base));
-        bool ok = false;
-        int ubx = 0, uby = 0, ubz = 0;
-        if (t < count) {
-          int ox, oy, oz;
-          shell_offset(rb, t, ox, oy, oz);
-          ubx = bx0 + ox;
-          uby = by0 + oy;
-          ubz = bz0 + oz;
-          const int wbx = ubx - floor_div(ubx, Gb) * Gb, wby = uby - floor_div(uby, Gb) * Gb,
-                    wbz = ubz - floor_div(ubz, Gb) * Gb;
-          const double lx = ubx * bh - xi - 1e-12 * L, ly = uby * bh - yi - 1e-12 * L,
-                       lz = ubz * bh - zi - 1e-12 * L;
-          const double hx = lx + bh + 2e-12 * L, hy = ly + bh + 2e-12 * L, hz = lz + bh + 2e-12 * L;
-          ok = box_may_cut(lx, ly, lz, hx, hy, hz, A.block_psimax[block_key(wbx, wby, wbz, Gb)]);
+      return far_ok();
+    };
+    int phase = 0;  // 0: 27 cells, 1 and 2: ring 2 of cells, 3: block shells
+    int rb = 0, gbase = 0, gcount = 1;
+    uint64_t bmask = 0;
+    int ubx = 0, uby = 0, ubz = 0;
+    while (!dead) {
+      bool act = false;
+      int32_t st = 0, cnt = 0, shp = 0;
+      if (phase == 1 || phase == 2) {
+        // ring 2 of grid cells (98 cells, two lists), after a reach check
+        if (phase == 1) {
+          refresh_ball();
+          if (beyond((1.0 + mc) * h, 0)) break;
         }
-        uint64_t bmask = ballot(ok);
-        while (bmask && !dead) {
-          const int l = __ffsll((unsigned long long)bmask) - 1;
-          bmask &= bmask - 1;
-          const int qbx = readlane_i(ubx, l), qby = readlane_i(uby, l), qbz = readlane_i(ubz, l);
-          c_box += 64;
-          const int ux = qbx * BLOCK_SIDE + (lane >> 4), uy = qby * BLOCK_SIDE + ((lane >> 2) & 3),
-                    uz = qbz * BLOCK_SIDE + (lane & 3);
-          const bool inA = abs(ux - cx) <= 1 && abs(uy - cy) <= 1 && abs(uz - cz) <= 1;
-          const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+        const int t = (phase == 1 ? 0 : 64) + lane;
+        phase += 1;
+        act = t < 98;
+        int ox = 0, oy = 0, oz = 0;
+        if (act) shell_offset(2, t, ox, oy, oz);
+        const int ux = cx + ox, uy = cy + oy, uz = cz + oz;
+        const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+        if (act) {
           const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
-          const int32_t st = A.cell_start[g];
-          const int32_t cnt = A.cell_start[g + 1] - st;
-          bool act = !inA && cnt > 0;
+          st = A.cell_start[g];
+          cnt = A.cell_start[g + 1] - st;
+          act = cnt > 0;
           if (act) {
             const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
                          lz = uz * h - zi - 1e-12 * L;
             act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L,
                               A.cell_psimax[g]);
           }
-          process_list(act, st, cnt, pack_shift(sx, sy, sz));
         }
+        CNT(c_box += 64);
+        shp = pack_shift(sx, sy, sz);
+      } else if (phase == 0) {
+        phase = 1;
+        act = lane < 27;
+        const int code = act ? kNearOrder[lane] : 13;
+        const int ux = cx + code / 9 - 1, uy = cy + (code / 3) % 3 - 1, uz = cz + code % 3 - 1;
+        const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+        if (act) {
+          const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
+          st = A.cell_start[g];
+          cnt = A.cell_start[g + 1] - st;
+        }
+        shp = pack_shift(sx, sy, sz);
+      } else {
+        if (rb == 0 && gbase == 0) {
+          refresh_ball();
+          if (beyond((2.0 + mc) * h, 0)) break;  // ring 3 out of reach
+        }
+        // next surviving block (advancing batches and shells as needed)
+        bool done = false;
+        while (!bmask && !done) {
+          refresh_ball();
+          if (gbase >= gcount) {
+            ++rb;
+            if (beyond((rb - 1) * bh + mb, rb)) {
+              done = true;
+              break;
+            }
+            if (rb > rb_max) {
+              flags |= CF_CAPACITY;
+              dead = true;
+              done = true;
+              break;
+            }
+            const int S1 = 2 * rb + 1, I1 = 2 * rb - 1;
+            gcount = S1 * S1 * S1 - I1 * I1 * I1;
+            gbase = 0;
+          }
+          const int t = gbase + lane;
+          CNT(c_box += uint32_t(min(64, gcount - gbase)));
+          gbase += 64;
+          bool ok = false;
+          if (t < gcount) {
+            int ox, oy, oz;
+            shell_offset(rb, t, ox, oy, oz);
+            ubx = bx0 + ox;
+            uby = by0 + oy;
+            ubz = bz0 + oz;
+            const int wbx = ubx - floor_div(ubx, Gb) * Gb, wby = uby - floor_div(uby, Gb) * Gb,
+                      wbz = ubz - floor_div(ubz, Gb) * Gb;
+            const double lx = ubx * bh - xi - 1e-12 * L, ly = uby * bh - yi - 1e-12 * L,
+                         lz = ubz * bh - zi - 1e-12 * L;
+            const double hx = lx + bh + 2e-12 * L, hy = ly + bh + 2e-12 * L, hz = lz + bh + 2e-12 * L;
+            ok = box_may_cut(lx, ly, lz, hx, hy, hz, A.block_psimax[block_key(wbx, wby, wbz, Gb)]);
+          }
+          bmask = ballot(ok);
+        }
+        if (done) break;
+        refresh_ball();
+        const int l = __ffsll((unsigned long long)bmask) - 1;
+        bmask &= bmask - 1;
+        const int qbx = readlane_i(ubx, l), qby = readlane_i(uby, l), qbz = readlane_i(ubz, l);
+        CNT(c_box += 64);
+        const int ux = qbx * BLOCK_SIDE + (lane >> 4), uy = qby * BLOCK_SIDE + ((lane >> 2) & 3),
+                  uz = qbz * BLOCK_SIDE + (lane & 3);
+        const bool inA = abs(ux - cx) <= 2 && abs(uy - cy) <= 2 && abs(uz - cz) <= 2;
+        const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+        const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
+        st = A.cell_start[g];
+        cnt = A.cell_start[g + 1] - st;
+        act = !inA && cnt > 0;
+        if (act) {
+          const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
+                       lz = uz * h - zi - 1e-12 * L;
+          act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L,
+                            A.cell_psimax[g]);
+        }
+        shp = pack_shift(sx, sy, sz);
       }
+      process_list(act, st, cnt, shp);
     }
   }
 
   auto flush_stats = [&](int ntri, int nfaces) {
-    if (A.stats && lane == 0) {
+    if (STATS && A.stats && lane == 0) {
       unsigned long long* st = A.stats;
       atomicAdd(&st[ST_CAND], (unsigned long long)c_cand);
       atomicAdd(&st[ST_TEST], (unsigned long long)c_test);
-      atomicAdd(&st[ST_VTEST], (unsigned long long)c_vt);
+      atomicAdd(&st[ST_VTEST], (unsigned long long)(c_vt + c_pre));
       atomicAdd(&st[ST_CUT], (unsigned long long)c_cut);
       atomicAdd(&st[ST_NEWV], (unsigned long long)c_newv);
       atomicAdd(&st[ST_BALL], (unsigned long long)c_ball);
@@ -648,8 +817,8 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
   if (dead) {
     flush_stats(0, 0);
     if (lane == 0) {
-      if (flags & (CF_CAPACITY | CF_NONMANIFOLD)) {
-        atomicAdd(&A.cause[(flags & CF_CAPACITY) ? 0 : 1], 1ull);
+      if (flags & (CF_CAPACITY | CF_NONMANIFOLD | CF_NEARDEG)) {
+        atomicAdd(&A.cause[(flags & CF_CAPACITY) ? 0 : ((flags & CF_NONMANIFOLD) ? 1 : 2)], 1ull);
         const unsigned long long r = atomicAdd(A.retry_count, 1ull);
         A.retry[r] = p;
       }
@@ -662,6 +831,49 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
   }
 
   // ---------------------------------------------------------------- integrals
+  auto plane_d = [&](int f) -> double4 { return S.pl[f]; };
+  // final vertices in float64
+  double fvx[TPL], fvy[TPL], fvz[TPL];
+  double* FX;
+  double* FY;
+  double* FZ;
+  if constexpr (kF64) {
+    FX = S.sx;
+    FY = S.sy;
+    FZ = S.sz;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      fvx[k] = vx[k];
+      fvy[k] = vy[k];
+      fvz[k] = vz[k];
+    }
+  } else {
+    FX = S.fin.x;
+    FY = S.fin.y;
+    FZ = S.fin.z;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      fvx[k] = fvy[k] = fvz[k] = 0.0;
+      const int slot = k * 64 + lane;
+      if (slot < nT) {
+        const double4 P1 = plane_d(tri_a(tri[k])), P2 = plane_d(tri_b(tri[k])),
+                      P3 = plane_d(tri_c(tri[k]));
+        const double c23x = P2.y * P3.z - P2.z * P3.y, c23y = P2.z * P3.x - P2.x * P3.z,
+                     c23z = P2.x * P3.y - P2.y * P3.x;
+        const double c31x = P3.y * P1.z - P3.z * P1.y, c31y = P3.z * P1.x - P3.x * P1.z,
+                     c31z = P3.x * P1.y - P3.y * P1.x;
+        const double c12x = P1.y * P2.z - P1.z * P2.y, c12y = P1.z * P2.x - P1.x * P2.z,
+                     c12z = P1.x * P2.y - P1.y * P2.x;
+        const double inv = 1.0 / (P1.x * c23x + P1.y * c23y + P1.z * c23z);
+        fvx[k] = (P1.w * c23x + P2.w * c31x + P3.w * c12x) * inv;
+        fvy[k] = (P1.w * c23y + P2.w * c31y + P3.w * c12y) * inv;
+        fvz[k] = (P1.w * c23z + P2.w * c31z + P3.w * c12z) * inv;
+        FX[slot] = fvx[k];
+        FY[slot] = fvy[k];
+        FZ[slot] = fvz[k];
+      }
+    }
+  }
   // membership masks: bit t of mask f is set when triangle t contains plane f
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
@@ -669,9 +881,9 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     if (slot < nT) {
       const uint32_t bit = 1u << (slot & 31);
       const int w = slot >> 5;
-      atomicOr(&S.bits[tri_a(tri[k]) * TW + w], bit);
-      atomicOr(&S.bits[tri_b(tri[k]) * TW + w], bit);
-      atomicOr(&S.bits[tri_c(tri[k]) * TW + w], bit);
+      atomicOr(&S.mem[tri_a(tri[k]) * TW + w], bit);
+      atomicOr(&S.mem[tri_b(tri[k]) * TW + w], bit);
+      atomicOr(&S.mem[tri_c(tri[k]) * TW + w], bit);
     }
   }
   __syncthreads();
@@ -690,7 +902,7 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
       int tw = -1;
 #pragma unroll
       for (int w = 0; w < TW; ++w) {
-        uint32_t m = S.bits[f * TW + w] & S.bits[pr * TW + w];
+        uint32_t m = S.mem[f * TW + w] & S.mem[pr * TW + w];
         if (w == (slot >> 5)) m &= ~(1u << (slot & 31));
         if (m && tw < 0) tw = w * 32 + __ffs(int(m)) - 1;
       }
@@ -698,25 +910,25 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
         broken = true;
         continue;
       }
-      const double tx = S.sx[tw], ty = S.sy[tw], tz = S.sz[tw];
-      const double4 P = S.pl[f];
+      const double tx = FX[tw], ty = FY[tw], tz = FZ[tw];
+      const double4 P = plane_d(f);
       const double nn = P.x * P.x + P.y * P.y + P.z * P.z;
       // fan apex: the lowest-slot vertex of face f (on the plane, close to
       // the face, so small faces keep their relative precision)
       int t0 = 0;
 #pragma unroll
       for (int w = TW - 1; w >= 0; --w) {
-        const uint32_t m = S.bits[f * TW + w];
+        const uint32_t m = S.mem[f * TW + w];
         if (m) t0 = w * 32 + __ffs(int(m)) - 1;
       }
-      const double px = S.sx[t0], py = S.sy[t0], pz = S.sz[t0];
-      const double det = px * (vy[k] * tz - vz[k] * ty) + py * (vz[k] * tx - vx[k] * tz) +
-                         pz * (vx[k] * ty - vy[k] * tx);
+      const double px = FX[t0], py = FY[t0], pz = FZ[t0];
+      const double det = px * (fvy[k] * tz - fvz[k] * ty) + py * (fvz[k] * tx - fvx[k] * tz) +
+                         pz * (fvx[k] * ty - fvy[k] * tx);
       v6 += det;
-      m0 += det * (px + vx[k] + tx);
-      m1 += det * (py + vy[k] + ty);
-      m2 += det * (pz + vz[k] + tz);
-      const double ax = vx[k] - px, ay = vy[k] - py, az = vz[k] - pz;
+      m0 += det * (px + fvx[k] + tx);
+      m1 += det * (py + fvy[k] + ty);
+      m2 += det * (pz + fvz[k] + tz);
+      const double ax = fvx[k] - px, ay = fvy[k] - py, az = fvz[k] - pz;
       const double bx = tx - px, by = ty - py, bz = tz - pz;
       const double crx = ay * bz - az * by, cry = az * bx - ax * bz, crz = ax * by - ay * bx;
       ar[k][e] = 0.5 * (crx * P.x + cry * P.y + crz * P.z) / sqrt(nn);
@@ -732,30 +944,30 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
   for (int k = 0; k < TPL; ++k) {
     const int slot = k * 64 + lane;
     if (slot < nT) {
-      S.sx[slot] = ar[k][0];
-      S.sy[slot] = ar[k][1];
-      S.sz[slot] = ar[k][2];
+      FX[slot] = ar[k][0];
+      FY[slot] = ar[k][1];
+      FZ[slot] = ar[k][2];
     }
   }
   __syncthreads();
   // per-face areas: one lane per plane (faces of the own-image box, tagged
   // j < 0, are not faces of J)
-  double Af[TPL];
+  double Af[NPC];
   int nf = 0;
 #pragma unroll
-  for (int c = 0; c < TPL; ++c) {
+  for (int c = 0; c < NPC; ++c) {
     const int f = c * 64 + lane;
     double a = 0.0;
     const bool real = f < nP && S.pj[f] >= 0;
     if (real) {
 #pragma unroll
       for (int w = 0; w < TW; ++w) {
-        uint32_t m = S.bits[f * TW + w];
+        uint32_t m = S.mem[f * TW + w];
         while (m) {
           const int t = w * 32 + __ffs(int(m)) - 1;
           m &= m - 1;
           const uint32_t tr = S.stri[t];
-          a += tri_a(tr) == f ? S.sx[t] : (tri_b(tr) == f ? S.sy[t] : S.sz[t]);
+          a += tri_a(tr) == f ? FX[t] : (tri_b(tr) == f ? FY[t] : FZ[t]);
         }
       }
     }
@@ -778,12 +990,12 @@ __global__ __launch_bounds__(64) void k_clip(ClipArgs A) {
     }
     int run = 0;
 #pragma unroll
-    for (int c = 0; c < TPL; ++c) {
+    for (int c = 0; c < NPC; ++c) {
       const int f = c * 64 + lane;
       const bool rep = Af[c] > 0.0;
       const uint64_t rm = ballot(rep);
       if (rep && dst) {
-        const double4 P = S.pl[f];
+        const double4 P = plane_d(f);
         FaceRec fr;
         fr.j = S.pj[f];
         fr.shift = S.ps[f];
@@ -822,7 +1034,7 @@ double clip_bytes(const unsigned long long* c) {
   return 72.0 * c[ST_CELLS] + 24.0 * c[ST_FACES];
 }
 
-template <int TPL>
+template <int TPL, typename R>
 void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
   Profiler* pr = g_prof;
   const bool counting = pr && pr->counting;
@@ -830,8 +1042,12 @@ void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
     a.stats = out.counters.as<unsigned long long>() + 4;
     MAK_HIP(hipMemsetAsync(a.stats, 0, ST_N * sizeof(unsigned long long), st));
   }
-  ProfScope ps(TPL == 2 ? "clip" : "clip_large", st, double(items));
-  hipLaunchKernelGGL(k_clip<TPL>, dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
+  const char* name = sizeof(R) == 4 ? "clip_f32" : (TPL == 2 ? "clip" : "clip_large");
+  ProfScope ps(name, st, double(items));
+  if (counting)
+    hipLaunchKernelGGL((k_clip<TPL, R, true>), dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_clip<TPL, R, false>), dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
   MAK_HIP(hipGetLastError());
   if (counting) {
     unsigned long long c[ST_N];
@@ -849,37 +1065,43 @@ void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
 
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
                     bool tolerate_failure) {
-  (void)precision;
   const int64_t N = ps.N;
   out.fslot = N <= (int64_t(1) << 24) ? 32 : 20;
   out.vol.ensure(size_t(N) * sizeof(double));
   out.mom.ensure(size_t(N) * 3 * sizeof(double));
   out.cflags.ensure(size_t(N) * sizeof(int32_t));
   out.nface.ensure(size_t(N) * sizeof(int32_t));
-  out.retry.ensure(size_t(N) * 2 * sizeof(int32_t));
-  out.counters.ensure(32 * sizeof(unsigned long long));
+  out.retry.ensure(size_t(N) * 3 * sizeof(int32_t));
+  out.counters.ensure(64 * sizeof(unsigned long long));
   if (faces) {
     out.faces.ensure(size_t(N) * out.fslot * sizeof(FaceRec));
     out.fbase.ensure(size_t(N) * sizeof(int64_t));
     if (out.ovf_cap < 4096 + N / 8) out.ovf_cap = 4096 + N / 8;
     out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
   }
+  // Stages: every cell runs in the first kernel; the cells it could not
+  // finish (capacity, inconsistent cut, float32 ambiguity) go to the next.
+  //   float64: <2 vertices per lane, f64>  ->  <4, f64, wider tie tolerance>
+  //   mixed:   <2, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
+  const bool mixed = precision == MAK_MIXED;
+  const int nstage = mixed ? 3 : 2;
+  unsigned long long* ctr = out.counters.as<unsigned long long>();
+  // counters: [0] overflow faces used, [1 + s] cells listed by stage s,
+  // [4..13] work counters, [16 + 3 s ..] causes (capacity, cut, ambiguity)
   ClipStats cs;
   for (int attempt = 0; attempt < 3; ++attempt) {
-    MAK_HIP(hipMemsetAsync(out.counters.p, 0, 32 * sizeof(unsigned long long), st));
+    MAK_HIP(hipMemsetAsync(out.counters.p, 0, 64 * sizeof(unsigned long long), st));
     ClipArgs a{};
     a.pts = ps.pts.as<double4>();
     a.cell_start = ps.cell_start.as<int32_t>();
     a.cell_psimax = ps.cell_psimax.as<double>();
     a.block_psimax = ps.block_psimax.as<double>();
+    a.block_suffix = ps.block_suffix.as<double>();
     a.gmax = ps.scal.as<double>();
     a.Gn = ps.g.Gn;
     a.Gb = ps.g.Gb;
     a.L = ps.g.L;
     a.h = ps.g.h;
-    a.work = nullptr;
-    a.nwork = N;
-    a.per_xcd = ceil_div(N, 8);
     a.vol = out.vol.as<double>();
     a.mom = out.mom.as<double>();
     a.cflags = out.cflags.as<int32_t>();
@@ -887,54 +1109,54 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
     a.faces = faces ? out.faces.as<FaceRec>() : nullptr;
     a.fbase = faces ? out.fbase.as<int64_t>() : nullptr;
     a.ovf = faces ? out.ovf.as<FaceRec>() : nullptr;
-    a.ovf_used = out.counters.as<unsigned long long>();
-    a.retry_count = out.counters.as<unsigned long long>() + 1;
-    a.cause = out.counters.as<unsigned long long>() + 16;
-    a.retry = out.retry.as<int32_t>();
+    a.ovf_used = ctr;
     a.ovf_cap = faces ? out.ovf_cap : 0;
     a.fslot = out.fslot;
     a.write_faces = faces ? 1 : 0;
     const double spacing = ps.g.L / std::cbrt(double(N));
     a.area_min = 1e-12 * spacing * spacing;
-    a.eps_rel = 1e-13;
+    a.tol_rel = 1e-6;
     a.stats = nullptr;
-    launch_clip<2>(a, out, N, st);
-    unsigned long long hc[4];
-    MAK_HIP(hipMemcpyAsync(hc, out.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
-    MAK_HIP(hipStreamSynchronize(st));
-    if (faces && int64_t(hc[0]) > out.ovf_cap) {
-      out.ovf_cap = int64_t(hc[0]) * 2 + 4096;
-      out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
-      continue;
-    }
-    cs.retried = int64_t(hc[1]);
-    if (hc[1] > 0) {
-      // Large-capacity kernel with a wider tie tolerance on the listed cells.
-      a.work = out.retry.as<int32_t>();
-      a.nwork = int64_t(hc[1]);
-      a.per_xcd = ceil_div(a.nwork, 8);
-      a.retry_count = out.counters.as<unsigned long long>() + 2;
-      a.cause = out.counters.as<unsigned long long>() + 18;
-      a.retry = out.retry.as<int32_t>() + a.nwork;  // failures land after the list
-      a.eps_rel = 1e-11;
-      launch_clip<4>(a, out, a.nwork, st);
-      MAK_HIP(hipMemcpyAsync(hc, out.counters.p, sizeof(hc), hipMemcpyDeviceToHost, st));
+    int64_t listed = N;  // cells of the current stage
+    bool regrow = false;
+    cs = ClipStats();
+    for (int stg = 0; stg < nstage && listed > 0; ++stg) {
+      a.work = stg == 0 ? nullptr : out.retry.as<int32_t>() + (stg - 1) * N;
+      a.nwork = listed;
+      a.per_xcd = ceil_div(listed, 8);
+      a.retry = out.retry.as<int32_t>() + stg * N;
+      a.retry_count = ctr + 1 + stg;
+      a.cause = ctr + 16 + 3 * stg;
+      const bool last = stg == nstage - 1;
+      a.eps_rel = last ? 1e-11 : 1e-13;
+      if (mixed && stg == 0)
+        launch_clip<2, float>(a, out, listed, st);
+      else if (!last)
+        launch_clip<2, double>(a, out, listed, st);
+      else
+        launch_clip<4, double>(a, out, listed, st);
+      unsigned long long hc[4];
+      MAK_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
       MAK_HIP(hipStreamSynchronize(st));
       if (faces && int64_t(hc[0]) > out.ovf_cap) {
         out.ovf_cap = int64_t(hc[0]) * 2 + 4096;
         out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
-        continue;
+        regrow = true;
+        break;
       }
-      if (hc[2] > 0) {
-        cs.overflow = int64_t(hc[2]);
+      listed = int64_t(hc[1 + stg]);
+      if (stg == 0) cs.retried = listed;
+      if (mixed && stg == 0) cs.fp64_rerun = listed;
+      if (last && listed > 0) {
+        cs.overflow = listed;
         if (tolerate_failure) return cs;
-        unsigned long long cz[2];
-        MAK_HIP(hipMemcpy(cz, out.counters.as<unsigned long long>() + 18, sizeof(cz),
-                          hipMemcpyDeviceToHost));
+        unsigned long long cz[3];
+        MAK_HIP(hipMemcpy(cz, ctr + 16 + 3 * stg, sizeof(cz), hipMemcpyDeviceToHost));
         MAK_FAIL(MAK_EOVERFLOW, std::to_string(cz[0]) + " cells exceeded the polytope capacity, " +
                                     std::to_string(cz[1]) + " had inconsistent cuts");
       }
     }
+    if (regrow) continue;
     return cs;
   }
   MAK_FAIL(MAK_ENOMEM, "face overflow buffer could not be sized");

@@ -59,6 +59,12 @@ __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int l) {
   return (uint64_t(hi) << 32) | lo;
 }
 
+// A value known to be equal on every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Butterfly reductions over the 64 lanes (fixed order: deterministic).
 __device__ __forceinline__ float wave_sum_f(float v) {
 #pragma unroll

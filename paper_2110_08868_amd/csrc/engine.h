@@ -56,6 +56,7 @@ enum : int32_t {
 };
 
 constexpr int BLOCK_SIDE = 4;  // neighbour-grid cells per block side
+constexpr int SHELL_MAX = 6;   // block shells covered by the per-block weight bounds
 
 struct GridDesc {
   int32_t Gn = 0;   // cells per axis (multiple of BLOCK_SIDE)
@@ -77,6 +78,8 @@ struct PointSet {
   DevBuf cell_start;   // int32 [G + 1]
   DevBuf cell_psimax;  // double [G]
   DevBuf block_psimax; // double [GB]
+  DevBuf block_suffix; // double [GB * (SHELL_MAX + 1)]: max weight over the blocks at
+                       // Chebyshev block distance exactly r from each block
   DevBuf scal;         // double [8]: [0] global psi max, [1] global psi min
   DevBuf key, rank, count, status, tmp;  // build temporaries
 };
@@ -117,7 +120,7 @@ void update_psi_bounds(PointSet& ps, hipStream_t st);
 
 // --- clip.hip
 struct ClipStats {
-  int64_t retried = 0, overflow = 0, nonmanifold = 0, empty = 0, coincident = 0, neardeg = 0;
+  int64_t retried = 0, overflow = 0, fp64_rerun = 0;
 };
 // Full cell pass at the psi stored in ps.pts[].w.  precision: MAK_FP64 or
 // MAK_MIXED.  Throws on capacity overflow past the large kernel.

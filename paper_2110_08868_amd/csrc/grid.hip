@@ -111,6 +111,30 @@ __global__ __launch_bounds__(64) void k_block_max(const double* __restrict__ cma
   if (threadIdx.x == 0) bmax[b] = v;
 }
 
+// For every block b and r = 0..SHELL_MAX: the largest weight in the
+// (unwrapped, periodic) blocks at Chebyshev block distance exactly r from b.
+// One thread per block walks the shells outwards.
+__global__ void k_block_suffix(const double* __restrict__ bmax, double* __restrict__ suf, int Gb,
+                               int64_t GB) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= GB) return;
+  const int bx = int(b / (int64_t(Gb) * Gb)), by = int((b / Gb) % Gb), bz = int(b % Gb);
+  double sh[SHELL_MAX + 1];
+  for (int r = 0; r <= SHELL_MAX; ++r) {
+    double m = -DBL_MAX;
+    for (int ox = -r; ox <= r; ++ox)
+      for (int oy = -r; oy <= r; ++oy)
+        for (int oz = -r; oz <= r; ++oz) {
+          if (max(abs(ox), max(abs(oy), abs(oz))) != r) continue;
+          const int wx = ((bx + ox) % Gb + Gb) % Gb, wy = ((by + oy) % Gb + Gb) % Gb,
+                    wz = ((bz + oz) % Gb + Gb) % Gb;
+          m = fmax(m, bmax[(int64_t(wx) * Gb + wy) * Gb + wz]);
+        }
+    sh[r] = m;
+  }
+  for (int r = 0; r <= SHELL_MAX; ++r) suf[b * (SHELL_MAX + 1) + r] = sh[r];
+}
+
 }  // namespace
 
 void build_pointset(PointSet& ps, const double* points, const double* psi, int64_t N, double L,
@@ -124,6 +148,7 @@ void build_pointset(PointSet& ps, const double* points, const double* psi, int64
   ps.cell_start.ensure(size_t(G + 1) * sizeof(int32_t));
   ps.cell_psimax.ensure(size_t(G) * sizeof(double));
   ps.block_psimax.ensure(size_t(ps.g.GB()) * sizeof(double));
+  ps.block_suffix.ensure(size_t(ps.g.GB()) * (SHELL_MAX + 1) * sizeof(double));
   ps.scal.ensure(8 * sizeof(double));
   ps.key.ensure(size_t(N) * sizeof(int32_t));
   ps.rank.ensure(size_t(N) * sizeof(int32_t));
@@ -166,6 +191,8 @@ void update_psi_bounds(PointSet& ps, hipStream_t st) {
                      ps.cell_start.as<int32_t>(), ps.pts.as<double4>(), ps.cell_psimax.as<double>(), G);
   hipLaunchKernelGGL(k_block_max, dim3(unsigned(GB)), dim3(64), 0, st, ps.cell_psimax.as<double>(),
                      ps.block_psimax.as<double>(), GB);
+  hipLaunchKernelGGL(k_block_suffix, dim3(unsigned(ceil_div(GB, 64))), dim3(64), 0, st,
+                     ps.block_psimax.as<double>(), ps.block_suffix.as<double>(), ps.g.Gb, GB);
   MAK_HIP(hipGetLastError());
   dev_max_to(ps.block_psimax.as<double>(), GB, ps.scal.as<double>(), ps.tmp, st);
 }

@@ -30,7 +30,7 @@ def run(ctx, x, psi, L):
 
 
 def check(ctx, x, psi, L, hessian=True, **kw):
-    print(f"case N={x.shape[0]} L={L}", flush=True)
+    print(f"case N={x.shape[0]} L={L} precision={ctx.options['precision']}", flush=True)
     V, C, F, info = run(ctx, x, psi, L)
     res = oracle.cells(x, psi, L)
     rep = compare_cells(x, psi, L, V, C, F, res=res, **kw)
@@ -51,8 +51,8 @@ def check(ctx, x, psi, L, hessian=True, **kw):
             assert np.all(np.diff(c) > 0)
         rs = np.add.reduceat(val, rp[:-1]) if len(val) else np.zeros(0)
         assert np.abs(rs).max() <= 1e-12 * max(np.abs(val).max(), 1e-300)
-    print(f"  {rep} nnz={info['nnz']} faces={info['faces']} max_faces={info['max_faces']}",
-          flush=True)
+    print(f"  {rep} nnz={info['nnz']} faces={info['faces']} max_faces={info['max_faces']} "
+          f"fp64_rerun={info['fp64_rerun_cells']} overflow={info['overflow_cells']}", flush=True)
     return V, C, F, info, rep
 
 
@@ -202,3 +202,36 @@ def test_full_size_64_sampled(ctx):
         rp, col, val = (t.cpu().numpy() for t in ctx.hessian())
         rs = np.add.reduceat(val, rp[:-1])
         assert np.abs(rs).max() <= 1e-12 * np.abs(val).max()
+
+
+# ---------------------------------------------------------------- mixed precision
+@pytest.fixture(scope="module")
+def mctx():
+    import paper_2110_08868_amd as mak
+    c = mak.Context(0, "mixed")
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("case", ["za16", "za16_psi", "clustered12", "lattice4", "uniform1000"])
+def test_mixed_precision_parity(mctx, case):
+    """Float32 clipping with float64 vertices for the integrals: identical
+    adjacency above the area threshold, volumes and centroids to 1e-6 (the
+    stated bound; observed far tighter), against the float64 oracle."""
+    rng = np.random.default_rng(42)
+    if case == "za16":
+        x = workloads.zeldovich(16, rms=0.3, smooth=2.0, seed=1)
+        psi = np.zeros(len(x))
+    elif case == "za16_psi":
+        x = workloads.zeldovich(16, rms=1.0, smooth=1.0, seed=2)
+        psi = rng.uniform(-1, 1, len(x)) * 0.05 / 256
+    elif case == "clustered12":
+        x = workloads.clustered(12, rms=2.0, smooth=1.0, frac=0.2, n_clumps=10, a=0.5, seed=4)
+        psi = np.zeros(len(x))
+    elif case == "lattice4":
+        x = workloads.lattice(4, offset=(0.01, 0.02, 0.03))
+        psi = np.zeros(len(x))
+    else:
+        x = rng.uniform(0, 1, size=(1000, 3))
+        psi = rng.uniform(-1, 1, 1000) * 0.005
+    check(mctx, x, psi, 1.0, vol_rel=1e-6, cen_rel=1e-6, area_rel=1e-6)
