@@ -34,7 +34,7 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 WORKLOADS = {
     # name: (generator kwargs, tol, default precision)
     "clustered_128": (dict(kind="clustered", n=128, rms=3.0, smooth=1.0, frac=0.2, n_clumps=2000,
-                           a=0.5, seed=3), 1e-6, "fp64"),
+                           a=0.5, seed=3), 1e-6, "mixed"),
     "zeldovich_64": (dict(kind="zeldovich", n=64, rms=1.0, smooth=1.0, seed=2), 1e-6, "fp64"),
     "zeldovich_16": (dict(kind="zeldovich", n=16, rms=0.3, smooth=2.0, seed=1), 1e-6, "fp64"),
 }
@@ -64,7 +64,7 @@ def timed_solves(mak, x_dev, L, tol, precision, steps, warmup, cg_rtol, verbose=
     t0 = time.perf_counter()
     infos = []
     for k in range(steps):
-        _, _, _, info = ctx.solve(x_dev, L, tol)
+        psi, C, D, info = ctx.solve(x_dev, L, tol)
         infos.append(info)
         log(f"[bench] step {k} {precision}: newton={info['newton_iters']} passes={info['cell_passes']} "
             f"cg={info['cg_iters_total']} err={info['final_err']:.2e} t={info['seconds']:.3f}s")
@@ -76,7 +76,7 @@ def timed_solves(mak, x_dev, L, tol, precision, steps, warmup, cg_rtol, verbose=
     ctx.solve(x_dev, L, tol)
     cprof = ctx.profile_read()
     ctx.close()
-    return t1 - t0, infos, prof, cprof
+    return t1 - t0, infos, prof, cprof, (psi, C, D)
 
 
 def roofline(prof, cprof):
@@ -102,6 +102,53 @@ def roofline(prof, cprof):
                "bytes_per_launch": per_launch_bytes}
     share = {k: round(kern[k]["total_ms"], 3) for k in kern}
     return out, share
+
+
+def compare_paths(a, b, L, N):
+    """rms / max differences between the two precision paths' solutions, in
+    grid units (spacing L / N^(1/3))."""
+    import numpy as np
+    D = L / N ** (1.0 / 3.0)
+    pa, ca, da = (t.cpu().numpy() for t in a)
+    pb, cb, db = (t.cpu().numpy() for t in b)
+    dc = ca - cb
+    dc -= L * np.round(dc / L)
+    dd = da - db
+    return {"centroid_rms_grid": float(np.sqrt(np.mean(np.sum(dc * dc, 1))) / D),
+            "centroid_max_grid": float(np.abs(dc).max() / D),
+            "disp_rms_grid": float(np.sqrt(np.mean(np.sum(dd * dd, 1))) / D),
+            "psi_rms_over_D2": float(np.sqrt(np.mean((pa - pa.mean() - pb + pb.mean()) ** 2)) / D ** 2)}
+
+
+def accuracy_vs_oracle(mak, x, out, L, sample=64):
+    """Mixed-precision cell pass at its converged weights against the float64
+    oracle on sampled cells: max relative volume error, centroid error in
+    grid units, and the oracle's own volume error (solve certificate)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    psi = out[0]
+    N = x.shape[0]
+    D = L / N ** (1.0 / 3.0)
+    ctx = mak.Context(0, "mixed")
+    V, C, info = ctx.laguerre_cells(torch.from_numpy(x).cuda(), psi, L)
+    ctx.close()
+    V = V.cpu().numpy()
+    C = C.cpu().numpy()
+    idx = np.random.default_rng(7).choice(N, sample, replace=False)
+    r = oracle.cells(x, psi.cpu().numpy(), L, idx=idx, threads=min(os.cpu_count() or 1, 16))
+    uo = r["M"] / r["V"][:, None]
+    co = np.mod(x[idx] + uo, L)
+    dc = C[idx] - co
+    dc -= L * np.round(dc / L)
+    m = L ** 3 / N
+    return {"sample_cells": sample,
+            "max_rel_volume_err": float(np.max(np.abs(V[idx] - r["V"]) / r["V"])),
+            "centroid_rms_grid": float(np.sqrt(np.mean(np.sum(dc * dc, 1))) / D),
+            "disp_rms_grid": float(np.sqrt(np.mean(np.sum(dc * dc, 1))) / D),
+            "oracle_max_rel_volume_err_vs_m": float(np.max(np.abs(r["V"] - m)) / m),
+            "fp64_rerun_cells_in_pass": int(info["fp64_rerun_cells"])}
 
 
 def cpu_baseline(x, L, seconds):
@@ -130,6 +177,56 @@ def cpu_baseline(x, L, seconds):
                       f"(one cell pass, {dt:.1f} s)"}
 
 
+def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, seed=1000):
+    """Continuous-batching serving: requests of the serving mix (lattice side
+    log-uniform in [32, 128], rms 0.5..3 spacings) arrive as a Poisson process
+    at 0.8 x the closed-loop capacity measured on a warm-up batch; latency is
+    submit -> done."""
+    import numpy as np
+    import torch
+
+    import workloads
+    reqs = workloads.serving_requests(count, seed=seed)
+    log(f"[bench] serving: generating {count} inputs ...")
+    xs = [torch.from_numpy(workloads.zeldovich(r["n"], rms=r["rms"], smooth=r["smooth"],
+                                               seed=r["seed"])).cuda() for r in reqs]
+    torch.cuda.synchronize()
+    budget = int(budget_gb * (1 << 30))
+    srv = mak.Server(0, precision, mem_budget=budget, max_slots=slots, cg_rtol=cg_rtol)
+    # closed loop on a warm-up batch (all submitted at once)
+    warm = xs[: min(len(xs), 2 * slots)]
+    t0 = time.perf_counter()
+    rs = [srv.submit(x, 1.0, tol) for x in warm]
+    for r in rs:
+        r.wait()
+    cap = len(warm) / (time.perf_counter() - t0)
+    lam = 0.8 * cap
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, len(xs)))
+    log(f"[bench] serving: capacity {cap:.2f} req/s, arrival rate {lam:.2f} req/s")
+    t0 = time.perf_counter()
+    sub = []
+    for x, ta in zip(xs, arrivals):
+        dt = t0 + ta - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        sub.append(srv.submit(x, 1.0, tol))
+    for r in sub:
+        r.wait()
+    lat = np.array([r.times[2] - r.times[0] for r in sub])
+    span = max(r.times[2] for r in sub) - min(r.times[0] for r in sub)
+    st = srv.stats()
+    srv.close()
+    ns = np.array([r["n"] ** 3 for r in reqs])
+    return {"requests": len(sub), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "requests_per_s": len(sub) / span,
+            "arrival_rate_per_s": lam, "closed_loop_capacity_per_s": cap, "slots": slots,
+            "mem_budget_gb": budget_gb, "peak_used_gb": st["peak_used_bytes"] / 2 ** 30,
+            "peak_active": st["peak_active"], "admitted_while_busy": st["admitted_while_busy"],
+            "N_min": int(ns.min()), "N_median": int(np.median(ns)), "N_max": int(ns.max()),
+            "precision": precision, "tol": tol}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,12 +234,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="clustered_128", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
-    ap.add_argument("--compare", default="mixed", choices=["fp64", "mixed", "none"],
-                    help="also time the other precision path (default: the other one if built)")
+    ap.add_argument("--compare", default="auto", choices=["auto", "fp64", "mixed", "none"],
+                    help="also time another precision path (auto: the other one)")
     ap.add_argument("--cg-rtol", type=float, default=1e-3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=32,
+                    help="requests of the serving leg (the full serving workload is 256; 0 = skip)")
+    ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -163,8 +264,8 @@ def main():
     x_dev = torch.from_numpy(x).cuda()
     torch.cuda.synchronize()
 
-    secs, infos, prof, cprof = timed_solves(mak, x_dev, L, tol, precision, args.steps, args.warmup,
-                                            args.cg_rtol, int(args.verbose))
+    secs, infos, prof, cprof, out = timed_solves(mak, x_dev, L, tol, precision, args.steps,
+                                                 args.warmup, args.cg_rtol, int(args.verbose))
     passes = sum(i["cell_passes"] for i in infos)
     value = N * passes / secs
     rl, share = roofline(prof, cprof)
@@ -191,13 +292,21 @@ def main():
         "roofline": rl,
     }
     other = args.compare
-    if other is None:
-        other = "none"
+    if other == "auto":
+        other = "fp64" if precision == "mixed" else "mixed"
     if other not in ("none", precision):
-        s2, inf2, p2, c2 = timed_solves(mak, x_dev, L, tol, other, max(1, args.steps), 0, args.cg_rtol)
+        s2, inf2, p2, c2, out2 = timed_solves(mak, x_dev, L, tol, other, max(1, args.steps), 0,
+                                              args.cg_rtol)
         res[other] = {"cells_per_s": N * sum(i["cell_passes"] for i in inf2) / s2,
                       "ms_per_solve": s2 / len(inf2) * 1e3,
-                      "newton_iters": inf2[-1]["newton_iters"], "final_err": inf2[-1]["final_err"]}
+                      "newton_iters": inf2[-1]["newton_iters"], "final_err": inf2[-1]["final_err"],
+                      "fp64_rerun_cells": inf2[-1]["fp64_rerun_cells"]}
+        res["paths_agreement"] = compare_paths(out, out2, L, N)
+    if precision == "mixed" or other == "mixed":
+        res["mixed_vs_oracle"] = accuracy_vs_oracle(mak, x, out if precision == "mixed" else out2, L)
+    if args.serving_requests > 0:
+        res["serving"] = serving(mak, args.serving_requests, args.serving_slots,
+                                 args.serving_budget_gb, precision, tol, args.cg_rtol)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline(x, L, args.cpu_seconds)

@@ -184,6 +184,49 @@ int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entr
  * vertices, faces, cells). */
 mak_status mak_profile_counters(mak_ctx* ctx, double* out);
 
+/* ---- serving: many reconstruction requests on one device ----
+ * A server owns `max_slots` worker slots, each with its own context (device
+ * workspace kept resident between requests) and HIP stream.  Requests are
+ * admitted first-in first-out when a slot is free and their memory estimate
+ * (mak_solve_memory_estimate) fits in what `mem_budget_bytes` has left;
+ * requests submitted while others run start as soon as slots and memory
+ * free up, and their kernels overlap on the device.  Results are bitwise
+ * the same as a solo mak_solve of the same input.
+ * For callers that batch many catalogues (continuous batching of solves). */
+typedef struct mak_server mak_server;
+
+typedef struct {
+  int64_t submitted, completed, queued;
+  int32_t active, peak_active;          /* requests on the device now / at most */
+  int64_t admitted_while_busy;          /* requests started while others ran */
+  size_t used_bytes, peak_used_bytes, budget_bytes;
+} mak_server_info;
+
+/* opt: solver options of every request (NULL = defaults); mem_budget_bytes
+ * 0 = unlimited; 1 <= max_slots <= 64. */
+mak_status mak_server_create(mak_server** out, int device, const mak_options* opt,
+                             size_t mem_budget_bytes, int32_t max_slots);
+/* Queue a solve (arguments as mak_solve; all DEVICE pointers stay owned by
+ * the caller and must stay valid until the request is done).  The points
+ * must be complete on the device when this is called (synchronise the
+ * stream that wrote them).  MAK_ENOMEM if the estimate exceeds the budget. */
+mak_status mak_server_submit(mak_server* s, const double* points, int64_t N, double L, double tol,
+                             double* psi, double* centroids, double* displacements,
+                             int64_t* req_id);
+/* *done = 1 once the outputs are written; then returns the request's status
+ * and fills info.  times (HOST double[3], may be NULL): submit, start, end
+ * (seconds, steady clock). */
+mak_status mak_server_poll(mak_server* s, int64_t req_id, int32_t* done, mak_solve_info* info,
+                           double* times);
+/* Block until the request is done; returns its status. */
+mak_status mak_server_wait(mak_server* s, int64_t req_id, mak_solve_info* info, double* times);
+/* Forget a finished request. */
+mak_status mak_server_release(mak_server* s, int64_t req_id);
+mak_status mak_server_stats(mak_server* s, mak_server_info* out);
+const char* mak_server_last_error(const mak_server* s);
+/* Finishes the queued and running requests, then frees the server. */
+void mak_server_destroy(mak_server* s);
+
 /* Device memory a solve of N sites needs at most (bytes), for admission. */
 size_t mak_solve_memory_estimate(int64_t N, int32_t precision);
 

@@ -12,7 +12,7 @@ import ctypes
 import os
 
 __all__ = [
-    "MakError", "Context", "load_library", "laguerre_cells", "solve", "solve_from",
+    "MakError", "Context", "Server", "Request", "load_library", "laguerre_cells", "solve", "solve_from",
     "memory_estimate", "LIB_PATH", "EXPORTED_SYMBOLS",
 ]
 
@@ -22,7 +22,9 @@ EXPORTED_SYMBOLS = [
     "mak_default_options", "mak_create", "mak_destroy", "mak_last_error",
     "mak_laguerre_cells", "mak_hessian_copy", "mak_faces_copy", "mak_solve",
     "mak_solve_from", "mak_solve_memory_estimate", "mak_profile_enable", "mak_profile_read",
-    "mak_profile_counters",
+    "mak_profile_counters", "mak_server_create", "mak_server_submit", "mak_server_poll",
+    "mak_server_wait", "mak_server_release", "mak_server_stats", "mak_server_last_error",
+    "mak_server_destroy",
 ]
 
 STATUS = {0: "MAK_OK", 1: "MAK_EINVAL", 2: "MAK_ENOMEM", 3: "MAK_EDEGENERATE",
@@ -77,6 +79,15 @@ COUNTER_NAMES = ["sites_scanned", "planes_tested", "vertex_tests", "cuts", "new_
                  "ball_vertices", "box_tests", "final_vertices", "faces", "cells"]
 
 
+class _ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("queued", ctypes.c_int64),
+        ("active", ctypes.c_int32), ("peak_active", ctypes.c_int32),
+        ("admitted_while_busy", ctypes.c_int64), ("used_bytes", ctypes.c_size_t),
+        ("peak_used_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
+    ]
+
+
 def _as_dict(s) -> dict:
     return {name: getattr(s, name) for name, _ in s._fields_ if name != "reserved"}
 
@@ -119,6 +130,22 @@ def load_library():
     lib.mak_profile_read.restype = I32
     lib.mak_profile_counters.argtypes = [P, P]
     lib.mak_profile_counters.restype = ctypes.c_int
+    lib.mak_server_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P, ctypes.c_size_t, I32]
+    lib.mak_server_create.restype = ctypes.c_int
+    lib.mak_server_submit.argtypes = [P, P, I64, D, D, P, P, P, ctypes.POINTER(I64)]
+    lib.mak_server_submit.restype = ctypes.c_int
+    lib.mak_server_poll.argtypes = [P, I64, ctypes.POINTER(I32), P, P]
+    lib.mak_server_poll.restype = ctypes.c_int
+    lib.mak_server_wait.argtypes = [P, I64, P, P]
+    lib.mak_server_wait.restype = ctypes.c_int
+    lib.mak_server_release.argtypes = [P, I64]
+    lib.mak_server_release.restype = ctypes.c_int
+    lib.mak_server_stats.argtypes = [P, P]
+    lib.mak_server_stats.restype = ctypes.c_int
+    lib.mak_server_last_error.argtypes = [P]
+    lib.mak_server_last_error.restype = ctypes.c_char_p
+    lib.mak_server_destroy.argtypes = [P]
+    lib.mak_server_destroy.restype = None
     _LIB = lib
     return lib
 
@@ -278,6 +305,98 @@ class Context:
     def solve_from(self, points, psi0, L: float, tol: float = 1e-6):
         """Resume a solve from saved weights psi0."""
         return self._solve(self.lib.mak_solve_from, points, L, tol, psi0)
+
+
+class Request:
+    """A submitted solve: output tensors plus its id on the server."""
+
+    def __init__(self, server, rid, points, psi, centroids, disp):
+        self.server, self.id = server, rid
+        self.points, self.psi, self.centroids, self.displacements = points, psi, centroids, disp
+        self.info = None
+        self.times = None
+
+    def done(self) -> bool:
+        return self.server._poll(self)
+
+    def wait(self):
+        """Block until done; returns (psi, centroids, displacements, info)."""
+        self.server._wait(self)
+        return self.psi, self.centroids, self.displacements, self.info
+
+
+class Server:
+    """Continuous-batching solver: requests are admitted FIFO as worker slots
+    and the memory budget allow, and run concurrently on their own streams."""
+
+    def __init__(self, device: int = 0, precision: str = "fp64", mem_budget: int = 0,
+                 max_slots: int = 4, **opts):
+        torch = _torch()
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        o = _Options()
+        self.lib.mak_default_options(ctypes.byref(o))
+        o.precision = PRECISION[precision]
+        for k, v in opts.items():
+            setattr(o, k, v)
+        h = ctypes.c_void_p()
+        torch.cuda.init()
+        st = self.lib.mak_server_create(ctypes.byref(h), device, ctypes.byref(o), int(mem_budget),
+                                        int(max_slots))
+        if st != 0:
+            raise MakError(st, "server creation failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.mak_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, points, L: float, tol: float = 1e-6) -> Request:
+        torch = _torch()
+        x = torch.as_tensor(points).to(device=self.device, dtype=torch.float64).contiguous()
+        n = x.shape[0]
+        psi = torch.empty(n, dtype=torch.float64, device=self.device)
+        C = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        D = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()  # inputs complete before submit
+        rid = ctypes.c_int64()
+        st = self.lib.mak_server_submit(self._h, x.data_ptr(), n, float(L), float(tol), psi.data_ptr(),
+                                        C.data_ptr(), D.data_ptr(), ctypes.byref(rid))
+        if st != 0:
+            raise MakError(st, self.lib.mak_server_last_error(self._h).decode())
+        return Request(self, rid.value, x, psi, C, D)
+
+    def _poll(self, r: Request) -> bool:
+        done = ctypes.c_int32()
+        info = _SolveInfo()
+        times = (ctypes.c_double * 3)()
+        st = self.lib.mak_server_poll(self._h, r.id, ctypes.byref(done), ctypes.byref(info), times)
+        if done.value:
+            if st != 0:
+                raise MakError(st, "request failed")
+            r.info, r.times = _as_dict(info), tuple(times)
+        return bool(done.value)
+
+    def _wait(self, r: Request):
+        info = _SolveInfo()
+        times = (ctypes.c_double * 3)()
+        st = self.lib.mak_server_wait(self._h, r.id, ctypes.byref(info), times)
+        if st != 0:
+            raise MakError(st, self.lib.mak_server_last_error(self._h).decode())
+        r.info, r.times = _as_dict(info), tuple(times)
+        self.lib.mak_server_release(self._h, r.id)
+
+    def stats(self) -> dict:
+        s = _ServerStats()
+        self.lib.mak_server_stats(self._h, ctypes.byref(s))
+        return _as_dict(s)
 
 
 def laguerre_cells(points, psi, L: float, device: int = 0, precision: str = "fp64"):

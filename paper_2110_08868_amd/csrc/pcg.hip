@@ -35,7 +35,9 @@ unsigned vec_blocks(int64_t n) {
   return unsigned(b < MAXB ? (b < 1 ? 1 : b) : MAXB);
 }
 
-// q = J p (16 lanes per row) and per-block partial of p . q
+// q = J p, one 16-lane group per row over the whole grid (rows ~15
+// nonzeros: one coalesced load of col/val per lane), and per-block partial
+// of p . q
 __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
                                                   const double* __restrict__ val,
@@ -43,9 +45,9 @@ __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp
                                                   double* __restrict__ part, int64_t n) {
   __shared__ double sh[TPB / WAVE];
   const int sub = threadIdx.x & 15;
+  const int64_t row = int64_t(blockIdx.x) * (TPB / 16) + (threadIdx.x >> 4);
   double acc = 0.0;
-  for (int64_t row = int64_t(blockIdx.x) * (TPB / 16) + (threadIdx.x >> 4); row < n;
-       row += int64_t(gridDim.x) * (TPB / 16)) {
+  if (row < n) {
     const int64_t b = rp[row], e = rp[row + 1];
     double s = 0.0;
     for (int64_t k = b + sub; k < e; k += 16) s += val[k] * p[col[k]];
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp
     s += __shfl_xor(s, 1);
     if (sub == 0) {
       q[row] = s;
-      acc += s * p[row];
+      acc = s * p[row];
     }
   }
   acc = block_sum(acc, sh);
@@ -171,7 +173,8 @@ int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, 
   w.p.ensure(size_t(n) * sizeof(double));
   w.q.ensure(size_t(n) * sizeof(double));
   w.dinv.ensure(size_t(n) * sizeof(double));
-  w.part.ensure(size_t(2 * MAXB + 16) * sizeof(double));
+  const unsigned nbs = unsigned(ceil_div(n, TPB / 16));
+  w.part.ensure(size_t(std::max<int64_t>(2 * MAXB, nbs) + 16) * sizeof(double));
   w.scal.ensure(16 * sizeof(double));
   double* r = w.r.as<double>();
   double* z = w.z.as<double>();
@@ -182,7 +185,6 @@ int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, 
   double* scal = w.scal.as<double>();
   const unsigned nb = vec_blocks(n);
   const unsigned nbe = unsigned(ceil_div(n, 256));
-  const unsigned nbs = unsigned(std::min<int64_t>(ceil_div(n, TPB / 16), MAXB));
 
   hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
                      J.col.as<int32_t>(), J.val.as<double>(), dinv, n);
