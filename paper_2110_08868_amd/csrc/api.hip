@@ -28,19 +28,29 @@ void swap_buf(DevBuf& a, DevBuf& b) {
   std::swap(a.cap, b.cap);
 }
 
+// Exchange the per-cell results of two passes that share one face store.
 void swap_pass(CellPass& a, CellPass& b) {
   swap_buf(a.vol, b.vol);
   swap_buf(a.mom, b.mom);
   swap_buf(a.cflags, b.cflags);
   swap_buf(a.nface, b.nface);
-  swap_buf(a.faces, b.faces);
-  swap_buf(a.fbase, b.fbase);
-  swap_buf(a.ovf, b.ovf);
-  swap_buf(a.counters, b.counters);
-  swap_buf(a.retry, b.retry);
-  swap_buf(a.scan_tmp, b.scan_tmp);
-  std::swap(a.fslot, b.fslot);
-  std::swap(a.ovf_cap, b.ovf_cap);
+}
+
+size_t solve_bytes_per_site(int64_t N) {
+  // Held for the whole solve (bytes per site):
+  //   points: sorted sites 32, perm 4, neighbour grid and weight bounds ~6
+  //   two passes (accepted, trial): volume 8, moment 24, flags 4, faces 4,
+  //     stage lists 12 -> 2 x 52
+  //   one face store: slots fslot x 16, overflow base 8, overflow ~1/8 of a
+  //     slot row
+  //   J: row_ptr 8, row counts 8, 16 nonzeros per row x 12 (col + val)
+  //   PCG r, z, p, q, 1/diag 40;  Newton psi, trial psi, g, step 32
+  // The grid build's staging (40 bytes per site) is released before the
+  // first pass for sets above 2^24 sites and fits in the pass buffers' share
+  // below that.
+  const size_t fslot = size_t(face_slots(N));
+  const size_t faces = fslot * sizeof(FaceRec) + 8 + 2 * sizeof(FaceRec);
+  return 42 + 2 * 52 + faces + 16 + 16 * 12 + 40 + 32;
 }
 
 namespace {
@@ -101,8 +111,9 @@ struct mak_ctx {
   DevBuf face_ptr;
   int64_t nfaces = 0;
   bool cells_valid = false;
-  // solver
+  // solver: the accepted pass and the line-search trial share one face store
   PointSet sps;
+  FaceStore sfaces;
   CellPass scp, scp_trial;
   Csr sJ;
   PcgWork pw;
@@ -175,6 +186,8 @@ mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
     return MAK_EINVAL;
   }
   mak_ctx* c = new mak_ctx();
+  c->scp.shared = &c->sfaces;
+  c->scp_trial.shared = &c->sfaces;
   c->device = device;
   mak_default_options(&c->opt);
   if (opt) c->opt = *opt;
@@ -416,9 +429,8 @@ mak_status mak_profile_counters(mak_ctx* ctx, double* out) {
 
 size_t mak_solve_memory_estimate(int64_t N, int32_t precision) {
   (void)precision;
-  const int64_t fslot = N <= (int64_t(1) << 24) ? 32 : 20;
-  const int64_t per_site = 80 + 2 * (60 + fslot * int64_t(sizeof(FaceRec)) + 16) + 232 + 80;
-  return size_t(N) * size_t(per_site) + (size_t(64) << 20);
+  if (N < 1) return 0;
+  return size_t(N) * solve_bytes_per_site(N) + (size_t(64) << 20);
 }
 
 }  // extern "C"

@@ -178,7 +178,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ ClipLDS<TPL, R> S;
 
   const int lane = threadIdx.x;
-  const int64_t blk = blockIdx.x;
+  // linear workgroup id (2-D grid above 2^16 items; gridDim.x is a multiple
+  // of 8, so blk & 7 is still the XCD the workgroup runs on)
+  const int64_t blk = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+  if ((blk >> 3) >= A.per_xcd) return;
   const int64_t item = (blk & 7) * A.per_xcd + (blk >> 3);
   if (item >= A.nwork) return;
   const int32_t p = A.work ? A.work[item] : int32_t(item);
@@ -999,8 +1002,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         FaceRec fr;
         fr.j = S.pj[f];
         fr.shift = S.ps[f];
-        fr.area = Af[c];
-        fr.dist = sqrt(P.x * P.x + P.y * P.y + P.z * P.z);
+        fr.w = Af[c] / sqrt(P.x * P.x + P.y * P.y + P.z * P.z);
         dst[run + lanes_below(rm)] = fr;
       }
       run += __popcll(rm);
@@ -1028,10 +1030,10 @@ double clip_flops(const unsigned long long* c) {
          11.0 * c[ST_BALL] + 30.0 * c[ST_BOX] + 135.0 * c[ST_TRI];
 }
 // Compulsory HBM bytes: read own site (32), write volume, moment, flags and
-// face count (40), write the reported faces (24 each).  Neighbour reads are
+// face count (40), write the reported faces (16 each).  Neighbour reads are
 // served by the caches.
 double clip_bytes(const unsigned long long* c) {
-  return 72.0 * c[ST_CELLS] + 24.0 * c[ST_FACES];
+  return 72.0 * c[ST_CELLS] + double(sizeof(FaceRec)) * c[ST_FACES];
 }
 
 template <int TPL, typename R>
@@ -1044,10 +1046,16 @@ void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
   }
   const char* name = sizeof(R) == 4 ? "clip_f32" : (TPL == 2 ? "clip" : "clip_large");
   ProfScope ps(name, st, double(items));
+  // one 64-lane workgroup per item; the work-items of one grid dimension
+  // must stay below 2^32, so passes above 2^16 items use a 2-D grid of rows
+  // of 2^16 workgroups
+  const int64_t nblk = 8 * a.per_xcd;
+  const int64_t gx = nblk < (int64_t(1) << 16) ? nblk : (int64_t(1) << 16);
+  const dim3 grid(unsigned(gx), unsigned(ceil_div(nblk, gx)));
   if (counting)
-    hipLaunchKernelGGL((k_clip<TPL, R, true>), dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_clip<TPL, R, true>), grid, dim3(64), 0, st, a);
   else
-    hipLaunchKernelGGL((k_clip<TPL, R, false>), dim3(unsigned(8 * a.per_xcd)), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_clip<TPL, R, false>), grid, dim3(64), 0, st, a);
   MAK_HIP(hipGetLastError());
   if (counting) {
     unsigned long long c[ST_N];
@@ -1063,10 +1071,13 @@ void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
 
 }  // namespace
 
+int32_t face_slots(int64_t N) { return N <= (int64_t(1) << 24) ? 32 : 20; }
+
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
                     bool tolerate_failure) {
   const int64_t N = ps.N;
-  out.fslot = N <= (int64_t(1) << 24) ? 32 : 20;
+  FaceStore& fst = out.fs();
+  fst.fslot = face_slots(N);
   out.vol.ensure(size_t(N) * sizeof(double));
   out.mom.ensure(size_t(N) * 3 * sizeof(double));
   out.cflags.ensure(size_t(N) * sizeof(int32_t));
@@ -1074,10 +1085,10 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
   out.retry.ensure(size_t(N) * 3 * sizeof(int32_t));
   out.counters.ensure(64 * sizeof(unsigned long long));
   if (faces) {
-    out.faces.ensure(size_t(N) * out.fslot * sizeof(FaceRec));
-    out.fbase.ensure(size_t(N) * sizeof(int64_t));
-    if (out.ovf_cap < 4096 + N / 8) out.ovf_cap = 4096 + N / 8;
-    out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
+    fst.faces.ensure(size_t(N) * fst.fslot * sizeof(FaceRec));
+    fst.fbase.ensure(size_t(N) * sizeof(int64_t));
+    if (fst.ovf_cap < 4096 + N / 8) fst.ovf_cap = 4096 + N / 8;
+    fst.ovf.ensure(size_t(fst.ovf_cap) * sizeof(FaceRec));
   }
   // Stages: every cell runs in the first kernel; the cells it could not
   // finish (capacity, inconsistent cut, float32 ambiguity) go to the next.
@@ -1106,12 +1117,12 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
     a.mom = out.mom.as<double>();
     a.cflags = out.cflags.as<int32_t>();
     a.nface = out.nface.as<int32_t>();
-    a.faces = faces ? out.faces.as<FaceRec>() : nullptr;
-    a.fbase = faces ? out.fbase.as<int64_t>() : nullptr;
-    a.ovf = faces ? out.ovf.as<FaceRec>() : nullptr;
+    a.faces = faces ? fst.faces.as<FaceRec>() : nullptr;
+    a.fbase = faces ? fst.fbase.as<int64_t>() : nullptr;
+    a.ovf = faces ? fst.ovf.as<FaceRec>() : nullptr;
     a.ovf_used = ctr;
-    a.ovf_cap = faces ? out.ovf_cap : 0;
-    a.fslot = out.fslot;
+    a.ovf_cap = faces ? fst.ovf_cap : 0;
+    a.fslot = fst.fslot;
     a.write_faces = faces ? 1 : 0;
     const double spacing = ps.g.L / std::cbrt(double(N));
     a.area_min = 1e-12 * spacing * spacing;
@@ -1138,9 +1149,9 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
       unsigned long long hc[4];
       MAK_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
       MAK_HIP(hipStreamSynchronize(st));
-      if (faces && int64_t(hc[0]) > out.ovf_cap) {
-        out.ovf_cap = int64_t(hc[0]) * 2 + 4096;
-        out.ovf.ensure(size_t(out.ovf_cap) * sizeof(FaceRec));
+      if (faces && int64_t(hc[0]) > fst.ovf_cap) {
+        fst.ovf_cap = int64_t(hc[0]) + int64_t(hc[0]) / 4 + 4096;
+        fst.ovf.ensure(size_t(fst.ovf_cap) * sizeof(FaceRec));
         regrow = true;
         break;
       }

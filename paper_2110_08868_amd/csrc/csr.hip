@@ -60,14 +60,14 @@ __global__ void k_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* 
   int64_t o = row_ptr[row];
   // off-diagonal sum first (fixed order), so the diagonal is minus the row sum
   double diag = 0.0;
-  for (int32_t k = 0; k < nf; ++k) diag += f[k].area / f[k].dist;
+  for (int32_t k = 0; k < nf; ++k) diag += f[k].w;
   bool diag_done = false;
   int32_t k = 0;
   while (k < nf) {
     const int64_t c = perm ? perm[f[k].j] : f[k].j;
     double w = 0.0;
     while (k < nf && (perm ? perm[f[k].j] : f[k].j) == c) {
-      w += f[k].area / f[k].dist;
+      w += f[k].w;
       ++k;
     }
     if (!diag_done && c > row) {
@@ -86,23 +86,31 @@ __global__ void k_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* 
   }
 }
 
+// Face lists in original order; the area is the stored weight times |d|,
+// with d formed exactly as the clip kernel forms it.
 __global__ void k_face_copy(const FaceRec* faces, const FaceRec* ovf, const int64_t* fbase,
                             int32_t fslot, const int32_t* __restrict__ nface,
-                            const int32_t* __restrict__ perm, const int64_t* __restrict__ fptr,
-                            int32_t* __restrict__ fj, int32_t* __restrict__ fs,
-                            double* __restrict__ fa, int64_t n) {
+                            const int32_t* __restrict__ perm, const double4* __restrict__ pts,
+                            double L, const int64_t* __restrict__ fptr, int32_t* __restrict__ fj,
+                            int32_t* __restrict__ fs, double* __restrict__ fa, int64_t n) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int32_t nf = nface[p];
   const FaceRec* f = face_list(const_cast<FaceRec*>(faces), const_cast<FaceRec*>(ovf), fbase, fslot,
                                int32_t(p), nf);
+  const double4 me = pts[p];
   int64_t o = fptr[perm[p]];
   for (int32_t k = 0; k < nf; ++k, ++o) {
+    const int32_t sh = f[k].shift;
+    const double4 P = pts[f[k].j];
+    const double dx = P.x + unpack_shift(sh, 0) * L - me.x;
+    const double dy = P.y + unpack_shift(sh, 1) * L - me.y;
+    const double dz = P.z + unpack_shift(sh, 2) * L - me.z;
     fj[o] = perm[f[k].j];
-    fs[3 * o] = unpack_shift(f[k].shift, 0);
-    fs[3 * o + 1] = unpack_shift(f[k].shift, 1);
-    fs[3 * o + 2] = unpack_shift(f[k].shift, 2);
-    fa[o] = f[k].area;
+    fs[3 * o] = unpack_shift(sh, 0);
+    fs[3 * o + 1] = unpack_shift(sh, 1);
+    fs[3 * o + 2] = unpack_shift(sh, 2);
+    fa[o] = f[k].w * sqrt(dx * dx + dy * dy + dz * dz);
   }
 }
 
@@ -112,13 +120,16 @@ void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hi
   const int64_t n = ps.N;
   ProfScope scope("csr_assembly", st, double(n));
   J.n = n;
-  J.rowcnt.ensure(size_t(n) * 2 * sizeof(int64_t));
+  // row counts, and (original space, for the face copy) the face counts after them
+  J.rowcnt.ensure(size_t(n) * (original_space ? 2 : 1) * sizeof(int64_t));
   J.row_ptr.ensure(size_t(n + 1) * sizeof(int64_t));
   const int32_t* perm = original_space ? ps.perm.as<int32_t>() : nullptr;
   const unsigned nb = unsigned(ceil_div(n, 256));
-  hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(256), 0, st, cp.faces.as<FaceRec>(),
-                     cp.ovf.as<FaceRec>(), cp.fbase.as<int64_t>(), cp.fslot, cp.nface.as<int32_t>(),
-                     perm, J.rowcnt.as<int64_t>(), J.rowcnt.as<int64_t>() + n, n);
+  const FaceStore& fst = cp.fs();
+  hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
+                     fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
+                     perm, J.rowcnt.as<int64_t>(), original_space ? J.rowcnt.as<int64_t>() + n : nullptr,
+                     n);
   MAK_HIP(hipGetLastError());
   exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr.as<int64_t>(), n, cp.scan_tmp, st);
   int64_t nnz = 0;
@@ -127,8 +138,8 @@ void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hi
   J.nnz = nnz;
   J.col.ensure(size_t(nnz) * sizeof(int32_t));
   J.val.ensure(size_t(nnz) * sizeof(double));
-  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, st, cp.faces.as<FaceRec>(), cp.ovf.as<FaceRec>(),
-                     cp.fbase.as<int64_t>(), cp.fslot, cp.nface.as<int32_t>(), perm,
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(), fst.ovf.as<FaceRec>(),
+                     fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(), perm,
                      J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.val.as<double>(), n);
   MAK_HIP(hipGetLastError());
 }
@@ -150,9 +161,10 @@ void copy_faces(const PointSet& ps, CellPass& cp, const DevBuf& face_ptr, int64_
   MAK_HIP(hipMemcpyAsync(out_ptr, face_ptr.p, size_t(n + 1) * sizeof(int64_t),
                          hipMemcpyDeviceToDevice, st));
   hipLaunchKernelGGL(k_face_copy, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st,
-                     cp.faces.as<FaceRec>(), cp.ovf.as<FaceRec>(), cp.fbase.as<int64_t>(), cp.fslot,
-                     cp.nface.as<int32_t>(), ps.perm.as<int32_t>(), face_ptr.as<int64_t>(), fj, fshift,
-                     farea, n);
+                     cp.fs().faces.as<FaceRec>(), cp.fs().ovf.as<FaceRec>(),
+                     cp.fs().fbase.as<int64_t>(), cp.fs().fslot, cp.nface.as<int32_t>(),
+                     ps.perm.as<int32_t>(), ps.pts.as<double4>(), ps.g.L, face_ptr.as<int64_t>(), fj,
+                     fshift, farea, n);
   MAK_HIP(hipGetLastError());
 }
 

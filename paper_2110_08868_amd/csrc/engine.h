@@ -38,12 +38,11 @@ struct DevBuf {
   }
 };
 
-// One face of a cell as written by the clip kernel.
+// One face of a cell as written by the clip kernel (16 bytes).
 struct FaceRec {
   int32_t j;      // other site, sorted index
   int32_t shift;  // packed periodic image of site j
-  double area;
-  double dist;    // |x_j + shift L - x_i|
+  double w;       // area / |x_j + shift L - x_i|, the Hessian weight of the face
 };
 
 // Per-cell flag bits written by the clip kernel.
@@ -81,7 +80,21 @@ struct PointSet {
   DevBuf block_suffix; // double [GB * (SHELL_MAX + 1)]: max weight over the blocks at
                        // Chebyshev block distance exactly r from each block
   DevBuf scal;         // double [8]: [0] global psi max, [1] global psi min
-  DevBuf key, rank, count, status, tmp;  // build temporaries
+  DevBuf key, rank, count, status, tmp;  // build temporaries (released after the
+                                         // build of a large set)
+};
+
+// Face records of one cell pass.  A cell with at most `fslot` faces keeps them
+// in its own slots; a larger one keeps them all in the overflow region, from
+// fbase[cell].  The solver shares one store between the accepted pass and the
+// line-search trial: once J is assembled the faces of the accepted pass are
+// dead, so a trial may overwrite them.
+struct FaceStore {
+  DevBuf faces;      // FaceRec [N * fslot]
+  DevBuf fbase;      // int64 [N]
+  DevBuf ovf;        // FaceRec [ovf_cap]
+  int32_t fslot = 0;
+  int64_t ovf_cap = 0;
 };
 
 // Output of one cell pass (sorted order).
@@ -90,15 +103,17 @@ struct CellPass {
   DevBuf mom;        // double [3N] first moment, seed-local
   DevBuf cflags;     // int32 [N]
   DevBuf nface;      // int32 [N]
-  DevBuf faces;      // FaceRec [N * fslot]
-  DevBuf fbase;      // int64 [N]: start in `ovf` of a cell with more than fslot faces
-  DevBuf ovf;        // FaceRec [ovf_cap]
-  DevBuf counters;   // uint64 [16]: [0] overflow faces used, [1] retries, [2] failures
-  DevBuf retry;      // int32 [N]
+  DevBuf counters;   // uint64 [64]: overflow faces used, stage lists, work counters
+  DevBuf retry;      // int32 [3N]: cells listed for the next stage
   DevBuf scan_tmp;
-  int32_t fslot = 0;
-  int64_t ovf_cap = 0;
+  FaceStore own;
+  FaceStore* shared = nullptr;  // face storage in use (`own` when NULL)
+  FaceStore& fs() { return shared ? *shared : own; }
+  const FaceStore& fs() const { return shared ? *shared : own; }
 };
+
+// Bytes of device memory per site (and fixed) that one solve holds.
+size_t solve_bytes_per_site(int64_t N);
 
 struct Csr {
   int64_t n = 0, nnz = 0;
@@ -137,6 +152,8 @@ void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hi
 int64_t count_faces(const PointSet& ps, CellPass& cp, Csr& J, DevBuf& face_ptr, hipStream_t st);
 void copy_faces(const PointSet& ps, CellPass& cp, const DevBuf& face_ptr, int64_t* out_ptr,
                 int32_t* fj, int32_t* fshift, double* farea, hipStream_t st);
+// Face slots per cell for a point set of N sites.
+int32_t face_slots(int64_t N);
 
 // --- pcg.hip / reductions
 double dev_reduce_max(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);

@@ -176,6 +176,13 @@ void build_pointset(PointSet& ps, const double* points, const double* psi, int64
   MAK_HIP(hipStreamSynchronize(st));
   if (hs) MAK_FAIL(MAK_EINVAL, "non-finite coordinate or weight");
   update_psi_bounds(ps, st);
+  if (N > (int64_t(1) << 24)) {
+    // a large set is built once per solve: give the staging back to the passes
+    ps.key.release();
+    ps.rank.release();
+    ps.count.release();
+    ps.status.release();
+  }
 }
 
 void set_psi_sorted(PointSet& ps, const double* psi_sorted, hipStream_t st) {

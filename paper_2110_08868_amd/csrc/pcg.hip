@@ -13,7 +13,8 @@ namespace mak {
 namespace {
 
 constexpr int TPB = 256;
-constexpr int MAXB = 1024;  // blocks of the grid-stride vector kernels
+constexpr int MAXB = 1024;       // blocks of the grid-stride vector kernels
+constexpr int SPMV_MAXB = 8192;  // blocks of the SpMV (16 rows each per sweep)
 
 // scalar slots (device doubles)
 enum { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6 };
@@ -35,8 +36,13 @@ unsigned vec_blocks(int64_t n) {
   return unsigned(b < MAXB ? (b < 1 ? 1 : b) : MAXB);
 }
 
-// q = J p, one 16-lane group per row over the whole grid (rows ~15
-// nonzeros: one coalesced load of col/val per lane), and per-block partial
+unsigned spmv_blocks(int64_t n) {
+  const int64_t b = ceil_div(n, TPB / 16);
+  return unsigned(b < SPMV_MAXB ? (b < 1 ? 1 : b) : SPMV_MAXB);
+}
+
+// q = J p, one 16-lane group per row (rows ~15 nonzeros: one coalesced load
+// of col/val per lane), grid-stride over row groups, and per-block partial
 // of p . q
 __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
@@ -45,9 +51,9 @@ __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp
                                                   double* __restrict__ part, int64_t n) {
   __shared__ double sh[TPB / WAVE];
   const int sub = threadIdx.x & 15;
-  const int64_t row = int64_t(blockIdx.x) * (TPB / 16) + (threadIdx.x >> 4);
   double acc = 0.0;
-  if (row < n) {
+  for (int64_t row = int64_t(blockIdx.x) * (TPB / 16) + (threadIdx.x >> 4); row < n;
+       row += int64_t(gridDim.x) * (TPB / 16)) {
     const int64_t b = rp[row], e = rp[row + 1];
     double s = 0.0;
     for (int64_t k = b + sub; k < e; k += 16) s += val[k] * p[col[k]];
@@ -57,7 +63,7 @@ __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp
     s += __shfl_xor(s, 1);
     if (sub == 0) {
       q[row] = s;
-      acc = s * p[row];
+      acc += s * p[row];
     }
   }
   acc = block_sum(acc, sh);
@@ -173,7 +179,7 @@ int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, 
   w.p.ensure(size_t(n) * sizeof(double));
   w.q.ensure(size_t(n) * sizeof(double));
   w.dinv.ensure(size_t(n) * sizeof(double));
-  const unsigned nbs = unsigned(ceil_div(n, TPB / 16));
+  const unsigned nbs = spmv_blocks(n);
   w.part.ensure(size_t(std::max<int64_t>(2 * MAXB, nbs) + 16) * sizeof(double));
   w.scal.ensure(16 * sizeof(double));
   double* r = w.r.as<double>();

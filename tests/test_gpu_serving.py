@@ -43,9 +43,12 @@ def test_admission_by_memory():
     est_small = mak.memory_estimate(len(small))
     est_big = mak.memory_estimate(len(big))
     # the budget holds one big request, or the big one is rejected outright
-    srv = mak.Server(0, mem_budget=est_big + est_small // 2, max_slots=4)
+    budget = est_big + est_small // 2
+    srv = mak.Server(0, mem_budget=budget, max_slots=4)
+    huge = workloads.zeldovich(48, rms=0.5, smooth=1.0, seed=5)
+    assert mak.memory_estimate(len(huge)) > budget
     with pytest.raises(mak.MakError) as e:
-        srv.submit(torch.from_numpy(workloads.zeldovich(32, rms=0.5, smooth=1.0, seed=5)), 1.0)
+        srv.submit(torch.from_numpy(huge), 1.0)
     assert e.value.name == "MAK_ENOMEM"
     r1 = srv.submit(torch.from_numpy(big), 1.0, 1e-6)
     r2 = srv.submit(torch.from_numpy(big), 1.0, 1e-6)

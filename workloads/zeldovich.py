@@ -17,8 +17,10 @@ uneven cell sizes of collapsed haloes.
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
+import scipy.fft
 
 
 def wrap(x: np.ndarray, L: float) -> np.ndarray:
@@ -57,10 +59,15 @@ def layered(xs, ny: int, nz: int, L: float = 1.0) -> np.ndarray:
     return np.stack([A.ravel(), B.ravel(), C.ravel()], axis=1).astype(np.float64)
 
 
+def _fft_workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
 def _displacement(n: int, L: float, smooth: float, rng: np.random.Generator) -> np.ndarray:
     D = L / n
     white = rng.standard_normal((n, n, n))
-    wk = np.fft.rfftn(white)
+    wk = scipy.fft.rfftn(white, workers=_fft_workers())
+    del white
     kx = 2.0 * np.pi * np.fft.fftfreq(n, d=D)
     kz = 2.0 * np.pi * np.fft.rfftfreq(n, d=D)
     KX, KY, KZ = np.meshgrid(kx, kx, kz, indexing="ij")
@@ -82,7 +89,8 @@ def _displacement(n: int, L: float, smooth: float, rng: np.random.Generator) -> 
                 comp[:, nyq, :] = 0.0
             else:
                 comp[:, :, nyq] = 0.0
-        out[a] = np.fft.irfftn(comp, s=(n, n, n), axes=(0, 1, 2))
+        out[a] = scipy.fft.irfftn(comp, s=(n, n, n), axes=(0, 1, 2), workers=_fft_workers())
+        del comp
     return out.reshape(3, -1).T.copy()
 
 
