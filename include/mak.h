@@ -181,7 +181,9 @@ mak_status mak_profile_enable(mak_ctx* ctx, int32_t flags);
 int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entries);
 /* HOST double[16]: summed clip work counters (sites scanned, planes tested,
  * vertex tests, cuts, new vertices, ball-update vertices, box tests, final
- * vertices, faces, cells). */
+ * vertices, faces, cells), then shader-clock cycles summed over waves spent
+ * in the candidate search, the serial clipping and the integrals; unused
+ * entries are zero. */
 mak_status mak_profile_counters(mak_ctx* ctx, double* out);
 
 /* ---- serving: many reconstruction requests on one device ----

@@ -76,7 +76,8 @@ class _KernelProfile(ctypes.Structure):
 
 
 COUNTER_NAMES = ["sites_scanned", "planes_tested", "vertex_tests", "cuts", "new_vertices",
-                 "ball_vertices", "box_tests", "final_vertices", "faces", "cells"]
+                 "ball_vertices", "box_tests", "final_vertices", "faces", "cells",
+                 "cycles_search", "cycles_clip", "cycles_integrals"]
 
 
 class _ServerStats(ctypes.Structure):

@@ -77,7 +77,11 @@ struct ClipArgs {
 // Work counters of the clip kernel (optional): sites scanned, planes tested
 // against the vertices, vertex tests, cuts, new vertices, ball updates (in
 // vertices), box tests, final vertices, reported faces, cells.
-enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS, ST_N };
+// The counting variant also sums shader-clock cycles per wave by phase:
+// candidate search (grid walk, site loads, batch filter and sort), serial
+// clipping, integrals and output.
+enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS,
+       ST_TSEARCH, ST_TCLIP, ST_TINT, ST_N };
 
 // Final vertices in float64 (the float32 path recomputes them from their
 // three planes before integrating; the float64 path integrates its own).
@@ -198,6 +202,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   bool dead = false;
   // work counters (compiled in only for the counting variant)
   uint32_t c_cand = 0, c_test = 0, c_vt = 0, c_cut = 0, c_newv = 0, c_ball = 0, c_box = 0, c_pre = 0;
+  uint64_t t_begin = 0, t_clip = 0, t_search_end = 0;
+  if (STATS) t_begin = __builtin_amdgcn_s_memtime();
 #define CNT(stmt)  \
   do {             \
     if (STATS) {   \
@@ -636,11 +642,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       S.candj[lane] = q;
       S.cands[lane] = shv;
       __syncthreads();
+      uint64_t tc0 = 0;
+      if (STATS) tc0 = __builtin_amdgcn_s_memtime();
       for (int r = 0; r < ns && !dead; ++r) {
         const int src = int(readlane_u(key, r) & 63u);
         const double4 C = S.cand[src];
         clip_one(C.x, C.y, C.z, C.w, S.candj[src], S.cands[src]);
       }
+      if (STATS) t_clip += __builtin_amdgcn_s_memtime() - tc0;
       __syncthreads();
     }
     __syncthreads();
@@ -801,9 +810,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
   }
 
+  if (STATS) t_search_end = __builtin_amdgcn_s_memtime();
   auto flush_stats = [&](int ntri, int nfaces) {
     if (STATS && A.stats && lane == 0) {
       unsigned long long* st = A.stats;
+      const uint64_t t_end = __builtin_amdgcn_s_memtime();
+      atomicAdd(&st[ST_TSEARCH], (unsigned long long)(t_search_end - t_begin - t_clip));
+      atomicAdd(&st[ST_TCLIP], (unsigned long long)t_clip);
+      atomicAdd(&st[ST_TINT], (unsigned long long)(t_end - t_search_end));
       atomicAdd(&st[ST_CAND], (unsigned long long)c_cand);
       atomicAdd(&st[ST_TEST], (unsigned long long)c_test);
       atomicAdd(&st[ST_VTEST], (unsigned long long)(c_vt + c_pre));
@@ -1073,6 +1087,8 @@ void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
 
 int32_t face_slots(int64_t N) { return N <= (int64_t(1) << 24) ? 32 : 20; }
 
+static_assert(4 + ST_N <= 32, "work counters overlap the stage causes");
+
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
                     bool tolerate_failure) {
   const int64_t N = ps.N;
@@ -1098,7 +1114,7 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
   const int nstage = mixed ? 3 : 2;
   unsigned long long* ctr = out.counters.as<unsigned long long>();
   // counters: [0] overflow faces used, [1 + s] cells listed by stage s,
-  // [4..13] work counters, [16 + 3 s ..] causes (capacity, cut, ambiguity)
+  // [4..4 + ST_N) work counters, [32 + 3 s ..] causes (capacity, cut, ambiguity)
   ClipStats cs;
   for (int attempt = 0; attempt < 3; ++attempt) {
     MAK_HIP(hipMemsetAsync(out.counters.p, 0, 64 * sizeof(unsigned long long), st));
@@ -1137,7 +1153,7 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
       a.per_xcd = ceil_div(listed, 8);
       a.retry = out.retry.as<int32_t>() + stg * N;
       a.retry_count = ctr + 1 + stg;
-      a.cause = ctr + 16 + 3 * stg;
+      a.cause = ctr + 32 + 3 * stg;
       const bool last = stg == nstage - 1;
       a.eps_rel = last ? 1e-11 : 1e-13;
       if (mixed && stg == 0)
@@ -1162,7 +1178,7 @@ ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipS
         cs.overflow = listed;
         if (tolerate_failure) return cs;
         unsigned long long cz[3];
-        MAK_HIP(hipMemcpy(cz, ctr + 16 + 3 * stg, sizeof(cz), hipMemcpyDeviceToHost));
+        MAK_HIP(hipMemcpy(cz, ctr + 32 + 3 * stg, sizeof(cz), hipMemcpyDeviceToHost));
         MAK_FAIL(MAK_EOVERFLOW, std::to_string(cz[0]) + " cells exceeded the polytope capacity, " +
                                     std::to_string(cz[1]) + " had inconsistent cuts");
       }
