@@ -280,6 +280,8 @@ def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, seed=1000):
             "arrival_rate_per_s": lam, "closed_loop_capacity_per_s": cap, "slots": slots,
             "mem_budget_gb": budget_gb, "peak_used_gb": st["peak_used_bytes"] / 2 ** 30,
             "peak_active": st["peak_active"], "admitted_while_busy": st["admitted_while_busy"],
+            "cell_passes_per_shared_launch": st["batched_passes"] / max(st["pass_batches"], 1),
+            "max_passes_in_one_launch": st["max_batch"],
             "N_min": int(ns.min()), "N_median": int(np.median(ns)), "N_max": int(ns.max()),
             "precision": precision, "tol": tol}
 

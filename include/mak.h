@@ -192,9 +192,11 @@ mak_status mak_profile_counters(mak_ctx* ctx, double* out);
  * admitted first-in first-out when a slot is free and their memory estimate
  * (mak_solve_memory_estimate) fits in what `mem_budget_bytes` has left;
  * requests submitted while others run start as soon as slots and memory
- * free up, and their kernels overlap on the device.  Results are bitwise
- * the same as a solo mak_solve of the same input.
- * For callers that batch many catalogues (continuous batching of solves). */
+ * free up (continuous batching).  The cell passes of all requests that need
+ * one at the same time are packed into shared clip launches (up to 8 point
+ * sets per launch) by the server's pass batcher; the Newton / PCG work of
+ * each request runs on its slot's stream and overlaps on the device.
+ * Results are bitwise the same as a solo mak_solve of the same input. */
 typedef struct mak_server mak_server;
 
 typedef struct {
@@ -202,6 +204,10 @@ typedef struct {
   int32_t active, peak_active;          /* requests on the device now / at most */
   int64_t admitted_while_busy;          /* requests started while others ran */
   size_t used_bytes, peak_used_bytes, budget_bytes;
+  int64_t pass_batches;                 /* shared cell-pass launches sequences */
+  int64_t batched_passes;               /* cell passes run in them */
+  int32_t max_batch;                    /* most passes in one of them */
+  int32_t reserved;
 } mak_server_info;
 
 /* opt: solver options of every request (NULL = defaults); mem_budget_bytes

@@ -86,6 +86,8 @@ class _ServerStats(ctypes.Structure):
         ("active", ctypes.c_int32), ("peak_active", ctypes.c_int32),
         ("admitted_while_busy", ctypes.c_int64), ("used_bytes", ctypes.c_size_t),
         ("peak_used_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
+        ("pass_batches", ctypes.c_int64), ("batched_passes", ctypes.c_int64),
+        ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

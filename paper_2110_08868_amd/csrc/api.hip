@@ -119,7 +119,14 @@ struct mak_ctx {
   PcgWork pw;
   DevBuf psi_s, psi_t, g, pstep, tmp;
   Profiler prof;
+  PassRunner* runner = nullptr;  // NULL: passes run on the solve's stream
 };
+
+namespace mak {
+
+void set_pass_runner(mak_ctx* ctx, PassRunner* r) { ctx->runner = r; }
+
+}  // namespace mak
 
 namespace {
 
@@ -300,8 +307,12 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       MAK_HIP(hipMemsetAsync(psi_s, 0, size_t(N) * sizeof(double), st));
     const double m = L * L * L / double(N);
 
+    auto pass = [&](CellPass& cp, bool tolerate) {
+      return ctx->runner ? ctx->runner->run(ps, cp, o.precision, true, st, tolerate)
+                         : run_cells(ps, cp, o.precision, true, st, tolerate);
+    };
     set_psi_sorted(ps, psi_s, st);
-    ClipStats cs = run_cells(ps, ctx->scp, o.precision, true, st);
+    ClipStats cs = pass(ctx->scp, false);
     si.cell_passes = 1;
     si.overflow_cells += cs.retried - cs.fp64_rerun;
     si.fp64_rerun_cells += cs.fp64_rerun;
@@ -328,7 +339,7 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       for (int ls = 0; ls <= o.max_halvings; ++ls) {
         axpy_into(ctx->psi_s.as<double>(), ctx->pstep.as<double>(), alpha, ctx->psi_t.as<double>(), N, st);
         set_psi_sorted(ps, ctx->psi_t.as<double>(), st);
-        ClipStats ct = run_cells(ps, ctx->scp_trial, o.precision, true, st, true);
+        ClipStats ct = pass(ctx->scp_trial, true);
         si.cell_passes += 1;
         si.ls_trials += 1;
         si.overflow_cells += ct.retried - ct.fp64_rerun;

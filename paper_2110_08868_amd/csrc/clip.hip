@@ -74,6 +74,15 @@ struct ClipArgs {
   unsigned long long* stats;  // optional work counters (see CLIP_STATS)
 };
 
+// One launch carries the cell passes of up to kMaxJobs point sets (the
+// concurrent requests of the server, or a single pass); job j owns the
+// workgroups [blk_start[j], blk_start[j + 1]), 8 per_xcd of them.
+struct ClipBatch {
+  ClipArgs job[kMaxJobs];
+  int64_t blk_start[kMaxJobs + 1];
+  int32_t njobs;
+};
+
 // Work counters of the clip kernel (optional): sites scanned, planes tested
 // against the vertices, vertex tests, cuts, new vertices, ball updates (in
 // vertices), box tests, final vertices, reported faces, cells.
@@ -172,7 +181,7 @@ __constant__ int kNearOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1, 7, 19, 25, 3, 5
                                    9, 11, 15, 17, 0, 2, 6, 8, 18, 20, 24, 26};
 
 template <int TPL, typename R, bool STATS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_clip(ClipArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_clip(ClipBatch B) {
   constexpr bool kF64 = sizeof(R) == 8;
   constexpr int PCAP = ClipLDS<TPL, R>::PCAP;
   constexpr int TCAP = ClipLDS<TPL, R>::TCAP;
@@ -182,9 +191,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   __shared__ ClipLDS<TPL, R> S;
 
   const int lane = threadIdx.x;
-  // linear workgroup id (2-D grid above 2^16 items; gridDim.x is a multiple
-  // of 8, so blk & 7 is still the XCD the workgroup runs on)
-  const int64_t blk = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+  // linear workgroup id (2-D grid above 2^16 workgroups; gridDim.x and every
+  // job's first workgroup are multiples of 8, so blk & 7 is still the XCD
+  // the workgroup runs on)
+  const int64_t gblk = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+  if (gblk >= B.blk_start[B.njobs]) return;
+  int jb = 0;
+  while (jb + 1 < B.njobs && gblk >= B.blk_start[jb + 1]) ++jb;
+  const ClipArgs& A = B.job[jb];
+  const int64_t blk = gblk - B.blk_start[jb];
   if ((blk >> 3) >= A.per_xcd) return;
   const int64_t item = (blk & 7) * A.per_xcd + (blk >> 3);
   if (item >= A.nwork) return;
@@ -1051,36 +1066,131 @@ double clip_bytes(const unsigned long long* c) {
 }
 
 template <int TPL, typename R>
-void launch_clip(ClipArgs& a, CellPass& out, int64_t items, hipStream_t st) {
+void launch_clip(ClipBatch& b, CellPass* const* outs, hipStream_t st) {
   Profiler* pr = g_prof;
   const bool counting = pr && pr->counting;
-  if (counting) {
-    a.stats = out.counters.as<unsigned long long>() + 4;
-    MAK_HIP(hipMemsetAsync(a.stats, 0, ST_N * sizeof(unsigned long long), st));
+  int64_t items = 0;
+  for (int j = 0; j < b.njobs; ++j) {
+    items += b.job[j].nwork;
+    if (counting) {
+      b.job[j].stats = outs[j]->counters.as<unsigned long long>() + 4;
+      MAK_HIP(hipMemsetAsync(b.job[j].stats, 0, ST_N * sizeof(unsigned long long), st));
+    }
   }
   const char* name = sizeof(R) == 4 ? "clip_f32" : (TPL == 2 ? "clip" : "clip_large");
   ProfScope ps(name, st, double(items));
   // one 64-lane workgroup per item; the work-items of one grid dimension
-  // must stay below 2^32, so passes above 2^16 items use a 2-D grid of rows
-  // of 2^16 workgroups
-  const int64_t nblk = 8 * a.per_xcd;
+  // must stay below 2^32, so launches above 2^16 workgroups use a 2-D grid of
+  // rows of 2^16 workgroups
+  const int64_t nblk = b.blk_start[b.njobs];
   const int64_t gx = nblk < (int64_t(1) << 16) ? nblk : (int64_t(1) << 16);
   const dim3 grid(unsigned(gx), unsigned(ceil_div(nblk, gx)));
   if (counting)
-    hipLaunchKernelGGL((k_clip<TPL, R, true>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_clip<TPL, R, true>), grid, dim3(64), 0, st, b);
   else
-    hipLaunchKernelGGL((k_clip<TPL, R, false>), grid, dim3(64), 0, st, a);
+    hipLaunchKernelGGL((k_clip<TPL, R, false>), grid, dim3(64), 0, st, b);
   MAK_HIP(hipGetLastError());
   if (counting) {
-    unsigned long long c[ST_N];
-    MAK_HIP(hipMemcpyAsync(c, a.stats, sizeof(c), hipMemcpyDeviceToHost, st));
-    MAK_HIP(hipStreamSynchronize(st));
-    ps.flops = clip_flops(c);
-    ps.bytes = clip_bytes(c);
-    for (int k = 0; k < ST_N; ++k) pr->counters[k] += double(c[k]);
+    double flops = 0, bytes = 0;
+    for (int j = 0; j < b.njobs; ++j) {
+      unsigned long long c[ST_N];
+      MAK_HIP(hipMemcpyAsync(c, b.job[j].stats, sizeof(c), hipMemcpyDeviceToHost, st));
+      MAK_HIP(hipStreamSynchronize(st));
+      flops += clip_flops(c);
+      bytes += clip_bytes(c);
+      for (int k = 0; k < ST_N; ++k) pr->counters[k] += double(c[k]);
+      b.job[j].stats = nullptr;
+    }
+    ps.flops = flops;
+    ps.bytes = bytes;
   }
   ps.stop();
+}
+
+}  // namespace
+
+namespace {
+
+// Stages: every cell runs in the first kernel; the cells it could not finish
+// (capacity, inconsistent cut, float32 ambiguity) go to the next.
+//   float64: <2 vertices per lane, f64>  ->  <4, f64, wider tie tolerance>
+//   mixed:   <2, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
+// counters of a pass: [0] overflow faces used, [1 + s] cells listed by stage
+// s, [4..4 + ST_N) work counters, [32 + 3 s ..] causes (capacity, cut,
+// ambiguity)
+int num_stages(int precision) { return precision == MAK_MIXED ? 3 : 2; }
+
+void job_begin(PassJob& jb, hipStream_t st) {
+  CellPass& out = *jb.out;
+  MAK_HIP(hipMemsetAsync(out.counters.p, 0, 64 * sizeof(unsigned long long), st));
+  jb.stage = 0;
+  jb.listed = jb.ps->N;
+  jb.cs = ClipStats();
+}
+
+ClipArgs job_args(PassJob& jb, int stage, int nstage) {
+  PointSet& ps = *jb.ps;
+  CellPass& out = *jb.out;
+  FaceStore& fst = out.fs();
+  const int64_t N = ps.N;
+  unsigned long long* ctr = out.counters.as<unsigned long long>();
+  ClipArgs a{};
+  a.pts = ps.pts.as<double4>();
+  a.cell_start = ps.cell_start.as<int32_t>();
+  a.cell_psimax = ps.cell_psimax.as<double>();
+  a.block_psimax = ps.block_psimax.as<double>();
+  a.block_suffix = ps.block_suffix.as<double>();
+  a.gmax = ps.scal.as<double>();
+  a.Gn = ps.g.Gn;
+  a.Gb = ps.g.Gb;
+  a.L = ps.g.L;
+  a.h = ps.g.h;
+  a.vol = out.vol.as<double>();
+  a.mom = out.mom.as<double>();
+  a.cflags = out.cflags.as<int32_t>();
+  a.nface = out.nface.as<int32_t>();
+  a.faces = jb.faces ? fst.faces.as<FaceRec>() : nullptr;
+  a.fbase = jb.faces ? fst.fbase.as<int64_t>() : nullptr;
+  a.ovf = jb.faces ? fst.ovf.as<FaceRec>() : nullptr;
+  a.ovf_used = ctr;
+  a.ovf_cap = jb.faces ? fst.ovf_cap : 0;
+  a.fslot = fst.fslot;
+  a.write_faces = jb.faces ? 1 : 0;
+  const double spacing = ps.g.L / std::cbrt(double(N));
+  a.area_min = 1e-12 * spacing * spacing;
+  a.tol_rel = 1e-6;
   a.stats = nullptr;
+  a.work = stage == 0 ? nullptr : out.retry.as<int32_t>() + (stage - 1) * N;
+  a.nwork = jb.listed;
+  a.per_xcd = ceil_div(jb.listed, 8);
+  a.retry = out.retry.as<int32_t>() + stage * N;
+  a.retry_count = ctr + 1 + stage;
+  a.cause = ctr + 32 + 3 * stage;
+  a.eps_rel = stage == nstage - 1 ? 1e-11 : 1e-13;
+  return a;
+}
+
+// One launch of stage `stage` over jobs[0..n).
+void launch_stage(PassJob* const* jobs, int n, int stage, int precision, hipStream_t st) {
+  const int nstage = num_stages(precision);
+  ClipBatch b{};
+  CellPass* outs[kMaxJobs];
+  b.njobs = n;
+  int64_t nb = 0;
+  for (int j = 0; j < n; ++j) {
+    b.job[j] = job_args(*jobs[j], stage, nstage);
+    outs[j] = jobs[j]->out;
+    b.blk_start[j] = nb;
+    nb += 8 * b.job[j].per_xcd;
+  }
+  for (int j = n; j <= kMaxJobs; ++j) b.blk_start[j] = nb;
+  const bool mixed = precision == MAK_MIXED;
+  if (mixed && stage == 0)
+    launch_clip<2, float>(b, outs, st);
+  else if (stage < nstage - 1)
+    launch_clip<2, double>(b, outs, st);
+  else
+    launch_clip<4, double>(b, outs, st);
 }
 
 }  // namespace
@@ -1089,104 +1199,103 @@ int32_t face_slots(int64_t N) { return N <= (int64_t(1) << 24) ? 32 : 20; }
 
 static_assert(4 + ST_N <= 32, "work counters overlap the stage causes");
 
-ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                    bool tolerate_failure) {
-  const int64_t N = ps.N;
-  FaceStore& fst = out.fs();
-  fst.fslot = face_slots(N);
-  out.vol.ensure(size_t(N) * sizeof(double));
-  out.mom.ensure(size_t(N) * 3 * sizeof(double));
-  out.cflags.ensure(size_t(N) * sizeof(int32_t));
-  out.nface.ensure(size_t(N) * sizeof(int32_t));
-  out.retry.ensure(size_t(N) * 3 * sizeof(int32_t));
-  out.counters.ensure(64 * sizeof(unsigned long long));
-  if (faces) {
-    fst.faces.ensure(size_t(N) * fst.fslot * sizeof(FaceRec));
-    fst.fbase.ensure(size_t(N) * sizeof(int64_t));
-    if (fst.ovf_cap < 4096 + N / 8) fst.ovf_cap = 4096 + N / 8;
-    fst.ovf.ensure(size_t(fst.ovf_cap) * sizeof(FaceRec));
-  }
-  // Stages: every cell runs in the first kernel; the cells it could not
-  // finish (capacity, inconsistent cut, float32 ambiguity) go to the next.
-  //   float64: <2 vertices per lane, f64>  ->  <4, f64, wider tie tolerance>
-  //   mixed:   <2, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
+void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t st) {
+  const int nstage = num_stages(precision);
   const bool mixed = precision == MAK_MIXED;
-  const int nstage = mixed ? 3 : 2;
-  unsigned long long* ctr = out.counters.as<unsigned long long>();
-  // counters: [0] overflow faces used, [1 + s] cells listed by stage s,
-  // [4..4 + ST_N) work counters, [32 + 3 s ..] causes (capacity, cut, ambiguity)
-  ClipStats cs;
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    MAK_HIP(hipMemsetAsync(out.counters.p, 0, 64 * sizeof(unsigned long long), st));
-    ClipArgs a{};
-    a.pts = ps.pts.as<double4>();
-    a.cell_start = ps.cell_start.as<int32_t>();
-    a.cell_psimax = ps.cell_psimax.as<double>();
-    a.block_psimax = ps.block_psimax.as<double>();
-    a.block_suffix = ps.block_suffix.as<double>();
-    a.gmax = ps.scal.as<double>();
-    a.Gn = ps.g.Gn;
-    a.Gb = ps.g.Gb;
-    a.L = ps.g.L;
-    a.h = ps.g.h;
-    a.vol = out.vol.as<double>();
-    a.mom = out.mom.as<double>();
-    a.cflags = out.cflags.as<int32_t>();
-    a.nface = out.nface.as<int32_t>();
-    a.faces = faces ? fst.faces.as<FaceRec>() : nullptr;
-    a.fbase = faces ? fst.fbase.as<int64_t>() : nullptr;
-    a.ovf = faces ? fst.ovf.as<FaceRec>() : nullptr;
-    a.ovf_used = ctr;
-    a.ovf_cap = faces ? fst.ovf_cap : 0;
-    a.fslot = fst.fslot;
-    a.write_faces = faces ? 1 : 0;
-    const double spacing = ps.g.L / std::cbrt(double(N));
-    a.area_min = 1e-12 * spacing * spacing;
-    a.tol_rel = 1e-6;
-    a.stats = nullptr;
-    int64_t listed = N;  // cells of the current stage
-    bool regrow = false;
-    cs = ClipStats();
-    for (int stg = 0; stg < nstage && listed > 0; ++stg) {
-      a.work = stg == 0 ? nullptr : out.retry.as<int32_t>() + (stg - 1) * N;
-      a.nwork = listed;
-      a.per_xcd = ceil_div(listed, 8);
-      a.retry = out.retry.as<int32_t>() + stg * N;
-      a.retry_count = ctr + 1 + stg;
-      a.cause = ctr + 32 + 3 * stg;
-      const bool last = stg == nstage - 1;
-      a.eps_rel = last ? 1e-11 : 1e-13;
-      if (mixed && stg == 0)
-        launch_clip<2, float>(a, out, listed, st);
-      else if (!last)
-        launch_clip<2, double>(a, out, listed, st);
-      else
-        launch_clip<4, double>(a, out, listed, st);
-      unsigned long long hc[4];
-      MAK_HIP(hipMemcpyAsync(hc, ctr, sizeof(hc), hipMemcpyDeviceToHost, st));
-      MAK_HIP(hipStreamSynchronize(st));
-      if (faces && int64_t(hc[0]) > fst.ovf_cap) {
-        fst.ovf_cap = int64_t(hc[0]) + int64_t(hc[0]) / 4 + 4096;
+  std::vector<PassJob*> live;
+  for (int j = 0; j < njobs; ++j) {
+    PassJob& jb = *jobs[j];
+    jb.status = MAK_OK;
+    jb.err.clear();
+    jb.attempt = 0;
+    try {
+      const int64_t N = jb.ps->N;
+      CellPass& out = *jb.out;
+      FaceStore& fst = out.fs();
+      fst.fslot = face_slots(N);
+      out.vol.ensure(size_t(N) * sizeof(double));
+      out.mom.ensure(size_t(N) * 3 * sizeof(double));
+      out.cflags.ensure(size_t(N) * sizeof(int32_t));
+      out.nface.ensure(size_t(N) * sizeof(int32_t));
+      out.retry.ensure(size_t(N) * 3 * sizeof(int32_t));
+      out.counters.ensure(64 * sizeof(unsigned long long));
+      if (jb.faces) {
+        fst.faces.ensure(size_t(N) * fst.fslot * sizeof(FaceRec));
+        fst.fbase.ensure(size_t(N) * sizeof(int64_t));
+        if (fst.ovf_cap < 4096 + N / 8) fst.ovf_cap = 4096 + N / 8;
         fst.ovf.ensure(size_t(fst.ovf_cap) * sizeof(FaceRec));
-        regrow = true;
-        break;
       }
-      listed = int64_t(hc[1 + stg]);
-      if (stg == 0) cs.retried = listed;
-      if (mixed && stg == 0) cs.fp64_rerun = listed;
-      if (last && listed > 0) {
-        cs.overflow = listed;
-        if (tolerate_failure) return cs;
-        unsigned long long cz[3];
-        MAK_HIP(hipMemcpy(cz, ctr + 32 + 3 * stg, sizeof(cz), hipMemcpyDeviceToHost));
-        MAK_FAIL(MAK_EOVERFLOW, std::to_string(cz[0]) + " cells exceeded the polytope capacity, " +
-                                    std::to_string(cz[1]) + " had inconsistent cuts");
+      job_begin(jb, st);
+      live.push_back(&jb);
+    } catch (const Error& e) {
+      jb.status = e.status;
+      jb.err = e.msg;
+    }
+  }
+  // Rounds: every live job runs its current stage (one launch per stage and
+  // up to kMaxJobs jobs), then the stage counters of all of them are read
+  // back together and each job advances, finishes or restarts.
+  while (!live.empty()) {
+    for (int s = 0; s < nstage; ++s) {
+      std::vector<PassJob*> grp;
+      for (PassJob* jb : live)
+        if (jb->stage == s) grp.push_back(jb);
+      for (size_t k = 0; k < grp.size(); k += kMaxJobs)
+        launch_stage(grp.data() + k, int(std::min<size_t>(kMaxJobs, grp.size() - k)), s, precision, st);
+    }
+    for (PassJob* jb : live)
+      MAK_HIP(hipMemcpyAsync(jb->hc, jb->out->counters.p, sizeof(jb->hc), hipMemcpyDeviceToHost, st));
+    MAK_HIP(hipStreamSynchronize(st));
+    std::vector<PassJob*> next;
+    for (PassJob* jb : live) {
+      const int s = jb->stage;
+      FaceStore& fst = jb->out->fs();
+      try {
+        if (jb->faces && int64_t(jb->hc[0]) > fst.ovf_cap) {
+          // the overflow region was too small: grow it and run the pass again
+          if (++jb->attempt >= 3) MAK_FAIL(MAK_ENOMEM, "face overflow buffer could not be sized");
+          fst.ovf_cap = int64_t(jb->hc[0]) + int64_t(jb->hc[0]) / 4 + 4096;
+          fst.ovf.ensure(size_t(fst.ovf_cap) * sizeof(FaceRec));
+          job_begin(*jb, st);
+          next.push_back(jb);
+          continue;
+        }
+        const int64_t listed = int64_t(jb->hc[1 + s]);
+        if (s == 0) jb->cs.retried = listed;
+        if (mixed && s == 0) jb->cs.fp64_rerun = listed;
+        if (listed == 0) continue;  // finished
+        if (s == nstage - 1) {
+          jb->cs.overflow = listed;
+          if (jb->tolerate) continue;
+          unsigned long long cz[3];
+          MAK_HIP(hipMemcpy(cz, jb->out->counters.as<unsigned long long>() + 32 + 3 * s, sizeof(cz),
+                            hipMemcpyDeviceToHost));
+          MAK_FAIL(MAK_EOVERFLOW, std::to_string(cz[0]) + " cells exceeded the polytope capacity, " +
+                                      std::to_string(cz[1]) + " had inconsistent cuts");
+        }
+        jb->listed = listed;
+        jb->stage = s + 1;
+        next.push_back(jb);
+      } catch (const Error& e) {
+        jb->status = e.status;
+        jb->err = e.msg;
       }
     }
-    if (regrow) continue;
-    return cs;
+    live.swap(next);
   }
-  MAK_FAIL(MAK_ENOMEM, "face overflow buffer could not be sized");
+}
+
+ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
+                    bool tolerate_failure) {
+  PassJob jb;
+  jb.ps = &ps;
+  jb.out = &out;
+  jb.faces = faces;
+  jb.tolerate = tolerate_failure;
+  PassJob* one = &jb;
+  run_cells_batch(&one, 1, precision, st);
+  if (jb.status != MAK_OK) MAK_FAIL(jb.status, jb.err);
+  return jb.cs;
 }
 
 }  // namespace mak

@@ -2,9 +2,12 @@
 // pass kernels (grid build, clip, CSR assembly, PCG).
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "common.h"
+
+struct mak_ctx;
 
 namespace mak {
 
@@ -144,6 +147,36 @@ struct ClipStats {
 // is then rejected).
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
                     bool tolerate_failure = false);
+
+// Cell passes of several point sets in shared launches (the serving form):
+// each job runs its stages like run_cells, but every stage launch carries up
+// to kMaxJobs jobs.  Errors are reported per job (status / err), not thrown.
+constexpr int kMaxJobs = 8;
+struct PassJob {
+  PointSet* ps = nullptr;
+  CellPass* out = nullptr;
+  bool faces = true;
+  bool tolerate = false;
+  // results
+  ClipStats cs;
+  mak_status status = MAK_OK;
+  std::string err;
+  // progress (driver-internal)
+  int stage = 0, attempt = 0;
+  int64_t listed = 0;
+  unsigned long long hc[4] = {0, 0, 0, 0};
+};
+void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t st);
+
+// Who runs the cell passes of a solve: by default the solve's own stream
+// (run_cells); the server substitutes its batcher, which packs the passes of
+// concurrent requests into shared launches.
+struct PassRunner {
+  virtual ~PassRunner() = default;
+  virtual ClipStats run(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
+                        bool tolerate_failure) = 0;
+};
+void set_pass_runner(::mak_ctx* ctx, PassRunner* r);
 
 // --- csr.hip
 // Assemble J (sorted index space, or original space when perm != NULL).

@@ -23,8 +23,95 @@
 #include <vector>
 
 #include "../../include/mak.h"
+#include "engine.h"
 
 namespace {
+
+// Packs the cell passes that solves post into shared launches.
+struct PassBatcher final : mak::PassRunner {
+  struct Posted {
+    mak::PassJob job;
+    bool done = false;
+  };
+  int device = 0;
+  int precision = MAK_FP64;
+  std::mutex mu;
+  std::condition_variable cv_post, cv_done;
+  std::deque<Posted*> posted;
+  bool stopping = false;
+  int64_t batches = 0, passes = 0;
+  int32_t max_batch = 0;
+  std::thread th;
+
+  void start(int dev, int prec) {
+    device = dev;
+    precision = prec;
+    th = std::thread([this] { loop(); });
+  }
+  void stop() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stopping = true;
+    }
+    cv_post.notify_all();
+    if (th.joinable()) th.join();
+  }
+  void loop() {
+    (void)hipSetDevice(device);
+    hipStream_t st = nullptr;
+    (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    std::vector<Posted*> take;
+    std::vector<mak::PassJob*> jobs;
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_post.wait(lk, [&] { return stopping || !posted.empty(); });
+        if (posted.empty()) break;  // stopping with nothing posted
+        take.assign(posted.begin(), posted.end());
+        posted.clear();
+      }
+      jobs.clear();
+      for (Posted* p : take) jobs.push_back(&p->job);
+      try {
+        mak::run_cells_batch(jobs.data(), int(jobs.size()), precision, st);
+      } catch (const mak::Error& e) {  // a device error: every job of the batch fails
+        for (mak::PassJob* j : jobs) {
+          j->status = e.status;
+          j->err = e.msg;
+        }
+      }
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        for (Posted* p : take) p->done = true;
+        ++batches;
+        passes += int64_t(take.size());
+        if (int32_t(take.size()) > max_batch) max_batch = int32_t(take.size());
+      }
+      cv_done.notify_all();
+    }
+    if (st) (void)hipStreamDestroy(st);
+  }
+  // Called by a solve on its worker thread.
+  mak::ClipStats run(mak::PointSet& ps, mak::CellPass& out, int prec, bool faces, hipStream_t st,
+                     bool tolerate) override {
+    if (prec != precision) MAK_FAIL(MAK_EINVAL, "pass precision differs from the server's");
+    // the solve's own stream wrote the weights: they must be on the device
+    MAK_HIP(hipStreamSynchronize(st));
+    Posted p;
+    p.job.ps = &ps;
+    p.job.out = &out;
+    p.job.faces = faces;
+    p.job.tolerate = tolerate;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      posted.push_back(&p);
+      cv_post.notify_all();
+      cv_done.wait(lk, [&] { return p.done; });
+    }
+    if (p.job.status != MAK_OK) MAK_FAIL(p.job.status, p.job.err);
+    return p.job.cs;
+  }
+};
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -64,6 +151,7 @@ struct mak_server {
   bool stopping = false;
   std::vector<std::thread> workers;
   std::string err;
+  PassBatcher batcher;
 
   void worker(int32_t slot) {
     (void)hipSetDevice(device);
@@ -99,6 +187,7 @@ struct mak_server {
       }
       if (!ctx) {
         if (mak_create(&ctx, device, &opt) != MAK_OK) ctx = nullptr;
+        if (ctx) mak::set_pass_runner(ctx, &batcher);
         ctx_est = 0;
       }
       if (r->est > ctx_est) ctx_est = r->est;
@@ -145,6 +234,7 @@ mak_status mak_server_create(mak_server** out, int device, const mak_options* op
   if (opt) s->opt = *opt;
   s->budget = mem_budget_bytes ? mem_budget_bytes : ~size_t(0);
   s->slots = max_slots;
+  s->batcher.start(device, s->opt.precision);
   for (int32_t k = 0; k < max_slots; ++k) s->workers.emplace_back([s, k] { s->worker(k); });
   *out = s;
   return MAK_OK;
@@ -237,6 +327,12 @@ mak_status mak_server_stats(mak_server* s, mak_server_info* out) {
   out->used_bytes = s->used;
   out->peak_used_bytes = s->peak_used;
   out->budget_bytes = s->budget;
+  {
+    std::lock_guard<std::mutex> lb(s->batcher.mu);
+    out->pass_batches = s->batcher.batches;
+    out->batched_passes = s->batcher.passes;
+    out->max_batch = s->batcher.max_batch;
+  }
   return MAK_OK;
 }
 
@@ -250,6 +346,7 @@ void mak_server_destroy(mak_server* s) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->workers) t.join();
+  s->batcher.stop();
   delete s;
 }
 

@@ -31,6 +31,8 @@ def test_same_alone_and_in_the_mix():
     st = srv.stats()
     print("  server stats", st, flush=True)
     assert st["completed"] == len(xs) and st["peak_active"] >= 2
+    # the cell passes of concurrent requests shared launches
+    assert st["max_batch"] >= 2 and st["batched_passes"] > st["pass_batches"]
     srv.close()
 
 
