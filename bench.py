@@ -298,7 +298,8 @@ def main():
     ap.add_argument("--cg-rtol", type=float, default=1e-3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--verbose", type=int, nargs="?", const=1, default=0,
+                    help="solver log on stderr: 1 per Newton iteration, 2 also per line-search trial")
     ap.add_argument("--no-counting", action="store_true",
                     help="skip the extra solve with the clip kernel's work counters")
     ap.add_argument("--oracle-sample", type=int, default=64,
@@ -337,7 +338,9 @@ def main():
     secs, infos, prof, cprof, out = timed_solves(mak, x_dev, L, tol, precision, args.steps,
                                                  args.warmup, args.cg_rtol, int(args.verbose),
                                                  counting=not args.no_counting)
-    passes = sum(i["cell_passes"] for i in infos)
+    # cells of complete passes only: a line-search trial abandoned at its
+    # first cell below eps0 counts as no cells
+    passes = sum(i["cell_passes"] - i["abandoned_trials"] for i in infos)
     value = N * passes / secs
     rl, share = roofline(prof, cprof, args.workload)
     res = {
@@ -357,6 +360,7 @@ def main():
                    **{k: v for k, v in spec.items()}, "cg_rtol": args.cg_rtol},
         "solve": {"seconds_median": float(np.median([i["seconds"] for i in infos])),
                   "newton_iters": infos[-1]["newton_iters"], "cell_passes": infos[-1]["cell_passes"],
+                  "abandoned_trials": infos[-1]["abandoned_trials"],
                   "cg_iters": infos[-1]["cg_iters_total"], "final_err": infos[-1]["final_err"]},
         "kernel_ms_total": share,
         "device_mem_used_gb": prof.get("_device_mem_used_gb"),
@@ -369,7 +373,7 @@ def main():
     if other not in ("none", precision):
         s2, inf2, p2, c2, out2 = timed_solves(mak, x_dev, L, tol, other, max(1, args.steps), 0,
                                               args.cg_rtol)
-        res[other] = {"cells_per_s": N * sum(i["cell_passes"] for i in inf2) / s2,
+        res[other] = {"cells_per_s": N * sum(i["cell_passes"] - i["abandoned_trials"] for i in inf2) / s2,
                       "ms_per_solve": s2 / len(inf2) * 1e3,
                       "newton_iters": inf2[-1]["newton_iters"], "final_err": inf2[-1]["final_err"],
                       "fp64_rerun_cells": inf2[-1]["fp64_rerun_cells"]}

@@ -60,7 +60,7 @@ typedef struct {
   double cg_rtol;          /* CG stop: ||r|| <= cg_rtol ||g||, default 1e-3 */
   double grid_occupancy;   /* target sites per neighbour-grid cell, default 2.5 */
   size_t mem_budget_bytes; /* 0 = no limit (server admission uses it) */
-  int32_t verbose;         /* 1: one line per Newton iteration on stderr */
+  int32_t verbose;         /* 1: one line per Newton iteration on stderr, 2: also per trial */
   int32_t reserved[7];
 } mak_options;
 
@@ -76,6 +76,9 @@ typedef struct {
   int64_t overflow_cells;     /* cells re-run with the large polytope capacity */
   double final_err;           /* max_i |V_i - m_i| / m_i at exit */
   double seconds;             /* wall time of the call */
+  int32_t abandoned_trials;   /* line-search passes stopped at the first cell
+                                 below eps0 (rejected whatever the rest gives) */
+  int32_t reserved;
 } mak_solve_info;
 
 typedef struct {
@@ -182,8 +185,9 @@ int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entr
 /* HOST double[16]: summed clip work counters (sites scanned, planes tested,
  * vertex tests, cuts, new vertices, ball-update vertices, box tests, final
  * vertices, faces, cells), then shader-clock cycles summed over waves spent
- * in the candidate search, the serial clipping and the integrals; unused
- * entries are zero. */
+ * in the candidate search, the serial clipping and the integrals, and within
+ * those in the batch pre-filter (part of the search) and in the cuts that
+ * removed vertices (part of the clipping); unused entries are zero. */
 mak_status mak_profile_counters(mak_ctx* ctx, double* out);
 
 /* ---- serving: many reconstruction requests on one device ----

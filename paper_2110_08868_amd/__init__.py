@@ -56,6 +56,7 @@ class _SolveInfo(ctypes.Structure):
         ("ls_trials", ctypes.c_int32), ("cell_passes", ctypes.c_int32),
         ("fp64_rerun_cells", ctypes.c_int64), ("overflow_cells", ctypes.c_int64),
         ("final_err", ctypes.c_double), ("seconds", ctypes.c_double),
+        ("abandoned_trials", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -77,7 +78,8 @@ class _KernelProfile(ctypes.Structure):
 
 COUNTER_NAMES = ["sites_scanned", "planes_tested", "vertex_tests", "cuts", "new_vertices",
                  "ball_vertices", "box_tests", "final_vertices", "faces", "cells",
-                 "cycles_search", "cycles_clip", "cycles_integrals"]
+                 "cycles_search", "cycles_clip", "cycles_integrals", "cycles_prefilter",
+                 "cycles_cuts"]
 
 
 class _ServerStats(ctypes.Structure):

@@ -307,12 +307,12 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       MAK_HIP(hipMemsetAsync(psi_s, 0, size_t(N) * sizeof(double), st));
     const double m = L * L * L / double(N);
 
-    auto pass = [&](CellPass& cp, bool tolerate) {
-      return ctx->runner ? ctx->runner->run(ps, cp, o.precision, true, st, tolerate)
-                         : run_cells(ps, cp, o.precision, true, st, tolerate);
+    auto pass = [&](CellPass& cp, bool tolerate, double doom_vol) {
+      return ctx->runner ? ctx->runner->run(ps, cp, o.precision, true, st, tolerate, doom_vol)
+                         : run_cells(ps, cp, o.precision, true, st, tolerate, doom_vol);
     };
     set_psi_sorted(ps, psi_s, st);
-    ClipStats cs = pass(ctx->scp, false);
+    ClipStats cs = pass(ctx->scp, false, 0.0);
     si.cell_passes = 1;
     si.overflow_cells += cs.retried - cs.fp64_rerun;
     si.fp64_rerun_cells += cs.fp64_rerun;
@@ -339,17 +339,36 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       for (int ls = 0; ls <= o.max_halvings; ++ls) {
         axpy_into(ctx->psi_s.as<double>(), ctx->pstep.as<double>(), alpha, ctx->psi_t.as<double>(), N, st);
         set_psi_sorted(ps, ctx->psi_t.as<double>(), st);
-        ClipStats ct = pass(ctx->scp_trial, true);
+        const auto tp0 = std::chrono::steady_clock::now();
+        // a trial with a cell below eps0 is rejected whatever else it gives:
+        // the pass stops at the first such cell
+        ClipStats ct = pass(ctx->scp_trial, true, eps0);
         si.cell_passes += 1;
         si.ls_trials += 1;
+        if (ct.doomed) {
+          si.abandoned_trials += 1;
+          if (o.verbose >= 2)
+            fprintf(stderr, "[mak]   trial alpha=%g pass %.1f ms: a cell below eps0, abandoned\n", alpha,
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());
+          alpha *= 0.5;
+          continue;
+        }
         si.overflow_cells += ct.retried - ct.fp64_rerun;
         si.fp64_rerun_cells += ct.fp64_rerun;
         if (ct.overflow > 0) {  // cells beyond the polytope capacity: reject the trial
+          if (o.verbose >= 2)
+            fprintf(stderr, "[mak]   trial alpha=%g pass %.1f ms: %lld cells over capacity\n", alpha,
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count(),
+                    (long long)ct.overflow);
           alpha *= 0.5;
           continue;
         }
         double e2 = 0, v2 = 0;
         const double g2 = residual_stats(ctx->scp_trial.vol.as<double>(), m, N, ctx->tmp, &e2, &v2, st);
+        if (o.verbose >= 2)
+          fprintf(stderr, "[mak]   trial alpha=%g pass %.1f ms retried=%lld: err=%.3e |g| %.3e -> %.3e minV/m=%.3e\n",
+                  alpha, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count(),
+                  (long long)ct.retried, e2, gn, g2, v2 / m);
         if (v2 >= eps0 && g2 <= (1.0 - 0.5 * alpha) * gn) {
           swap_buf(ctx->psi_s, ctx->psi_t);
           swap_pass(ctx->scp, ctx->scp_trial);

@@ -39,6 +39,11 @@
 #include "gridkey.h"
 #include "profile.h"
 
+// Products and sums in this file may fuse into FMAs (one rounding instead of
+// two; fewer instructions).  The tie tolerances and the float32 ambiguity
+// band bound the rounding of the unfused forms, so they hold.
+#pragma clang fp contract(fast)
+
 namespace mak {
 
 namespace {
@@ -72,6 +77,11 @@ struct ClipArgs {
   double eps_rel;  // float64 tie tolerance (relative to the grid cell side)
   double tol_rel;  // float32 ambiguity band (relative to |v||d| + |b|)
   unsigned long long* stats;  // optional work counters (see CLIP_STATS)
+  // Line-search trials: a cell whose volume ends below doom_vol (or empty)
+  // rejects the trial; it raises *doom and the workgroups that start after
+  // it skip their cell (the host discards the pass).  doom == NULL: off.
+  unsigned int* doom;
+  double doom_vol;
 };
 
 // One launch carries the cell passes of up to kMaxJobs point sets (the
@@ -90,7 +100,7 @@ struct ClipBatch {
 // candidate search (grid walk, site loads, batch filter and sort), serial
 // clipping, integrals and output.
 enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS,
-       ST_TSEARCH, ST_TCLIP, ST_TINT, ST_N };
+       ST_TSEARCH, ST_TCLIP, ST_TINT, ST_TPRE, ST_TCUT, ST_N };
 
 // Final vertices in float64 (the float32 path recomputes them from their
 // three planes before integrating; the float64 path integrates its own).
@@ -120,9 +130,6 @@ struct ClipLDS {
   int32_t cstart[64];
   int32_t cpre[64];
   int32_t cshift[64];
-  double4 cand[64];   // planes of the current batch of sites (by lane)
-  int32_t candj[64];
-  int32_t cands[64];
 };
 
 __device__ __forceinline__ uint32_t tri_pack(int a, int b, int c) {
@@ -176,6 +183,17 @@ __device__ __forceinline__ void shell_offset(int r, int t, int& ox, int& oy, int
   oy = rem % I - (r - 1);
 }
 
+// Shader clock for the counting variant's phase timers: waits for the
+// wave's outstanding memory operations first, so their latency is charged to
+// the phase that issued them, and keeps the compiler from moving memory
+// operations across the stamp.
+__device__ __forceinline__ uint64_t clock_stamp() {
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+  const uint64_t t = __builtin_amdgcn_s_memtime();
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  return t;
+}
+
 // The 27 neighbour cells (code = (ox+1)*9 + (oy+1)*3 + (oz+1)) by distance class.
 __constant__ int kNearOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1, 7, 19, 25, 3, 5, 21, 23,
                                    9, 11, 15, 17, 0, 2, 6, 8, 18, 20, 24, 26};
@@ -203,6 +221,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   if ((blk >> 3) >= A.per_xcd) return;
   const int64_t item = (blk & 7) * A.per_xcd + (blk >> 3);
   if (item >= A.nwork) return;
+  if (A.doom && __hip_atomic_load(A.doom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const int32_t p = A.work ? A.work[item] : int32_t(item);
 
   const double4 me = A.pts[p];
@@ -217,8 +236,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   bool dead = false;
   // work counters (compiled in only for the counting variant)
   uint32_t c_cand = 0, c_test = 0, c_vt = 0, c_cut = 0, c_newv = 0, c_ball = 0, c_box = 0, c_pre = 0;
-  uint64_t t_begin = 0, t_clip = 0, t_search_end = 0;
-  if (STATS) t_begin = __builtin_amdgcn_s_memtime();
+  uint64_t t_begin = 0, t_clip = 0, t_search_end = 0, t_pre = 0, t_cut = 0;
+  if (STATS) t_begin = clock_stamp();
 #define CNT(stmt)  \
   do {             \
     if (STATS) {   \
@@ -381,8 +400,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   };
 
   // Clip by u . d <= bb (plane tag jj / ss).
-  auto clip_one = [&](double ddx, double ddy, double ddz, double dbb, int32_t jj, int32_t ss) {
-    const double dnd = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+  auto clip_one = [&](double ddx, double ddy, double ddz, double dbb, double dnd, int32_t jj,
+                      int32_t ss) {
     const double cd = double(bcx) * ddx + double(bcy) * ddy + double(bcz) * ddz;
     if (cd + double(brho) * dnd <= dbb - mtol) return;  // cannot reach the ball
     const R dx = R(ddx), dy = R(ddy), dz = R(ddz), bb = R(dbb);
@@ -412,6 +431,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       return;
     }
     if (nout == 0) return;
+    uint64_t tk0 = 0;
+    if (STATS) tk0 = clock_stamp();
     if (nout == nT) {
       flags |= CF_EMPTY;
       dead = true;
@@ -557,6 +578,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       }
     }
     ball_dirty = true;  // the ball is refreshed lazily (a stale ball is still a bound)
+    if (STATS) t_cut += clock_stamp() - tk0;
   };
 
   auto refresh_ball = [&]() {
@@ -640,31 +662,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         // a vertex within the ambiguity band are kept for the serial test.)
         const R eps = kF64 ? R(eps_scale * dn) : -tol_rel * (R(rvert) * R(dn) + fabs(rbb));
         bool cut = false;
+        uint64_t tp0 = 0;
+        if (STATS) tp0 = clock_stamp();
 #pragma unroll 1
         for (int v = 0; v < nT; ++v) {
           const R ux = S.sx[v], uy = S.sy[v], uz = S.sz[v];
           cut |= ux * rx + uy * ry + uz * rz - rbb > eps;
         }
         CNT(c_pre += uint32_t(nT));
+        if (STATS) t_pre += clock_stamp() - tp0;
         may = may && cut;
         if (!may) key = 0xffffffffu;
         ns = __popcll(ballot(may));
         if (ns == 0) continue;
       }
       key = wave_sort_u32(key);
-      // park the batch in LDS: the serial loop reads one plane at a time
-      S.cand[lane] = make_double4(dx, dy, dz, bb);
-      S.candj[lane] = q;
-      S.cands[lane] = shv;
-      __syncthreads();
       uint64_t tc0 = 0;
-      if (STATS) tc0 = __builtin_amdgcn_s_memtime();
+      if (STATS) tc0 = clock_stamp();
+      // the serial loop broadcasts one candidate at a time from its lane
       for (int r = 0; r < ns && !dead; ++r) {
         const int src = int(readlane_u(key, r) & 63u);
-        const double4 C = S.cand[src];
-        clip_one(C.x, C.y, C.z, C.w, S.candj[src], S.cands[src]);
+        clip_one(readlane_d(dx, src), readlane_d(dy, src), readlane_d(dz, src), readlane_d(bb, src),
+                 readlane_d(dn, src), readlane_i(q, src), readlane_i(shv, src));
       }
-      if (STATS) t_clip += __builtin_amdgcn_s_memtime() - tc0;
+      if (STATS) t_clip += clock_stamp() - tc0;
       __syncthreads();
     }
     __syncthreads();
@@ -825,14 +846,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
   }
 
-  if (STATS) t_search_end = __builtin_amdgcn_s_memtime();
+  if (STATS) t_search_end = clock_stamp();
   auto flush_stats = [&](int ntri, int nfaces) {
     if (STATS && A.stats && lane == 0) {
       unsigned long long* st = A.stats;
-      const uint64_t t_end = __builtin_amdgcn_s_memtime();
+      const uint64_t t_end = clock_stamp();
       atomicAdd(&st[ST_TSEARCH], (unsigned long long)(t_search_end - t_begin - t_clip));
       atomicAdd(&st[ST_TCLIP], (unsigned long long)t_clip);
       atomicAdd(&st[ST_TINT], (unsigned long long)(t_end - t_search_end));
+      atomicAdd(&st[ST_TPRE], (unsigned long long)t_pre);
+      atomicAdd(&st[ST_TCUT], (unsigned long long)t_cut);
       atomicAdd(&st[ST_CAND], (unsigned long long)c_cand);
       atomicAdd(&st[ST_TEST], (unsigned long long)c_test);
       atomicAdd(&st[ST_VTEST], (unsigned long long)(c_vt + c_pre));
@@ -849,6 +872,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   if (dead) {
     flush_stats(0, 0);
     if (lane == 0) {
+      if (A.doom && (flags & CF_EMPTY) &&
+          !(flags & (CF_CAPACITY | CF_NONMANIFOLD | CF_NEARDEG)))
+        __hip_atomic_store(A.doom, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (flags & (CF_CAPACITY | CF_NONMANIFOLD | CF_NEARDEG)) {
         atomicAdd(&A.cause[(flags & CF_CAPACITY) ? 0 : ((flags & CF_NONMANIFOLD) ? 1 : 2)], 1ull);
         const unsigned long long r = atomicAdd(A.retry_count, 1ull);
@@ -1039,6 +1065,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   }
   flush_stats(nT, nf);
   if (lane == 0) {
+    if (A.doom && v6 / 6.0 < A.doom_vol)
+      __hip_atomic_store(A.doom, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     A.vol[p] = v6 / 6.0;
     A.mom[3 * p] = m0 / 24.0;
     A.mom[3 * p + 1] = m1 / 24.0;
@@ -1073,7 +1101,7 @@ void launch_clip(ClipBatch& b, CellPass* const* outs, hipStream_t st) {
   for (int j = 0; j < b.njobs; ++j) {
     items += b.job[j].nwork;
     if (counting) {
-      b.job[j].stats = outs[j]->counters.as<unsigned long long>() + 4;
+      b.job[j].stats = outs[j]->counters.as<unsigned long long>() + 8;
       MAK_HIP(hipMemsetAsync(b.job[j].stats, 0, ST_N * sizeof(unsigned long long), st));
     }
   }
@@ -1116,8 +1144,8 @@ namespace {
 //   float64: <2 vertices per lane, f64>  ->  <4, f64, wider tie tolerance>
 //   mixed:   <2, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
 // counters of a pass: [0] overflow faces used, [1 + s] cells listed by stage
-// s, [4..4 + ST_N) work counters, [32 + 3 s ..] causes (capacity, cut,
-// ambiguity)
+// s, [4] doom flag of a line-search trial, [8..8 + ST_N) work counters,
+// [32 + 3 s ..] causes (capacity, cut, ambiguity)
 int num_stages(int precision) { return precision == MAK_MIXED ? 3 : 2; }
 
 void job_begin(PassJob& jb, hipStream_t st) {
@@ -1167,6 +1195,8 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.retry_count = ctr + 1 + stage;
   a.cause = ctr + 32 + 3 * stage;
   a.eps_rel = stage == nstage - 1 ? 1e-11 : 1e-13;
+  a.doom = jb.doom_vol > 0 ? reinterpret_cast<unsigned int*>(ctr + 4) : nullptr;
+  a.doom_vol = jb.doom_vol;
   return a;
 }
 
@@ -1197,7 +1227,7 @@ void launch_stage(PassJob* const* jobs, int n, int stage, int precision, hipStre
 
 int32_t face_slots(int64_t N) { return N <= (int64_t(1) << 24) ? 32 : 20; }
 
-static_assert(4 + ST_N <= 32, "work counters overlap the stage causes");
+static_assert(8 + ST_N <= 32, "work counters overlap the stage causes");
 
 void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t st) {
   const int nstage = num_stages(precision);
@@ -1260,6 +1290,10 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
           next.push_back(jb);
           continue;
         }
+        if (jb->hc[4] != 0) {  // a cell below doom_vol: the trial is rejected
+          jb->cs.doomed = true;
+          continue;
+        }
         const int64_t listed = int64_t(jb->hc[1 + s]);
         if (s == 0) jb->cs.retried = listed;
         if (mixed && s == 0) jb->cs.fp64_rerun = listed;
@@ -1286,12 +1320,13 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
 }
 
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                    bool tolerate_failure) {
+                    bool tolerate_failure, double doom_vol) {
   PassJob jb;
   jb.ps = &ps;
   jb.out = &out;
   jb.faces = faces;
   jb.tolerate = tolerate_failure;
+  jb.doom_vol = doom_vol;
   PassJob* one = &jb;
   run_cells_batch(&one, 1, precision, st);
   if (jb.status != MAK_OK) MAK_FAIL(jb.status, jb.err);

@@ -87,7 +87,7 @@ __global__ void k_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* 
 }
 
 // Face lists in original order; the area is the stored weight times |d|,
-// with d formed exactly as the clip kernel forms it.
+// with d formed as the clip kernel forms it (equal to within rounding).
 __global__ void k_face_copy(const FaceRec* faces, const FaceRec* ovf, const int64_t* fbase,
                             int32_t fslot, const int32_t* __restrict__ nface,
                             const int32_t* __restrict__ perm, const double4* __restrict__ pts,

@@ -139,14 +139,18 @@ void update_psi_bounds(PointSet& ps, hipStream_t st);
 // --- clip.hip
 struct ClipStats {
   int64_t retried = 0, overflow = 0, fp64_rerun = 0;
+  bool doomed = false;  // a cell ended below doom_vol: the pass was abandoned
 };
 // Full cell pass at the psi stored in ps.pts[].w.  precision: MAK_FP64 or
 // MAK_MIXED.  Throws on capacity overflow past the large kernel.
 // With `tolerate_failure`, cells the large kernel cannot represent are
 // reported in ClipStats::overflow instead of throwing (a line-search trial
 // is then rejected).
+// With doom_vol > 0 (a line-search trial), the first cell whose volume ends
+// below doom_vol (or empty) abandons the pass: ClipStats::doomed, outputs
+// unspecified.
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                    bool tolerate_failure = false);
+                    bool tolerate_failure = false, double doom_vol = 0.0);
 
 // Cell passes of several point sets in shared launches (the serving form):
 // each job runs its stages like run_cells, but every stage launch carries up
@@ -157,6 +161,7 @@ struct PassJob {
   CellPass* out = nullptr;
   bool faces = true;
   bool tolerate = false;
+  double doom_vol = 0.0;
   // results
   ClipStats cs;
   mak_status status = MAK_OK;
@@ -164,7 +169,7 @@ struct PassJob {
   // progress (driver-internal)
   int stage = 0, attempt = 0;
   int64_t listed = 0;
-  unsigned long long hc[4] = {0, 0, 0, 0};
+  unsigned long long hc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t st);
 
@@ -174,7 +179,7 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
 struct PassRunner {
   virtual ~PassRunner() = default;
   virtual ClipStats run(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                        bool tolerate_failure) = 0;
+                        bool tolerate_failure, double doom_vol) = 0;
 };
 void set_pass_runner(::mak_ctx* ctx, PassRunner* r);
 

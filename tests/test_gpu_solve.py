@@ -82,3 +82,21 @@ def test_resume_from_saved_psi(ctx):
     certificate(x, psi2, 1.0, 1e-9)
     psi3, C3, D3, i3 = gsolve(ctx, x, 1.0, 1e-9)
     assert np.allclose(psi2, psi3, atol=1e-9 / n ** 2)
+
+
+def test_damped_steps_certified(ctx):
+    """A clustered input whose first Newton steps must be damped: line-search
+    trials with a cell below eps0 are abandoned at that cell (they would be
+    rejected whatever the rest of the pass gave), and the solve still lands
+    on the oracle's solution."""
+    n = 12
+    x = workloads.clustered(n, rms=2.0, smooth=1.0, frac=0.2, n_clumps=10, a=0.5, seed=4)
+    psi, C, D, info = gsolve(ctx, x, 1.0, 1e-8)
+    assert info["abandoned_trials"] >= 1
+    assert info["cell_passes"] == 1 + info["ls_trials"]
+    certificate(x, psi, 1.0, 1e-8)
+    s = oracle.solve(x, 1.0, tol=1e-10)
+    dpsi = psi - s["psi"]
+    dpsi -= dpsi.mean()
+    D2 = (1.0 / n) ** 2
+    assert np.sqrt(np.mean(dpsi ** 2)) <= 1e-5 * D2
