@@ -307,12 +307,12 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       MAK_HIP(hipMemsetAsync(psi_s, 0, size_t(N) * sizeof(double), st));
     const double m = L * L * L / double(N);
 
-    auto pass = [&](CellPass& cp, bool tolerate, double doom_vol) {
-      return ctx->runner ? ctx->runner->run(ps, cp, o.precision, true, st, tolerate, doom_vol)
-                         : run_cells(ps, cp, o.precision, true, st, tolerate, doom_vol);
+    auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Csr* warm) {
+      return ctx->runner ? ctx->runner->run(ps, cp, o.precision, true, st, tolerate, doom_vol, warm)
+                         : run_cells(ps, cp, o.precision, true, st, tolerate, doom_vol, warm);
     };
     set_psi_sorted(ps, psi_s, st);
-    ClipStats cs = pass(ctx->scp, false, 0.0);
+    ClipStats cs = pass(ctx->scp, false, 0.0, nullptr);
     si.cell_passes = 1;
     si.overflow_cells += cs.retried - cs.fp64_rerun;
     si.fp64_rerun_cells += cs.fp64_rerun;
@@ -342,7 +342,8 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
         const auto tp0 = std::chrono::steady_clock::now();
         // a trial with a cell below eps0 is rejected whatever else it gives:
         // the pass stops at the first such cell
-        ClipStats ct = pass(ctx->scp_trial, true, eps0);
+        // the accepted pass's neighbours (J) warm-start the trial
+        ClipStats ct = pass(ctx->scp_trial, true, eps0, &ctx->sJ);
         si.cell_passes += 1;
         si.ls_trials += 1;
         if (ct.doomed) {

@@ -51,10 +51,17 @@ namespace {
 struct ClipArgs {
   const double4* pts;
   const int32_t* cell_start;
-  const double* cell_psimax;
-  const double* block_psimax;
   const double* block_suffix;
+  const double* block_g;     // tilted bounds: slope per block (3 doubles)
+  const double* block_tmax;  // max_j psi_j - g . (x_j - block centre) per block
+  const double* cell_tmax;   // the same per cell (with its block's slope)
   const double* gmax;
+  // Optional warm start: the neighbours of each cell in an earlier pass (CSR
+  // rows of J over the same sorted sites).  They are clipped first, so the
+  // polytope is near its final shape before the grid walk; the walk then
+  // meets them again and skips planes already in the table.
+  const int64_t* warm_rp;
+  const int32_t* warm_col;
   int32_t Gn, Gb;
   double L, h;
   const int32_t* work;
@@ -404,6 +411,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
                       int32_t ss) {
     const double cd = double(bcx) * ddx + double(bcy) * ddy + double(bcz) * ddz;
     if (cd + double(brho) * dnd <= dbb - mtol) return;  // cannot reach the ball
+    if (A.warm_rp) {
+      // with a warm start the walk meets the warm planes again: a plane
+      // already in the table is not applied twice
+      bool same = false;
+#pragma unroll
+      for (int c = 0; c < NPC; ++c) {
+        const int f = c * 64 + lane;
+        same = same || (f < nP && S.pj[f] == jj && S.ps[f] == ss);
+      }
+      if (ballot(same)) return;
+    }
     const R dx = R(ddx), dy = R(ddy), dz = R(ddz), bb = R(dbb);
     // float64: out iff s > eps.  float32: out iff s > tol; |s| <= tol is
     // ambiguous at this precision and sends the cell to the float64 kernel.
@@ -588,18 +606,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
   };
 
-  // Could a site with weight <= wmax inside the seed-local box [lo, hi] cut
-  // the ball (c, rho)?  Needs c.d + rho|d| > |d|^2/2 + psi_i - psi_j.
+  // Could a site of the seed-local box [lo, hi] cut the ball (c, rho)?  It
+  // needs c.d + rho|d| > |d|^2/2 + psi_i - psi_j.  The box lies in block
+  // (ubx, uby, ubz) (unwrapped; key bkey) whose sites obey the tilted bound
+  // psi_j <= tmax + g . (d - D), D the block centre (seed-local): then a cut
+  // needs |d|^2/2 - rho|d| - d.(c + g) < tmax - g.D - psi_i, and the left
+  // side is bounded below over the box.
+  const double bh = BLOCK_SIDE * h;
   auto box_may_cut = [&](double lx, double ly, double lz, double hx, double hy, double hz,
-                         double wmax) -> bool {
+                         int64_t bkey, int ubx, int uby, int ubz, double tmax) -> bool {
+    const double gx = A.block_g[3 * bkey], gy = A.block_g[3 * bkey + 1], gz = A.block_g[3 * bkey + 2];
+    const double Dx = (ubx + 0.5) * bh - xi, Dy = (uby + 0.5) * bh - yi, Dz = (ubz + 0.5) * bh - zi;
+    const double wmax = tmax - (gx * Dx + gy * Dy + gz * Dz);
     const double mx = lx > 0 ? lx : (hx < 0 ? -hx : 0.0);
     const double my = ly > 0 ? ly : (hy < 0 ? -hy : 0.0);
     const double mz = lz > 0 ? lz : (hz < 0 ? -hz : 0.0);
     const double m = sqrt(mx * mx + my * my + mz * mz);
     const double r = double(brho);
     const double f = m >= r ? 0.5 * m * m - r * m : -0.5 * r * r;
-    const double cmax = fmax(double(bcx) * lx, double(bcx) * hx) + fmax(double(bcy) * ly, double(bcy) * hy) +
-                        fmax(double(bcz) * lz, double(bcz) * hz);
+    const double ex = double(bcx) + gx, ey = double(bcy) + gy, ez = double(bcz) + gz;
+    const double cmax = fmax(ex * lx, ex * hx) + fmax(ey * ly, ey * hy) + fmax(ez * lz, ez * hz);
     return f - cmax < wmax - wi + mtol;
   };
 
@@ -699,7 +725,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   // until what is left lies beyond the reach R + sqrt(R^2 + 2 (psi_max - psi_i)).
   {
     const int bx0 = cx >> 2, by0 = cy >> 2, bz0 = cz >> 2;
-    const double bh = BLOCK_SIDE * h;
     double mb = fmin(fmin(xi - bx0 * bh, (bx0 + 1) * bh - xi),
                      fmin(fmin(yi - by0 * bh, (by0 + 1) * bh - yi), fmin(zi - bz0 * bh, (bz0 + 1) * bh - zi)));
     mb = fmax(mb, 0.0);
@@ -730,6 +755,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
       }
       return far_ok();
     };
+    if (A.warm_rp) {
+      // warm start: the earlier neighbours (nearest image), 64 per list
+      const int64_t wb = A.warm_rp[p], we = A.warm_rp[p + 1];
+      for (int64_t k0 = wb; k0 < we && !dead; k0 += 64) {
+        const int64_t k = k0 + lane;
+        int32_t j = -1;
+        if (k < we) j = A.warm_col[k];
+        const bool act = j >= 0 && j != p;
+        int32_t shw = 0;
+        if (act) {
+          const double4 P = A.pts[j];
+          shw = pack_shift(-int(rint((P.x - xi) / L)), -int(rint((P.y - yi) / L)),
+                           -int(rint((P.z - zi) / L)));
+        }
+        process_list(act, act ? j : 0, 1, shw);
+      }
+    }
     int phase = 0;  // 0: 27 cells, 1 and 2: ring 2 of cells, 3: block shells
     int rb = 0, gbase = 0, gcount = 1;
     uint64_t bmask = 0;
@@ -758,8 +800,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
           if (act) {
             const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
                          lz = uz * h - zi - 1e-12 * L;
-            act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L,
-                              A.cell_psimax[g]);
+            const int ubx = floor_div(ux, BLOCK_SIDE), uby = floor_div(uy, BLOCK_SIDE),
+                      ubz = floor_div(uz, BLOCK_SIDE);
+            const int64_t bk = block_key(ubx - floor_div(ubx, Gb) * Gb, uby - floor_div(uby, Gb) * Gb,
+                                         ubz - floor_div(ubz, Gb) * Gb, Gb);
+            act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L, bk,
+                              ubx, uby, ubz, A.cell_tmax[g]);
           }
         }
         CNT(c_box += 64);
@@ -816,7 +862,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
             const double lx = ubx * bh - xi - 1e-12 * L, ly = uby * bh - yi - 1e-12 * L,
                          lz = ubz * bh - zi - 1e-12 * L;
             const double hx = lx + bh + 2e-12 * L, hy = ly + bh + 2e-12 * L, hz = lz + bh + 2e-12 * L;
-            ok = box_may_cut(lx, ly, lz, hx, hy, hz, A.block_psimax[block_key(wbx, wby, wbz, Gb)]);
+            const int64_t bk = block_key(wbx, wby, wbz, Gb);
+            ok = box_may_cut(lx, ly, lz, hx, hy, hz, bk, ubx, uby, ubz, A.block_tmax[bk]);
           }
           bmask = ballot(ok);
         }
@@ -837,8 +884,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
         if (act) {
           const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
                        lz = uz * h - zi - 1e-12 * L;
-          act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L,
-                            A.cell_psimax[g]);
+          const int64_t bk = block_key(qbx - floor_div(qbx, Gb) * Gb, qby - floor_div(qby, Gb) * Gb,
+                                       qbz - floor_div(qbz, Gb) * Gb, Gb);
+          act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L, bk,
+                            qbx, qby, qbz, A.cell_tmax[g]);
         }
         shp = pack_shift(sx, sy, sz);
       }
@@ -1165,9 +1214,12 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   ClipArgs a{};
   a.pts = ps.pts.as<double4>();
   a.cell_start = ps.cell_start.as<int32_t>();
-  a.cell_psimax = ps.cell_psimax.as<double>();
-  a.block_psimax = ps.block_psimax.as<double>();
   a.block_suffix = ps.block_suffix.as<double>();
+  a.warm_rp = jb.warm_rp;
+  a.warm_col = jb.warm_col;
+  a.block_g = ps.block_g.as<double>();
+  a.block_tmax = ps.block_tmax.as<double>();
+  a.cell_tmax = ps.cell_tmax.as<double>();
   a.gmax = ps.scal.as<double>();
   a.Gn = ps.g.Gn;
   a.Gb = ps.g.Gb;
@@ -1320,8 +1372,12 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
 }
 
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                    bool tolerate_failure, double doom_vol) {
+                    bool tolerate_failure, double doom_vol, const Csr* warm) {
   PassJob jb;
+  if (warm && warm->n == ps.N) {
+    jb.warm_rp = warm->row_ptr.as<int64_t>();
+    jb.warm_col = warm->col.as<int32_t>();
+  }
   jb.ps = &ps;
   jb.out = &out;
   jb.faces = faces;

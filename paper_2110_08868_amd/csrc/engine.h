@@ -82,6 +82,9 @@ struct PointSet {
   DevBuf block_psimax; // double [GB]
   DevBuf block_suffix; // double [GB * (SHELL_MAX + 1)]: max weight over the blocks at
                        // Chebyshev block distance exactly r from each block
+  DevBuf block_g;      // double [GB * 3]: slope of the tilted bounds
+  DevBuf block_tmax;   // double [GB]: max_j psi_j - g . (x_j - x_block centre)
+  DevBuf cell_tmax;    // double [G]: the same over the sites of each cell
   DevBuf scal;         // double [8]: [0] global psi max, [1] global psi min
   DevBuf key, rank, count, status, tmp;  // build temporaries (released after the
                                          // build of a large set)
@@ -149,8 +152,12 @@ struct ClipStats {
 // With doom_vol > 0 (a line-search trial), the first cell whose volume ends
 // below doom_vol (or empty) abandons the pass: ClipStats::doomed, outputs
 // unspecified.
+// `warm` (may be NULL): J of an earlier pass over the same sorted sites; its
+// rows are clipped first (a warm start; results do not depend on it beyond
+// rounding).
 ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                    bool tolerate_failure = false, double doom_vol = 0.0);
+                    bool tolerate_failure = false, double doom_vol = 0.0,
+                    const Csr* warm = nullptr);
 
 // Cell passes of several point sets in shared launches (the serving form):
 // each job runs its stages like run_cells, but every stage launch carries up
@@ -162,6 +169,8 @@ struct PassJob {
   bool faces = true;
   bool tolerate = false;
   double doom_vol = 0.0;
+  const int64_t* warm_rp = nullptr;  // optional warm start (CSR rows, sorted space)
+  const int32_t* warm_col = nullptr;
   // results
   ClipStats cs;
   mak_status status = MAK_OK;
@@ -179,7 +188,7 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
 struct PassRunner {
   virtual ~PassRunner() = default;
   virtual ClipStats run(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                        bool tolerate_failure, double doom_vol) = 0;
+                        bool tolerate_failure, double doom_vol, const Csr* warm) = 0;
 };
 void set_pass_runner(::mak_ctx* ctx, PassRunner* r);
 

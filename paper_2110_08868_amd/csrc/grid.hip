@@ -135,6 +135,78 @@ __global__ void k_block_suffix(const double* __restrict__ bmax, double* __restri
   for (int r = 0; r <= SHELL_MAX; ++r) suf[b * (SHELL_MAX + 1) + r] = sh[r];
 }
 
+// Tilted weight bounds.  For block B with centre x_B take a slope g_B (the
+// least-squares fit of psi over the block's sites; any slope gives a valid
+// bound) and M = max_j (psi_j - g_B . (x_j - x_B)) over the block's sites,
+// and per cell over the cell's sites: every site j of the block satisfies
+// psi_j <= M + g_B . (x_j - x_B).  The clip kernel's box tests use these, so
+// a linear trend of the weights across a block (converged weights follow the
+// displacement field) does not inflate the bound of the whole block.
+// One thread per block; the block's sites are contiguous (block-major keys).
+__global__ void k_block_tilt(const int32_t* __restrict__ start, const double4* __restrict__ pts,
+                             double bh, int Gb, int64_t GB, double* __restrict__ block_g,
+                             double* __restrict__ block_tmax, double* __restrict__ cell_tmax) {
+  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= GB) return;
+  const int bx = int(b / (int64_t(Gb) * Gb)), by = int((b / Gb) % Gb), bz = int(b % Gb);
+  const double ox = (bx + 0.5) * bh, oy = (by + 0.5) * bh, oz = (bz + 0.5) * bh;
+  const int32_t s0 = start[b * 64], s1 = start[b * 64 + 64];
+  const int n = s1 - s0;
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+  if (n >= 4) {
+    double mx = 0, my = 0, mz = 0, mp = 0;
+    for (int32_t k = s0; k < s1; ++k) {
+      const double4 P = pts[k];
+      mx += P.x - ox;
+      my += P.y - oy;
+      mz += P.z - oz;
+      mp += P.w;
+    }
+    mx /= n;
+    my /= n;
+    mz /= n;
+    mp /= n;
+    double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0, vx = 0, vy = 0, vz = 0;
+    for (int32_t k = s0; k < s1; ++k) {
+      const double4 P = pts[k];
+      const double ex = P.x - ox - mx, ey = P.y - oy - my, ez = P.z - oz - mz, ep = P.w - mp;
+      cxx += ex * ex;
+      cxy += ex * ey;
+      cxz += ex * ez;
+      cyy += ey * ey;
+      cyz += ey * ez;
+      czz += ez * ez;
+      vx += ex * ep;
+      vy += ey * ep;
+      vz += ez * ep;
+    }
+    // adjugate solve of the 3x3 normal equations, skipped when ill-conditioned
+    const double a00 = cyy * czz - cyz * cyz, a01 = cxz * cyz - cxy * czz, a02 = cxy * cyz - cxz * cyy;
+    const double a11 = cxx * czz - cxz * cxz, a12 = cxy * cxz - cxx * cyz, a22 = cxx * cyy - cxy * cxy;
+    const double det = cxx * a00 + cxy * a01 + cxz * a02;
+    const double tr = cxx + cyy + czz;
+    if (det > 1e-6 * tr * tr * tr) {
+      gx = (a00 * vx + a01 * vy + a02 * vz) / det;
+      gy = (a01 * vx + a11 * vy + a12 * vz) / det;
+      gz = (a02 * vx + a12 * vy + a22 * vz) / det;
+    }
+  }
+  double M = -DBL_MAX;
+  for (int c = 0; c < 64; ++c) {
+    double mc = -DBL_MAX;
+    for (int32_t k = start[b * 64 + c]; k < start[b * 64 + c + 1]; ++k) {
+      const double4 P = pts[k];
+      mc = fmax(mc, P.w - (gx * (P.x - ox) + gy * (P.y - oy) + gz * (P.z - oz)));
+    }
+    cell_tmax[b * 64 + c] = mc;
+    M = fmax(M, mc);
+  }
+  block_tmax[b] = M;
+  block_g[3 * b] = gx;
+  block_g[3 * b + 1] = gy;
+  block_g[3 * b + 2] = gz;
+}
+
 }  // namespace
 
 void build_pointset(PointSet& ps, const double* points, const double* psi, int64_t N, double L,
@@ -149,6 +221,9 @@ void build_pointset(PointSet& ps, const double* points, const double* psi, int64
   ps.cell_psimax.ensure(size_t(G) * sizeof(double));
   ps.block_psimax.ensure(size_t(ps.g.GB()) * sizeof(double));
   ps.block_suffix.ensure(size_t(ps.g.GB()) * (SHELL_MAX + 1) * sizeof(double));
+  ps.block_g.ensure(size_t(ps.g.GB()) * 3 * sizeof(double));
+  ps.block_tmax.ensure(size_t(ps.g.GB()) * sizeof(double));
+  ps.cell_tmax.ensure(size_t(G) * sizeof(double));
   ps.scal.ensure(8 * sizeof(double));
   ps.key.ensure(size_t(N) * sizeof(int32_t));
   ps.rank.ensure(size_t(N) * sizeof(int32_t));
@@ -200,6 +275,9 @@ void update_psi_bounds(PointSet& ps, hipStream_t st) {
                      ps.block_psimax.as<double>(), GB);
   hipLaunchKernelGGL(k_block_suffix, dim3(unsigned(ceil_div(GB, 64))), dim3(64), 0, st,
                      ps.block_psimax.as<double>(), ps.block_suffix.as<double>(), ps.g.Gb, GB);
+  hipLaunchKernelGGL(k_block_tilt, dim3(unsigned(ceil_div(GB, 64))), dim3(64), 0, st,
+                     ps.cell_start.as<int32_t>(), ps.pts.as<double4>(), BLOCK_SIDE * ps.g.h, ps.g.Gb,
+                     GB, ps.block_g.as<double>(), ps.block_tmax.as<double>(), ps.cell_tmax.as<double>());
   MAK_HIP(hipGetLastError());
   dev_max_to(ps.block_psimax.as<double>(), GB, ps.scal.as<double>(), ps.tmp, st);
 }
