@@ -61,7 +61,15 @@ typedef struct {
   double grid_occupancy;   /* target sites per neighbour-grid cell, default 2.5 */
   size_t mem_budget_bytes; /* 0 = no limit (server admission uses it) */
   int32_t verbose;         /* 1: one line per Newton iteration on stderr, 2: also per trial */
-  int32_t reserved[7];
+  int32_t first_stage;     /* cell-pass stage to start at, default 0.  A pass
+                              runs every cell in the first kernel and re-runs the
+                              cells it cannot finish in the next: float64 path
+                              0 = float64, 1 = float64 with the larger polytope
+                              and a wider tie tolerance; mixed path 0 = float32,
+                              1 = float64, 2 = the larger float64 kernel.  A later
+                              first stage runs all cells in that fallback kernel
+                              (for testing it). */
+  int32_t reserved[6];
 } mak_options;
 
 /* Fill `opt` with the defaults listed above. */

@@ -203,7 +203,9 @@ mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
     g_create_error = "unknown precision";
     return MAK_EINVAL;
   }
-  if (!(c->opt.cg_rtol > 0) || c->opt.max_newton < 0 || c->opt.max_cg < 1 || c->opt.max_halvings < 0) {
+  const int nstage = c->opt.precision == MAK_MIXED ? 3 : 2;
+  if (!(c->opt.cg_rtol > 0) || c->opt.max_newton < 0 || c->opt.max_cg < 1 || c->opt.max_halvings < 0 ||
+      c->opt.first_stage < 0 || c->opt.first_stage >= nstage) {
     delete c;
     g_create_error = "invalid options";
     return MAK_EINVAL;
@@ -233,7 +235,10 @@ mak_status mak_laguerre_cells(mak_ctx* ctx, const double* points, const double* 
     hipStream_t st = static_cast<hipStream_t>(stream);
     ctx->cells_valid = false;
     build_pointset(ctx->ps, points, psi, N, L, ctx->opt.grid_occupancy, st);
-    ClipStats cs = run_cells(ctx->ps, ctx->cp, ctx->opt.precision, true, st);
+    PassOpts po;
+    po.precision = ctx->opt.precision;
+    po.first_stage = ctx->opt.first_stage;
+    ClipStats cs = run_cells(ctx->ps, ctx->cp, po, st);
     FlagStats fs = flag_stats(ctx->ps, ctx->cp, ctx->tmp, st);
     if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
     build_csr(ctx->ps, ctx->cp, ctx->J, true, st);
@@ -308,8 +313,13 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
     const double m = L * L * L / double(N);
 
     auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Csr* warm) {
-      return ctx->runner ? ctx->runner->run(ps, cp, o.precision, true, st, tolerate, doom_vol, warm)
-                         : run_cells(ps, cp, o.precision, true, st, tolerate, doom_vol, warm);
+      PassOpts po;
+      po.precision = o.precision;
+      po.tolerate_failure = tolerate;
+      po.doom_vol = doom_vol;
+      po.warm = warm;
+      po.first_stage = o.first_stage;
+      return ctx->runner ? ctx->runner->run(ps, cp, po, st) : run_cells(ps, cp, po, st);
     };
     set_psi_sorted(ps, psi_s, st);
     ClipStats cs = pass(ctx->scp, false, 0.0, nullptr);

@@ -205,8 +205,13 @@ __device__ __forceinline__ uint64_t clock_stamp() {
 __constant__ int kNearOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1, 7, 19, 25, 3, 5, 21, 23,
                                    9, 11, 15, 17, 0, 2, 6, 8, 18, 20, 24, 26};
 
+// Occupancy: the kernel is bound by instruction issue and the latency of its
+// dependent LDS / memory steps, so more waves per SIMD pay even with some
+// registers spilled: 4 waves per SIMD (128 VGPRs; 10 KB LDS per wave fits 16
+// per CU) for the main kernels, 2 for the large-capacity one.
 template <int TPL, typename R, bool STATS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_clip(ClipBatch B) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4 : 2))) void k_clip(
+    ClipBatch B) {
   constexpr bool kF64 = sizeof(R) == 8;
   constexpr int PCAP = ClipLDS<TPL, R>::PCAP;
   constexpr int TCAP = ClipLDS<TPL, R>::TCAP;
@@ -1200,7 +1205,8 @@ int num_stages(int precision) { return precision == MAK_MIXED ? 3 : 2; }
 void job_begin(PassJob& jb, hipStream_t st) {
   CellPass& out = *jb.out;
   MAK_HIP(hipMemsetAsync(out.counters.p, 0, 64 * sizeof(unsigned long long), st));
-  jb.stage = 0;
+  jb.stage = jb.opt.first_stage;
+  jb.all_cells = true;
   jb.listed = jb.ps->N;
   jb.cs = ClipStats();
 }
@@ -1215,8 +1221,10 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.pts = ps.pts.as<double4>();
   a.cell_start = ps.cell_start.as<int32_t>();
   a.block_suffix = ps.block_suffix.as<double>();
-  a.warm_rp = jb.warm_rp;
-  a.warm_col = jb.warm_col;
+  const Csr* warm = jb.opt.warm;
+  const bool use_warm = warm && warm->n == N && warm->row_ptr.p && warm->col.p;
+  a.warm_rp = use_warm ? warm->row_ptr.as<int64_t>() : nullptr;
+  a.warm_col = use_warm ? warm->col.as<int32_t>() : nullptr;
   a.block_g = ps.block_g.as<double>();
   a.block_tmax = ps.block_tmax.as<double>();
   a.cell_tmax = ps.cell_tmax.as<double>();
@@ -1229,26 +1237,27 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.mom = out.mom.as<double>();
   a.cflags = out.cflags.as<int32_t>();
   a.nface = out.nface.as<int32_t>();
-  a.faces = jb.faces ? fst.faces.as<FaceRec>() : nullptr;
-  a.fbase = jb.faces ? fst.fbase.as<int64_t>() : nullptr;
-  a.ovf = jb.faces ? fst.ovf.as<FaceRec>() : nullptr;
+  const bool faces = jb.opt.faces;
+  a.faces = faces ? fst.faces.as<FaceRec>() : nullptr;
+  a.fbase = faces ? fst.fbase.as<int64_t>() : nullptr;
+  a.ovf = faces ? fst.ovf.as<FaceRec>() : nullptr;
   a.ovf_used = ctr;
-  a.ovf_cap = jb.faces ? fst.ovf_cap : 0;
+  a.ovf_cap = faces ? fst.ovf_cap : 0;
   a.fslot = fst.fslot;
-  a.write_faces = jb.faces ? 1 : 0;
+  a.write_faces = faces ? 1 : 0;
   const double spacing = ps.g.L / std::cbrt(double(N));
   a.area_min = 1e-12 * spacing * spacing;
   a.tol_rel = 1e-6;
   a.stats = nullptr;
-  a.work = stage == 0 ? nullptr : out.retry.as<int32_t>() + (stage - 1) * N;
+  a.work = jb.all_cells ? nullptr : out.retry.as<int32_t>() + (stage - 1) * N;
   a.nwork = jb.listed;
   a.per_xcd = ceil_div(jb.listed, 8);
   a.retry = out.retry.as<int32_t>() + stage * N;
   a.retry_count = ctr + 1 + stage;
   a.cause = ctr + 32 + 3 * stage;
   a.eps_rel = stage == nstage - 1 ? 1e-11 : 1e-13;
-  a.doom = jb.doom_vol > 0 ? reinterpret_cast<unsigned int*>(ctr + 4) : nullptr;
-  a.doom_vol = jb.doom_vol;
+  a.doom = jb.opt.doom_vol > 0 ? reinterpret_cast<unsigned int*>(ctr + 4) : nullptr;
+  a.doom_vol = jb.opt.doom_vol;
   return a;
 }
 
@@ -1301,7 +1310,9 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
       out.nface.ensure(size_t(N) * sizeof(int32_t));
       out.retry.ensure(size_t(N) * 3 * sizeof(int32_t));
       out.counters.ensure(64 * sizeof(unsigned long long));
-      if (jb.faces) {
+      if (jb.opt.first_stage < 0 || jb.opt.first_stage >= nstage)
+        MAK_FAIL(MAK_EINVAL, "first stage out of range");
+      if (jb.opt.faces) {
         fst.faces.ensure(size_t(N) * fst.fslot * sizeof(FaceRec));
         fst.fbase.ensure(size_t(N) * sizeof(int64_t));
         if (fst.ovf_cap < 4096 + N / 8) fst.ovf_cap = 4096 + N / 8;
@@ -1333,7 +1344,7 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
       const int s = jb->stage;
       FaceStore& fst = jb->out->fs();
       try {
-        if (jb->faces && int64_t(jb->hc[0]) > fst.ovf_cap) {
+        if (jb->opt.faces && int64_t(jb->hc[0]) > fst.ovf_cap) {
           // the overflow region was too small: grow it and run the pass again
           if (++jb->attempt >= 3) MAK_FAIL(MAK_ENOMEM, "face overflow buffer could not be sized");
           fst.ovf_cap = int64_t(jb->hc[0]) + int64_t(jb->hc[0]) / 4 + 4096;
@@ -1347,12 +1358,12 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
           continue;
         }
         const int64_t listed = int64_t(jb->hc[1 + s]);
-        if (s == 0) jb->cs.retried = listed;
+        if (jb->all_cells) jb->cs.retried = listed;
         if (mixed && s == 0) jb->cs.fp64_rerun = listed;
         if (listed == 0) continue;  // finished
         if (s == nstage - 1) {
           jb->cs.overflow = listed;
-          if (jb->tolerate) continue;
+          if (jb->opt.tolerate_failure) continue;
           unsigned long long cz[3];
           MAK_HIP(hipMemcpy(cz, jb->out->counters.as<unsigned long long>() + 32 + 3 * s, sizeof(cz),
                             hipMemcpyDeviceToHost));
@@ -1361,6 +1372,7 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
         }
         jb->listed = listed;
         jb->stage = s + 1;
+        jb->all_cells = false;
         next.push_back(jb);
       } catch (const Error& e) {
         jb->status = e.status;
@@ -1371,20 +1383,13 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
   }
 }
 
-ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                    bool tolerate_failure, double doom_vol, const Csr* warm) {
+ClipStats run_cells(PointSet& ps, CellPass& out, const PassOpts& o, hipStream_t st) {
   PassJob jb;
-  if (warm && warm->n == ps.N) {
-    jb.warm_rp = warm->row_ptr.as<int64_t>();
-    jb.warm_col = warm->col.as<int32_t>();
-  }
   jb.ps = &ps;
   jb.out = &out;
-  jb.faces = faces;
-  jb.tolerate = tolerate_failure;
-  jb.doom_vol = doom_vol;
+  jb.opt = o;
   PassJob* one = &jb;
-  run_cells_batch(&one, 1, precision, st);
+  run_cells_batch(&one, 1, o.precision, st);
   if (jb.status != MAK_OK) MAK_FAIL(jb.status, jb.err);
   return jb.cs;
 }

@@ -144,39 +144,44 @@ struct ClipStats {
   int64_t retried = 0, overflow = 0, fp64_rerun = 0;
   bool doomed = false;  // a cell ended below doom_vol: the pass was abandoned
 };
-// Full cell pass at the psi stored in ps.pts[].w.  precision: MAK_FP64 or
-// MAK_MIXED.  Throws on capacity overflow past the large kernel.
-// With `tolerate_failure`, cells the large kernel cannot represent are
-// reported in ClipStats::overflow instead of throwing (a line-search trial
-// is then rejected).
-// With doom_vol > 0 (a line-search trial), the first cell whose volume ends
-// below doom_vol (or empty) abandons the pass: ClipStats::doomed, outputs
-// unspecified.
-// `warm` (may be NULL): J of an earlier pass over the same sorted sites; its
-// rows are clipped first (a warm start; results do not depend on it beyond
-// rounding).
-ClipStats run_cells(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                    bool tolerate_failure = false, double doom_vol = 0.0,
-                    const Csr* warm = nullptr);
+// How one cell pass runs.
+struct PassOpts {
+  int precision = MAK_FP64;  // MAK_FP64 or MAK_MIXED
+  bool faces = true;         // write the face records (for J)
+  // Cells the largest kernel cannot represent are reported in
+  // ClipStats::overflow instead of failing the pass (a line-search trial is
+  // then rejected).
+  bool tolerate_failure = false;
+  // > 0 (a line-search trial): the first cell whose volume ends below it (or
+  // empty) abandons the pass: ClipStats::doomed, outputs unspecified.
+  double doom_vol = 0.0;
+  // J of an earlier pass over the same sorted sites (may be NULL): its rows
+  // are clipped first (a warm start; results differ only by rounding).
+  const Csr* warm = nullptr;
+  // Stage the pass starts at (0: the first kernel); > 0 runs every cell in
+  // the fallback kernels (testing them).
+  int first_stage = 0;
+};
+
+// Full cell pass at the psi stored in ps.pts[].w.  Throws on failure.
+ClipStats run_cells(PointSet& ps, CellPass& out, const PassOpts& o, hipStream_t st);
 
 // Cell passes of several point sets in shared launches (the serving form):
 // each job runs its stages like run_cells, but every stage launch carries up
-// to kMaxJobs jobs.  Errors are reported per job (status / err), not thrown.
+// to kMaxJobs jobs (of one precision).  Errors are reported per job (status
+// / err), not thrown.
 constexpr int kMaxJobs = 8;
 struct PassJob {
   PointSet* ps = nullptr;
   CellPass* out = nullptr;
-  bool faces = true;
-  bool tolerate = false;
-  double doom_vol = 0.0;
-  const int64_t* warm_rp = nullptr;  // optional warm start (CSR rows, sorted space)
-  const int32_t* warm_col = nullptr;
+  PassOpts opt;
   // results
   ClipStats cs;
   mak_status status = MAK_OK;
   std::string err;
   // progress (driver-internal)
   int stage = 0, attempt = 0;
+  bool all_cells = true;  // the current stage runs over every cell
   int64_t listed = 0;
   unsigned long long hc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
@@ -187,8 +192,7 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
 // concurrent requests into shared launches.
 struct PassRunner {
   virtual ~PassRunner() = default;
-  virtual ClipStats run(PointSet& ps, CellPass& out, int precision, bool faces, hipStream_t st,
-                        bool tolerate_failure, double doom_vol, const Csr* warm) = 0;
+  virtual ClipStats run(PointSet& ps, CellPass& out, const PassOpts& o, hipStream_t st) = 0;
 };
 void set_pass_runner(::mak_ctx* ctx, PassRunner* r);
 

@@ -14,7 +14,7 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int MAXB = 1024;       // blocks of the grid-stride vector kernels
-constexpr int SPMV_MAXB = 8192;  // blocks of the SpMV (16 rows each per sweep)
+constexpr int SPMV_MAXB = 8192;  // blocks of the SpMV (grid-stride over rows)
 
 // scalar slots (device doubles)
 enum { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6 };
@@ -36,31 +36,43 @@ unsigned vec_blocks(int64_t n) {
   return unsigned(b < MAXB ? (b < 1 ? 1 : b) : MAXB);
 }
 
+// SpMV layout: LPR lanes per row, each lane issuing UNR independent loads of
+// col / val before the gathers of p (rows hold ~17 nonzeros: one unrolled
+// step covers most rows, and the loads of a lane are all in flight at once).
+constexpr int LPR = 4, UNR = 6;
+
 unsigned spmv_blocks(int64_t n) {
-  const int64_t b = ceil_div(n, TPB / 16);
+  const int64_t b = ceil_div(n, TPB / LPR);
   return unsigned(b < SPMV_MAXB ? (b < 1 ? 1 : b) : SPMV_MAXB);
 }
 
-// q = J p, one 16-lane group per row (rows ~15 nonzeros: one coalesced load
-// of col/val per lane), grid-stride over row groups, and per-block partial
-// of p . q
+// q = J p, grid-stride over row groups, and per-block partial of p . q
 __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
                                                   const double* __restrict__ val,
                                                   const double* __restrict__ p, double* __restrict__ q,
                                                   double* __restrict__ part, int64_t n) {
   __shared__ double sh[TPB / WAVE];
-  const int sub = threadIdx.x & 15;
+  const int sub = threadIdx.x & (LPR - 1);
   double acc = 0.0;
-  for (int64_t row = int64_t(blockIdx.x) * (TPB / 16) + (threadIdx.x >> 4); row < n;
-       row += int64_t(gridDim.x) * (TPB / 16)) {
+  for (int64_t row = int64_t(blockIdx.x) * (TPB / LPR) + (threadIdx.x / LPR); row < n;
+       row += int64_t(gridDim.x) * (TPB / LPR)) {
     const int64_t b = rp[row], e = rp[row + 1];
     double s = 0.0;
-    for (int64_t k = b + sub; k < e; k += 16) s += val[k] * p[col[k]];
-    s += __shfl_xor(s, 8);
-    s += __shfl_xor(s, 4);
-    s += __shfl_xor(s, 2);
-    s += __shfl_xor(s, 1);
+    for (int64_t k = b + sub; k < e; k += UNR * LPR) {
+      int32_t c[UNR];
+      double v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int64_t kk = k + u * LPR;
+        c[u] = kk < e ? col[kk] : -1;
+        v[u] = kk < e ? val[kk] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) s += c[u] >= 0 ? v[u] * p[c[u]] : 0.0;
+    }
+#pragma unroll
+    for (int o = LPR / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     if (sub == 0) {
       q[row] = s;
       acc += s * p[row];

@@ -68,21 +68,15 @@ struct PassBatcher final : mak::PassRunner {
         });
   }
   // Called by a solve on its worker thread.
-  mak::ClipStats run(mak::PointSet& ps, mak::CellPass& out, int prec, bool faces, hipStream_t sst,
-                     bool tolerate, double doom_vol, const mak::Csr* warm) override {
-    if (prec != precision) MAK_FAIL(MAK_EINVAL, "pass precision differs from the server's");
+  mak::ClipStats run(mak::PointSet& ps, mak::CellPass& out, const mak::PassOpts& o,
+                     hipStream_t sst) override {
+    if (o.precision != precision) MAK_FAIL(MAK_EINVAL, "pass precision differs from the server's");
     // the solve's own stream wrote the weights: they must be on the device
     MAK_HIP(hipStreamSynchronize(sst));
     mak::PassJob job;
     job.ps = &ps;
     job.out = &out;
-    job.faces = faces;
-    job.tolerate = tolerate;
-    job.doom_vol = doom_vol;
-    if (warm && warm->n == ps.N) {
-      job.warm_rp = warm->row_ptr.as<int64_t>();
-      job.warm_col = warm->col.as<int32_t>();
-    }
+    job.opt = o;
     b.post(&job);
     if (job.status != MAK_OK) MAK_FAIL(job.status, job.err);
     return job.cs;

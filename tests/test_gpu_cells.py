@@ -235,3 +235,19 @@ def test_mixed_precision_parity(mctx, case):
         x = rng.uniform(0, 1, size=(1000, 3))
         psi = rng.uniform(-1, 1, 1000) * 0.005
     check(mctx, x, psi, 1.0, vol_rel=1e-6, cen_rel=1e-6, area_rel=1e-6)
+
+
+# ---------------------------------------------------------------- fallback kernels
+@pytest.mark.parametrize("precision,stage", [("fp64", 1), ("mixed", 1), ("mixed", 2)])
+def test_fallback_kernels_alone(precision, stage):
+    """Every cell through a fallback kernel (the larger polytope / float64
+    re-run): the same cells as the oracle, to the float64 bar."""
+    import paper_2110_08868_amd as mak
+    c = mak.Context(0, precision, first_stage=stage)
+    try:
+        x = workloads.clustered(12, rms=2.0, smooth=1.0, frac=0.2, n_clumps=10, a=0.5, seed=4)
+        psi = np.random.default_rng(3).uniform(-1, 1, len(x)) * 0.02 / 144
+        V, C, F, info, rep = check(c, x, psi, 1.0)
+        assert info["fp64_rerun_cells"] == 0 or precision == "mixed"
+    finally:
+        c.close()
