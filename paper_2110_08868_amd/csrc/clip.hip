@@ -162,7 +162,7 @@ __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
 }
 
 // Offset of the t-th block of the Chebyshev shell of radius r (r >= 1).
-__device__ __forceinline__ void shell_offset(int r, int t, int& ox, int& oy, int& oz) {
+__host__ __device__ constexpr void shell_offset_calc(int r, int t, int& ox, int& oy, int& oz) {
   if (r == 0) {
     ox = oy = oz = 0;
     return;
@@ -188,6 +188,55 @@ __device__ __forceinline__ void shell_offset(int r, int t, int& ox, int& oy, int
   oz = side ? r : -r;
   ox = rem / I - (r - 1);
   oy = rem % I - (r - 1);
+}
+
+// The offsets of shells 1..SHELL_MAX in one table (4 bits per axis, biased by
+// 8), built at compile time by the function above: the walk reads an entry
+// instead of dividing by runtime shell sizes.
+constexpr int kShellEntries = (2 * SHELL_MAX + 1) * (2 * SHELL_MAX + 1) * (2 * SHELL_MAX + 1) - 1;
+struct ShellTable {
+  uint16_t v[kShellEntries];
+};
+constexpr ShellTable make_shell_table() {
+  ShellTable tb{};
+  int n = 0;
+  for (int r = 1; r <= SHELL_MAX; ++r) {
+    const int S = 2 * r + 1, I = 2 * r - 1;
+    for (int t = 0; t < S * S * S - I * I * I; ++t) {
+      int ox = 0, oy = 0, oz = 0;
+      shell_offset_calc(r, t, ox, oy, oz);
+      tb.v[n++] = uint16_t((ox + 8) | ((oy + 8) << 4) | ((oz + 8) << 8));
+    }
+  }
+  return tb;
+}
+static_assert(SHELL_MAX <= 7, "shell offsets are packed in 4 bits");
+static_assert(BLOCK_SIDE == 4, "cell -> block uses shifts by 2");
+__constant__ ShellTable kShell = make_shell_table();
+
+__device__ __forceinline__ void shell_offset(int r, int t, int& ox, int& oy, int& oz) {
+  if (r >= 1 && r <= SHELL_MAX) {
+    const int I = 2 * r - 1;
+    const uint32_t v = kShell.v[I * I * I - 1 + t];
+    ox = int(v & 15u) - 8;
+    oy = int((v >> 4) & 15u) - 8;
+    oz = int((v >> 8) & 15u) - 8;
+    return;
+  }
+  if (r == 0) {
+    ox = oy = oz = 0;
+    return;
+  }
+  shell_offset_calc(r, t, ox, oy, oz);
+}
+
+// floor(a / n) for n > 0, without a division in the common case of a within
+// one period of [0, n).
+__device__ __forceinline__ int period_div(int a, int n) {
+  if (a >= 0 && a < n) return 0;
+  if (a < 0 && a >= -n) return -1;
+  if (a >= n && a < 2 * n) return 1;
+  return floor_div(a, n);
 }
 
 // Shader clock for the counting variant's phase timers: waits for the
@@ -796,7 +845,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         int ox = 0, oy = 0, oz = 0;
         if (act) shell_offset(2, t, ox, oy, oz);
         const int ux = cx + ox, uy = cy + oy, uz = cz + oz;
-        const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+        const int sx = period_div(ux, Gn), sy = period_div(uy, Gn), sz = period_div(uz, Gn);
         if (act) {
           const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
           st = A.cell_start[g];
@@ -805,10 +854,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           if (act) {
             const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
                          lz = uz * h - zi - 1e-12 * L;
-            const int ubx = floor_div(ux, BLOCK_SIDE), uby = floor_div(uy, BLOCK_SIDE),
-                      ubz = floor_div(uz, BLOCK_SIDE);
-            const int64_t bk = block_key(ubx - floor_div(ubx, Gb) * Gb, uby - floor_div(uby, Gb) * Gb,
-                                         ubz - floor_div(ubz, Gb) * Gb, Gb);
+            // (arithmetic shifts floor: BLOCK_SIDE is 4)
+            const int ubx = ux >> 2, uby = uy >> 2, ubz = uz >> 2;
+            const int64_t bk = block_key(ubx - period_div(ubx, Gb) * Gb, uby - period_div(uby, Gb) * Gb,
+                                         ubz - period_div(ubz, Gb) * Gb, Gb);
             act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L, bk,
                               ubx, uby, ubz, A.cell_tmax[g]);
           }
@@ -820,7 +869,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         act = lane < 27;
         const int code = act ? kNearOrder[lane] : 13;
         const int ux = cx + code / 9 - 1, uy = cy + (code / 3) % 3 - 1, uz = cz + code % 3 - 1;
-        const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+        const int sx = period_div(ux, Gn), sy = period_div(uy, Gn), sz = period_div(uz, Gn);
         if (act) {
           const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
           st = A.cell_start[g];
@@ -862,8 +911,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
             ubx = bx0 + ox;
             uby = by0 + oy;
             ubz = bz0 + oz;
-            const int wbx = ubx - floor_div(ubx, Gb) * Gb, wby = uby - floor_div(uby, Gb) * Gb,
-                      wbz = ubz - floor_div(ubz, Gb) * Gb;
+            const int wbx = ubx - period_div(ubx, Gb) * Gb, wby = uby - period_div(uby, Gb) * Gb,
+                      wbz = ubz - period_div(ubz, Gb) * Gb;
             const double lx = ubx * bh - xi - 1e-12 * L, ly = uby * bh - yi - 1e-12 * L,
                          lz = ubz * bh - zi - 1e-12 * L;
             const double hx = lx + bh + 2e-12 * L, hy = ly + bh + 2e-12 * L, hz = lz + bh + 2e-12 * L;
@@ -881,7 +930,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         const int ux = qbx * BLOCK_SIDE + (lane >> 4), uy = qby * BLOCK_SIDE + ((lane >> 2) & 3),
                   uz = qbz * BLOCK_SIDE + (lane & 3);
         const bool inA = abs(ux - cx) <= 2 && abs(uy - cy) <= 2 && abs(uz - cz) <= 2;
-        const int sx = floor_div(ux, Gn), sy = floor_div(uy, Gn), sz = floor_div(uz, Gn);
+        const int sx = period_div(ux, Gn), sy = period_div(uy, Gn), sz = period_div(uz, Gn);
         const int64_t g = cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb);
         st = A.cell_start[g];
         cnt = A.cell_start[g + 1] - st;
@@ -889,8 +938,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         if (act) {
           const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
                        lz = uz * h - zi - 1e-12 * L;
-          const int64_t bk = block_key(qbx - floor_div(qbx, Gb) * Gb, qby - floor_div(qby, Gb) * Gb,
-                                       qbz - floor_div(qbz, Gb) * Gb, Gb);
+          const int64_t bk = block_key(qbx - period_div(qbx, Gb) * Gb, qby - period_div(qby, Gb) * Gb,
+                                       qbz - period_div(qbz, Gb) * Gb, Gb);
           act = box_may_cut(lx, ly, lz, lx + h + 2e-12 * L, ly + h + 2e-12 * L, lz + h + 2e-12 * L, bk,
                             qbx, qby, qbz, A.cell_tmax[g]);
         }
