@@ -590,6 +590,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     int krun = 0, nrun = 0;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
+      if (k > 0 && nT <= k * 64) break;  // no slots in this group (uniform)
       const int slot = k * 64 + lane;
       const bool kept = slot < nT && !((om[k] >> lane) & 1ull);
       const uint64_t km = ballot(kept);
@@ -606,30 +607,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       int pos = nkept + nrun + lanes_below(b0) + 2 * lanes_below(b1);
       nrun += __popcll(b0) + 2 * __popcll(b1);
       if (bm[k]) {
+        // the new triangles (x, y, p) of this lane's boundary edges; their
+        // vertices are computed below, one per lane
         const int st[3] = {tri_a(tri[k]), tri_b(tri[k]), tri_c(tri[k])};
-#pragma unroll 1
+#pragma unroll
         for (int e = 0; e < 3; ++e) {
           if (bm[k] & (1 << e)) {
-            const int x = st[e], y = st[(e + 1) % 3];
-            const double4 P1 = S.pl[x], P2 = S.pl[y];
-            // intersection of planes x, y, pn (Cramer's rule, float64 on both
-            // paths; the float32 path stores the vertex rounded)
-            const double c23x = P2.y * Pn.z - P2.z * Pn.y, c23y = P2.z * Pn.x - P2.x * Pn.z,
-                         c23z = P2.x * Pn.y - P2.y * Pn.x;
-            const double c31x = Pn.y * P1.z - Pn.z * P1.y, c31y = Pn.z * P1.x - Pn.x * P1.z,
-                         c31z = Pn.x * P1.y - Pn.y * P1.x;
-            const double c12x = P1.y * P2.z - P1.z * P2.y, c12y = P1.z * P2.x - P1.x * P2.z,
-                         c12z = P1.x * P2.y - P1.y * P2.x;
-            const double det = P1.x * c23x + P1.y * c23y + P1.z * c23z;
-            const double inv = 1.0 / det;
-            S.stri[pos] = tri_pack(x, y, pn);
-            S.sx[pos] = (P1.w * c23x + P2.w * c31x + Pn.w * c12x) * inv;
-            S.sy[pos] = (P1.w * c23y + P2.w * c31y + Pn.w * c12y) * inv;
-            S.sz[pos] = (P1.w * c23z + P2.w * c31z + Pn.w * c12z) * inv;
+            S.stri[pos] = tri_pack(st[e], st[(e + 1) % 3], pn);
             ++pos;
           }
         }
       }
+    }
+    __syncthreads();
+    // new vertices: intersection of planes x, y, pn (Cramer's rule, float64 on
+    // both paths; the float32 path stores the vertex rounded)
+    for (int t = nkept + lane; t < nTn; t += 64) {
+      const uint32_t tr = S.stri[t];
+      const double4 P1 = S.pl[tri_a(tr)], P2 = S.pl[tri_b(tr)];
+      const double c23x = P2.y * Pn.z - P2.z * Pn.y, c23y = P2.z * Pn.x - P2.x * Pn.z,
+                   c23z = P2.x * Pn.y - P2.y * Pn.x;
+      const double c31x = Pn.y * P1.z - Pn.z * P1.y, c31y = Pn.z * P1.x - Pn.x * P1.z,
+                   c31z = Pn.x * P1.y - Pn.y * P1.x;
+      const double c12x = P1.y * P2.z - P1.z * P2.y, c12y = P1.z * P2.x - P1.x * P2.z,
+                   c12z = P1.x * P2.y - P1.y * P2.x;
+      const double det = P1.x * c23x + P1.y * c23y + P1.z * c23z;
+      const double inv = recip_d(det);
+      S.sx[t] = (P1.w * c23x + P2.w * c31x + Pn.w * c12x) * inv;
+      S.sy[t] = (P1.w * c23y + P2.w * c31y + Pn.w * c12y) * inv;
+      S.sz[t] = (P1.w * c23z + P2.w * c31z + Pn.w * c12z) * inv;
     }
     __syncthreads();
     CNT(c_cut += 1);
@@ -640,6 +646,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       const int slot = k * 64 + lane;
+      if (k > 0 && nT <= k * 64) {  // no slots in this group (uniform)
+        tri[k] = 0;
+        continue;
+      }
       if (slot < nT) {
         tri[k] = S.stri[slot];
         vx[k] = S.sx[slot];
@@ -1025,7 +1035,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
                      c31z = P3.x * P1.y - P3.y * P1.x;
         const double c12x = P1.y * P2.z - P1.z * P2.y, c12y = P1.z * P2.x - P1.x * P2.z,
                      c12z = P1.x * P2.y - P1.y * P2.x;
-        const double inv = 1.0 / (P1.x * c23x + P1.y * c23y + P1.z * c23z);
+        const double inv = recip_d(P1.x * c23x + P1.y * c23y + P1.z * c23z);
         fvx[k] = (P1.w * c23x + P2.w * c31x + P3.w * c12x) * inv;
         fvy[k] = (P1.w * c23y + P2.w * c31y + P3.w * c12y) * inv;
         fvz[k] = (P1.w * c23z + P2.w * c31z + P3.w * c12z) * inv;

@@ -65,31 +65,64 @@ __device__ __forceinline__ float uniform_f(float v) {
 }
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Butterfly reductions over the 64 lanes (fixed order: deterministic).
+// Wave reductions (fixed order: deterministic).  Within each 16-lane row,
+// DPP steps combine lane i with lane i^1 and i^2 (quad permutes), then with
+// the mirrored lane of its half-row and of its row: every lane of a row then
+// holds the row's result (bitwise equal across the row, the combining
+// operations being commutative).  The four row results are read into
+// scalars and combined in a fixed order, so the result is wave-uniform.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int C>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, C, 0xF, 0xF, false);
+}
+template <int C>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<C>(__float_as_int(v)));
+}
+template <int C>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t b = uint64_t(__double_as_longlong(v));
+  const uint32_t lo = uint32_t(dpp_i<C>(int(uint32_t(b))));
+  const uint32_t hi = uint32_t(dpp_i<C>(int(uint32_t(b >> 32))));
+  return __longlong_as_double((long long)((uint64_t(hi) << 32) | lo));
+}
+
 __device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_f<kDppXor1>(v);
+  v += dpp_f<kDppXor2>(v);
+  v += dpp_f<kDppHalfMirror>(v);
+  v += dpp_f<kDppMirror>(v);
+  return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
 }
 __device__ __forceinline__ float wave_max_f(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
+  v = fmaxf(v, dpp_f<kDppXor1>(v));
+  v = fmaxf(v, dpp_f<kDppXor2>(v));
+  v = fmaxf(v, dpp_f<kDppHalfMirror>(v));
+  v = fmaxf(v, dpp_f<kDppMirror>(v));
+  return fmaxf(fmaxf(readlane_f(v, 0), readlane_f(v, 16)), fmaxf(readlane_f(v, 32), readlane_f(v, 48)));
 }
 __device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_d<kDppXor1>(v);
+  v += dpp_d<kDppXor2>(v);
+  v += dpp_d<kDppHalfMirror>(v);
+  v += dpp_d<kDppMirror>(v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 __device__ __forceinline__ double wave_max_d(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  v = fmax(v, dpp_d<kDppXor1>(v));
+  v = fmax(v, dpp_d<kDppXor2>(v));
+  v = fmax(v, dpp_d<kDppHalfMirror>(v));
+  v = fmax(v, dpp_d<kDppMirror>(v));
+  return fmax(fmax(readlane_d(v, 0), readlane_d(v, 16)), fmax(readlane_d(v, 32), readlane_d(v, 48)));
 }
 __device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp_i<kDppXor1>(v);
+  v += dpp_i<kDppXor2>(v);
+  v += dpp_i<kDppHalfMirror>(v);
+  v += dpp_i<kDppMirror>(v);
+  return (readlane_i(v, 0) + readlane_i(v, 16)) + (readlane_i(v, 32) + readlane_i(v, 48));
 }
 // Inclusive prefix sum over lanes.
 __device__ __forceinline__ int wave_incl_scan_i(int v) {
@@ -100,6 +133,17 @@ __device__ __forceinline__ int wave_incl_scan_i(int v) {
     if (l >= o) v += t;
   }
   return v;
+}
+
+// 1 / x in float64 for normal, finite x: the hardware reciprocal estimate
+// refined by two Newton-Raphson steps r <- r + r (1 - x r), each of which
+// roughly doubles the correct bits; the result is within a few ulps of the
+// correctly rounded quotient (a vertex position needs no more).
+__device__ __forceinline__ double recip_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
 
 // Order-preserving map of a float to uint32 (for sort keys).
