@@ -685,6 +685,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     const double mx = lx > 0 ? lx : (hx < 0 ? -hx : 0.0);
     const double my = ly > 0 ? ly : (hy < 0 ? -hy : 0.0);
     const double mz = lz > 0 ? lz : (hz < 0 ? -hz : 0.0);
+    // a lower bound of the distance m to the box (a float root, shrunk by
+    // far more than its error): f(m) = m^2/2 - r m is increasing for m >= r,
+    // so the bound keeps the test conservative
     const double m = sqrt(mx * mx + my * my + mz * mz);
     const double r = double(brho);
     const double f = m >= r ? 0.5 * m * m - r * m : -0.5 * r * r;
@@ -733,6 +736,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           coinc = true;
         } else {
           bb = 0.5 * d2 + wi - P.w;
+          // |d| from a float root, enlarged by far more than its error: it
+          // only scales the ball test (larger = more conservative), the tie
+          // tolerances and the sort key
           dn = sqrt(d2);
           const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
           may = cd + double(brho) * dn > bb - mtol;
@@ -801,21 +807,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     // a site at distance t from x_i lies at distance >= t/2 - (w - psi_i)/t
     // from x_i, beyond every vertex once t >= R + sqrt(R^2 + 2 (w - psi_i)),
     // R = the largest vertex distance from x_i.
-    auto reach_w = [&](double w) {
+    // t >= R + sqrt(R^2 + 2 max(0, w - psi_i)) is tested without the root:
+    // for t >= 0 it is equivalent to t (t - 2R) >= 2 max(0, w - psi_i).
+    auto out_of_reach = [&](double t, double w) {
       const double Rv = double(rvert);
-      return Rv + sqrt(Rv * Rv + 2.0 * fmax(0.0, w - wi));
+      return t * (t - 2.0 * Rv) >= 2.0 * fmax(0.0, w - wi);
     };
     const double* bsuf = A.block_suffix + block_key(bx0, by0, bz0, Gb) * (SHELL_MAX + 1);
     // sites in blocks farther than SHELL_MAX block shells (bounded by the
     // global maximum weight) are out of reach
-    auto far_ok = [&]() { return SHELL_MAX * bh + mb - 1e-12 * L >= reach_w(gmax); };
+    auto far_ok = [&]() { return out_of_reach(SHELL_MAX * bh + mb - 1e-12 * L, gmax); };
     // Every site at distance >= t from x_i that lies in a block of shell
     // >= r is out of reach: the sites of shell q are farther than
     // max(t, (q - 1) bh + mb) and weigh at most bsuf[q] (the shell's maximum).
     auto beyond = [&](double t, int r) {
       for (int q = r; q <= SHELL_MAX; ++q) {
         const double dq = fmax(t, q >= 1 ? (q - 1) * bh + mb : 0.0);
-        if (dq - 1e-12 * L < reach_w(bsuf[q])) return false;
+        if (!out_of_reach(dq - 1e-12 * L, bsuf[q])) return false;
       }
       return far_ok();
     };
