@@ -130,7 +130,16 @@ struct ClipLDS {
   int32_t ps[PCAP];
   uint32_t stri[TCAP];
   R sx[TCAP], sy[TCAP], sz[TCAP];
-  FinalCoords<R, TCAP> fin;
+  // the batch of sites being clipped (by lane) while clipping; the float64
+  // final vertices while integrating
+  union {
+    FinalCoords<R, TCAP> fin;
+    struct {
+      double4 cand[64];
+      int32_t candj[64];
+      int32_t cands[64];
+    } batch;
+  } u;
   uint32_t bits[PCAP * PCAP / 32];   // directed dual edges of removed vertices
   uint32_t mem[PCAP * TCAP / 32];    // plane -> vertex membership (integrals)
   uint32_t sbits[PCAP / 32];
@@ -775,11 +784,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       key = wave_sort_u32(key);
       uint64_t tc0 = 0;
       if (STATS) tc0 = clock_stamp();
-      // the serial loop broadcasts one candidate at a time from its lane
+      // park the batch in LDS (frees its registers during the serial loop)
+      S.u.batch.cand[lane] = make_double4(dx, dy, dz, bb);
+      S.u.batch.candj[lane] = q;
+      S.u.batch.cands[lane] = shv;
+      const float dnf = float(dn);
+      __syncthreads();
       for (int r = 0; r < ns && !dead; ++r) {
         const int src = int(readlane_u(key, r) & 63u);
-        clip_one(readlane_d(dx, src), readlane_d(dy, src), readlane_d(dz, src), readlane_d(bb, src),
-                 readlane_d(dn, src), readlane_i(q, src), readlane_i(shv, src));
+        const double4 C = S.u.batch.cand[src];
+        clip_one(C.x, C.y, C.z, C.w, double(readlane_f(dnf, src)) * (1.0 + 1e-6), S.u.batch.candj[src],
+                 S.u.batch.cands[src]);
       }
       if (STATS) t_clip += clock_stamp() - tc0;
       __syncthreads();
@@ -1027,9 +1042,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       fvz[k] = vz[k];
     }
   } else {
-    FX = S.fin.x;
-    FY = S.fin.y;
-    FZ = S.fin.z;
+    FX = S.u.fin.x;
+    FY = S.u.fin.y;
+    FZ = S.u.fin.z;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       fvx[k] = fvy[k] = fvz[k] = 0.0;
