@@ -43,14 +43,15 @@ size_t solve_bytes_per_site(int64_t N) {
   //     stage lists 12 -> 2 x 52
   //   one face store: slots fslot x 16, overflow base 8, overflow ~1/8 of a
   //     slot row
-  //   J: row_ptr 8, row counts 8, 16 nonzeros per row x 12 (col + val)
+  //   J: row_ptr 8, row counts 8, diagonal 8, 16 neighbours per row x 12
+  //     (col + float64 weight; 8 with the mixed path's float weights)
   //   PCG r, z, p, q, 1/diag 40;  Newton psi, trial psi, g, step 32
   // The grid build's staging (40 bytes per site) is released before the
   // first pass for sets above 2^24 sites and fits in the pass buffers' share
   // below that.
   const size_t fslot = size_t(face_slots(N));
   const size_t faces = fslot * sizeof(FaceRec) + 8 + 2 * sizeof(FaceRec);
-  return 42 + 2 * 52 + faces + 16 + 16 * 12 + 40 + 32;
+  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 40 + 32;
 }
 
 namespace {
@@ -115,7 +116,7 @@ struct mak_ctx {
   PointSet sps;
   FaceStore sfaces;
   CellPass scp, scp_trial;
-  Csr sJ;
+  Lap sJ;
   PcgWork pw;
   DevBuf psi_s, psi_t, g, pstep, tmp;
   Profiler prof;
@@ -312,12 +313,15 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
       MAK_HIP(hipMemsetAsync(psi_s, 0, size_t(N) * sizeof(double), st));
     const double m = L * L * L / double(N);
 
-    auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Csr* warm) {
+    auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Lap* warm) {
       PassOpts po;
       po.precision = o.precision;
       po.tolerate_failure = tolerate;
       po.doom_vol = doom_vol;
-      po.warm = warm;
+      if (warm && warm->n == N) {
+        po.warm_rp = warm->row_ptr.as<int64_t>();
+        po.warm_col = warm->col.as<int32_t>();
+      }
       po.first_stage = o.first_stage;
       return ctx->runner ? ctx->runner->run(ps, cp, po, st) : run_cells(ps, cp, po, st);
     };
@@ -328,7 +332,7 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
     si.fp64_rerun_cells += cs.fp64_rerun;
     FlagStats fs = flag_stats(ps, ctx->scp, ctx->tmp, st);
     if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
-    build_csr(ps, ctx->scp, ctx->sJ, false, st);
+    build_lap(ps, ctx->scp, ctx->sJ, o.precision == MAK_MIXED, st);
     double err = 0, vmin = 0;
     double gn = residual_stats(ctx->scp.vol.as<double>(), m, N, ctx->tmp, &err, &vmin, st);
     const double eps0 = 0.5 * std::min(m, vmin);
@@ -383,7 +387,7 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
         if (v2 >= eps0 && g2 <= (1.0 - 0.5 * alpha) * gn) {
           swap_buf(ctx->psi_s, ctx->psi_t);
           swap_pass(ctx->scp, ctx->scp_trial);
-          build_csr(ps, ctx->scp, ctx->sJ, false, st);
+          build_lap(ps, ctx->scp, ctx->sJ, o.precision == MAK_MIXED, st);
           err = e2;
           gn = g2;
           vmin = v2;

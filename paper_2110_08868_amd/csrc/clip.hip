@@ -1303,10 +1303,8 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.pts = ps.pts.as<double4>();
   a.cell_start = ps.cell_start.as<int32_t>();
   a.block_suffix = ps.block_suffix.as<double>();
-  const Csr* warm = jb.opt.warm;
-  const bool use_warm = warm && warm->n == N && warm->row_ptr.p && warm->col.p;
-  a.warm_rp = use_warm ? warm->row_ptr.as<int64_t>() : nullptr;
-  a.warm_col = use_warm ? warm->col.as<int32_t>() : nullptr;
+  a.warm_rp = jb.opt.warm_rp && jb.opt.warm_col ? jb.opt.warm_rp : nullptr;
+  a.warm_col = a.warm_rp ? jb.opt.warm_col : nullptr;
   a.block_g = ps.block_g.as<double>();
   a.block_tmax = ps.block_tmax.as<double>();
   a.cell_tmax = ps.cell_tmax.as<double>();

@@ -15,10 +15,12 @@ __device__ __forceinline__ FaceRec* face_list(FaceRec* faces, FaceRec* ovf, cons
   return nf > fslot ? ovf + fbase[p] : faces + int64_t(p) * fslot;
 }
 
-// Sort the faces of each cell by (target column, shift); count distinct columns.
+// Sort the faces of each cell by (target column, shift); count distinct
+// columns (plus one for the diagonal when `diag_entry`).
 __global__ void k_sort_count(FaceRec* faces, FaceRec* ovf, const int64_t* fbase, int32_t fslot,
                              const int32_t* __restrict__ nface, const int32_t* __restrict__ perm,
-                             int64_t* __restrict__ rowcnt, int64_t* __restrict__ facecnt, int64_t n) {
+                             int64_t* __restrict__ rowcnt, int64_t* __restrict__ facecnt, int64_t n,
+                             int diag_entry) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int32_t nf = nface[p];
@@ -43,7 +45,7 @@ __global__ void k_sort_count(FaceRec* faces, FaceRec* ovf, const int64_t* fbase,
     prev = c;
   }
   const int64_t row = perm ? perm[p] : p;
-  rowcnt[row] = distinct + 1;
+  rowcnt[row] = distinct + diag_entry;
   if (facecnt) facecnt[row] = nf;
 }
 
@@ -84,6 +86,38 @@ __global__ void k_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* 
     col[o] = int32_t(row);
     val[o] = diag;
   }
+}
+
+// Laplacian rows (sorted space): one weight per distinct neighbour, summed
+// over its images in face order, and the diagonal as the sum of the stored
+// (rounded) weights.
+template <typename W>
+__global__ void k_lap_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* fbase, int32_t fslot,
+                           const int32_t* __restrict__ nface, const int64_t* __restrict__ row_ptr,
+                           int32_t* __restrict__ col, W* __restrict__ w, double* __restrict__ diag,
+                           int64_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t nf = nface[p];
+  const FaceRec* f = face_list(const_cast<FaceRec*>(faces), const_cast<FaceRec*>(ovf), fbase, fslot,
+                               int32_t(p), nf);
+  int64_t o = row_ptr[p];
+  double d = 0.0;
+  int32_t k = 0;
+  while (k < nf) {
+    const int32_t c = f[k].j;
+    double s = 0.0;
+    while (k < nf && f[k].j == c) {
+      s += f[k].w;
+      ++k;
+    }
+    const W ws = W(s);
+    col[o] = c;
+    w[o] = ws;
+    d += double(ws);
+    ++o;
+  }
+  diag[p] = d;
 }
 
 // Face lists in original order; the area is the stored weight times |d|,
@@ -129,7 +163,7 @@ void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hi
   hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
                      fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
                      perm, J.rowcnt.as<int64_t>(), original_space ? J.rowcnt.as<int64_t>() + n : nullptr,
-                     n);
+                     n, 1);
   MAK_HIP(hipGetLastError());
   exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr.as<int64_t>(), n, cp.scan_tmp, st);
   int64_t nnz = 0;
@@ -141,6 +175,40 @@ void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hi
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(), fst.ovf.as<FaceRec>(),
                      fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(), perm,
                      J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.val.as<double>(), n);
+  MAK_HIP(hipGetLastError());
+}
+
+void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t st) {
+  const int64_t n = ps.N;
+  ProfScope scope("csr_assembly", st, double(n));
+  J.n = n;
+  J.f32 = f32;
+  J.rowcnt.ensure(size_t(n) * sizeof(int64_t));
+  J.row_ptr.ensure(size_t(n + 1) * sizeof(int64_t));
+  J.diag.ensure(size_t(n) * sizeof(double));
+  const unsigned nb = unsigned(ceil_div(n, 256));
+  const FaceStore& fst = cp.fs();
+  hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
+                     fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
+                     nullptr, J.rowcnt.as<int64_t>(), nullptr, n, 0);
+  MAK_HIP(hipGetLastError());
+  exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr.as<int64_t>(), n, cp.scan_tmp, st);
+  int64_t nnz = 0;
+  MAK_HIP(hipMemcpyAsync(&nnz, J.row_ptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  J.nnz = nnz;
+  J.col.ensure(size_t(nnz) * sizeof(int32_t));
+  J.w.ensure(size_t(nnz) * (f32 ? sizeof(float) : sizeof(double)));
+  if (f32)
+    hipLaunchKernelGGL(k_lap_fill<float>, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
+                       fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
+                       J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.w.as<float>(),
+                       J.diag.as<double>(), n);
+  else
+    hipLaunchKernelGGL(k_lap_fill<double>, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
+                       fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
+                       J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.w.as<double>(),
+                       J.diag.as<double>(), n);
   MAK_HIP(hipGetLastError());
 }
 

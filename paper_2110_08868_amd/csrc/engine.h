@@ -129,6 +129,21 @@ struct Csr {
   DevBuf rowcnt;   // int64 [n]
 };
 
+// J in the solver's graph-Laplacian form: off-diagonal weights only,
+// w_ij = sum over the faces of cell i with images of site j of A / |d|
+// (J_ij = -w_ij), and the diagonal J_ii = sum_j w_ij of the stored weights,
+// so the rows sum to zero exactly.  Weights in float on the mixed path (the
+// CG vectors, dots and the diagonal stay float64), float64 otherwise.
+struct Lap {
+  int64_t n = 0, nnz = 0;
+  bool f32 = false;
+  DevBuf row_ptr;  // int64 [n + 1]
+  DevBuf col;      // int32 [nnz], sorted within a row
+  DevBuf w;        // float or double [nnz]
+  DevBuf diag;     // double [n]
+  DevBuf rowcnt;   // int64 [n]
+};
+
 // --- grid.hip
 // Wrap, validate and sort `points` (original order, device) into `ps`; psi may
 // be NULL (zeros).  Returns MAK_OK / EINVAL through exceptions.
@@ -155,9 +170,11 @@ struct PassOpts {
   // > 0 (a line-search trial): the first cell whose volume ends below it (or
   // empty) abandons the pass: ClipStats::doomed, outputs unspecified.
   double doom_vol = 0.0;
-  // J of an earlier pass over the same sorted sites (may be NULL): its rows
-  // are clipped first (a warm start; results differ only by rounding).
-  const Csr* warm = nullptr;
+  // Neighbour lists of an earlier pass over the same sorted sites (CSR rows;
+  // may be NULL): they are clipped first (a warm start; results differ only
+  // by rounding).
+  const int64_t* warm_rp = nullptr;
+  const int32_t* warm_col = nullptr;
   // Stage the pass starts at (0: the first kernel); > 0 runs every cell in
   // the fallback kernels (testing them).
   int first_stage = 0;
@@ -199,6 +216,8 @@ void set_pass_runner(::mak_ctx* ctx, PassRunner* r);
 // --- csr.hip
 // Assemble J (sorted index space, or original space when perm != NULL).
 void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hipStream_t st);
+// Assemble the solver's Laplacian form of J (sorted index space).
+void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t st);
 // Faces (original space) for mak_faces_copy; returns the face count.
 int64_t count_faces(const PointSet& ps, CellPass& cp, Csr& J, DevBuf& face_ptr, hipStream_t st);
 void copy_faces(const PointSet& ps, CellPass& cp, const DevBuf& face_ptr, int64_t* out_ptr,
@@ -219,7 +238,7 @@ struct PcgWork {
 };
 // Solve J x = b (b mean-free) with Jacobi-preconditioned CG; x is overwritten
 // (start from 0).  Returns the iteration count.
-int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
+int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
               PcgWork& w, hipStream_t st);
 
 // Elementwise helpers for the Newton driver.

@@ -41,22 +41,33 @@ unsigned vec_blocks(int64_t n) {
 // step covers most rows, and the loads of a lane are all in flight at once).
 constexpr int LPR = 4, UNR = 6;
 
+// A multiple of 8: workgroup b runs on XCD b mod 8 (round-robin dispatch),
+// and each XCD takes one contiguous eighth of the rows, so the gathers of p
+// by its rows (spatial neighbours in the grid-sorted order) stay in its own
+// L2 instead of all eight.
 unsigned spmv_blocks(int64_t n) {
-  const int64_t b = ceil_div(n, TPB / LPR);
-  return unsigned(b < SPMV_MAXB ? (b < 1 ? 1 : b) : SPMV_MAXB);
+  int64_t b = ceil_div(n, TPB / LPR);
+  b = b < SPMV_MAXB ? b : SPMV_MAXB;
+  return unsigned(ceil_div(b < 1 ? 1 : b, 8) * 8);
 }
 
-// q = J p, grid-stride over row groups, and per-block partial of p . q
+// q = J p for the Laplacian form (q_i = d_i p_i - sum_j w_ij p_j),
+// grid-stride over row groups, and per-block partial of p . q
+template <typename W>
 __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
-                                                  const double* __restrict__ val,
+                                                  const W* __restrict__ w,
+                                                  const double* __restrict__ diag,
                                                   const double* __restrict__ p, double* __restrict__ q,
                                                   double* __restrict__ part, int64_t n) {
   __shared__ double sh[TPB / WAVE];
   const int sub = threadIdx.x & (LPR - 1);
+  const int xcd = int(blockIdx.x & 7u);
+  const int64_t r0 = n * xcd / 8, r1 = n * (xcd + 1) / 8;
+  const int64_t step = int64_t(gridDim.x >> 3) * (TPB / LPR);
   double acc = 0.0;
-  for (int64_t row = int64_t(blockIdx.x) * (TPB / LPR) + (threadIdx.x / LPR); row < n;
-       row += int64_t(gridDim.x) * (TPB / LPR)) {
+  for (int64_t row = r0 + int64_t(blockIdx.x >> 3) * (TPB / LPR) + (threadIdx.x / LPR); row < r1;
+       row += step) {
     const int64_t b = rp[row], e = rp[row + 1];
     double s = 0.0;
     for (int64_t k = b + sub; k < e; k += UNR * LPR) {
@@ -66,7 +77,7 @@ __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp
       for (int u = 0; u < UNR; ++u) {
         const int64_t kk = k + u * LPR;
         c[u] = kk < e ? col[kk] : -1;
-        v[u] = kk < e ? val[kk] : 0.0;
+        v[u] = kk < e ? double(w[kk]) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) s += c[u] >= 0 ? v[u] * p[c[u]] : 0.0;
@@ -74,8 +85,10 @@ __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp
 #pragma unroll
     for (int o = LPR / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o);
     if (sub == 0) {
-      q[row] = s;
-      acc += s * p[row];
+      const double pr = p[row];
+      const double qi = diag[row] * pr - s;
+      q[row] = qi;
+      acc += qi * pr;
     }
   }
   acc = block_sum(acc, sh);
@@ -128,13 +141,10 @@ __global__ __launch_bounds__(TPB) void k_pupdate(double* __restrict__ p, const d
     p[i] = z[i] + beta * p[i];
 }
 
-__global__ void k_diag_inv(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                           const double* __restrict__ val, double* __restrict__ dinv, int64_t n) {
+__global__ void k_diag_inv(const double* __restrict__ diag, double* __restrict__ dinv, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double d = 0.0;
-  for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
-    if (col[k] == i) d = val[k];
+  const double d = diag[i];
   dinv[i] = d > 0.0 ? 1.0 / d : 1.0;
 }
 
@@ -183,7 +193,7 @@ __global__ void k_sub_mean(double* __restrict__ x, const double* __restrict__ sc
 
 }  // namespace
 
-int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
+int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
               PcgWork& w, hipStream_t st) {
   ProfScope whole("pcg_solve", st, double(n));
   w.r.ensure(size_t(n) * sizeof(double));
@@ -204,8 +214,7 @@ int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, 
   const unsigned nb = vec_blocks(n);
   const unsigned nbe = unsigned(ceil_div(n, 256));
 
-  hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
-                     J.col.as<int32_t>(), J.val.as<double>(), dinv, n);
+  hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.diag.as<double>(), dinv, n);
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, b, part, n);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_MEAN), 0);
   hipLaunchKernelGGL(k_init, dim3(nb), dim3(TPB), 0, st, b, scal, x, r, z, p, dinv, part, n);
@@ -221,11 +230,17 @@ int pcg_solve(const Csr& J, const double* b, double* x, int64_t n, double rtol, 
   for (; it < max_iter; ++it) {
     const int cur = (it & 1) ? S_RZ1 : S_RZ0, nxt = (it & 1) ? S_RZ0 : S_RZ1;
     {
-      // compulsory bytes: row_ptr, col, val, p (own row), q; flops 2 per nonzero + dot
-      ProfScope ps("spmv", st, double(n), 24.0 * double(n) + 12.0 * double(J.nnz));
-      ps.flops = 2.0 * double(J.nnz) + 2.0 * double(n);
-      hipLaunchKernelGGL(k_spmv_dot, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
-                         J.col.as<int32_t>(), J.val.as<double>(), p, q, part, n);
+      // compulsory bytes: row_ptr, diagonal, p (own row), q, and per nonzero
+      // col + weight; flops 2 per nonzero + the diagonal and the dot
+      const double wb = J.f32 ? 4.0 : 8.0;
+      ProfScope ps("spmv", st, double(n), 32.0 * double(n) + (4.0 + wb) * double(J.nnz));
+      ps.flops = 2.0 * double(J.nnz) + 4.0 * double(n);
+      if (J.f32)
+        hipLaunchKernelGGL(k_spmv_dot<float>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
+                           J.col.as<int32_t>(), J.w.as<float>(), J.diag.as<double>(), p, q, part, n);
+      else
+        hipLaunchKernelGGL(k_spmv_dot<double>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
+                           J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), p, q, part, n);
     }
     hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nbs), 1, scal, int(S_PQ), 0);
     {
