@@ -34,15 +34,23 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2110_08868_amd", "csrc")
 
 
-def kernel_source_hash() -> str:
-    """sha256 over the HIP sources: measured HBM traffic is only reported
-    for the kernels it was taken on."""
+# the sources each timed kernel is built from (its file and the headers it
+# includes)
+KERNEL_SOURCES = {
+    "clip": ["clip.hip", "engine.h", "common.h", "gridkey.h", "profile.h"],
+    "spmv": ["pcg.hip", "engine.h", "common.h", "profile.h"],
+}
+
+
+def kernel_source_hash(kernel: str = "clip") -> str:
+    """sha256 over the HIP sources of a kernel: measured HBM traffic is only
+    reported for the kernel code it was taken on."""
     import hashlib
+    files = KERNEL_SOURCES["clip" if kernel.startswith("clip") else "spmv"]
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(CSRC, f), "rb").read())
+    for f in sorted(files):
+        h.update(f.encode())
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
 
 
@@ -57,7 +65,7 @@ def measured_traffic(kernel, workload):
     for line in open(path):
         if line.startswith("{"):
             rec = json.loads(line)
-    if not rec or rec.get("source_sha256") != kernel_source_hash():
+    if not rec or rec.get("source_sha256") != kernel_source_hash(kernel):
         return None
     return rec["hbm_bytes_per_launch"]
 

@@ -40,6 +40,8 @@ def check(ctx, x, psi, L, hessian=True, **kw):
             Jg = csr_to_dense(rp, col, val, x.shape[0])
             Jo = oracle.hessian_dense(res, x.shape[0])
             assert np.abs(Jg - Jo).max() <= 1e-9 * max(np.abs(Jo).max(), 1e-300)
+            # A_ij from cell i and A_ji from cell j are computed apart
+            assert np.abs(Jg - Jg.T).max() <= 1e-10 * max(np.abs(Jg).max(), 1e-300)
         else:
             import scipy.sparse as sp
             Jg = sp.csr_matrix((val, col, rp), shape=(x.shape[0],) * 2)
@@ -251,3 +253,22 @@ def test_fallback_kernels_alone(precision, stage):
         assert info["fp64_rerun_cells"] == 0 or precision == "mixed"
     finally:
         c.close()
+
+
+def test_pyramid_identity_on_device(ctx):
+    """Device-side invariant, independent of the oracle: each cell is the union
+    of the pyramids from its site over its faces, V_i = sum_f A_f h_f / 3 with
+    h_f = (|d|^2/2 + psi_i - psi_j) / |d| the distance of face f from x_i
+    (cells small enough to have no face with an image of their own site)."""
+    n = 16
+    x = workloads.zeldovich(n, rms=0.6, smooth=1.0, seed=31)
+    psi = np.random.default_rng(31).uniform(-1, 1, n ** 3) * 0.05 / n ** 2
+    V, C, F, info = run(ctx, x, psi, 1.0)
+    fp, fj, fs, fa = F["face_ptr"], F["face_j"], F["face_shift"], F["face_area"]
+    i = np.repeat(np.arange(n ** 3), np.diff(fp))
+    d = x[fj] + fs * 1.0 - x[i]
+    dn = np.linalg.norm(d, axis=1)
+    h = (0.5 * dn ** 2 + psi[i] - psi[fj]) / dn
+    Vp = np.bincount(i, weights=fa * h / 3.0, minlength=n ** 3)
+    assert np.abs(Vp - V).max() <= 1e-10 * V.max()
+    assert V.sum() == pytest.approx(1.0, rel=1e-12)
