@@ -49,7 +49,8 @@ typedef enum {
   MAK_FP64 = 0,   /* clipping, integrals and Newton all in float64 */
   MAK_MIXED = 1   /* clipping in float32 seed-local coordinates, integrals
                      accumulated in float64, near-degenerate cells re-run in
-                     float64; Newton, line search and CG in float64 */
+                     float64; Newton, line search and CG vectors and dots in
+                     float64, the solver's Hessian weights stored in float32 */
 } mak_precision;
 
 typedef struct {

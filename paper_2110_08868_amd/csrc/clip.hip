@@ -835,7 +835,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     // Every site at distance >= t from x_i that lies in a block of shell
     // >= r is out of reach: the sites of shell q are farther than
     // max(t, (q - 1) bh + mb) and weigh at most bsuf[q] (the shell's maximum).
+    // (not unrolled: unrolled, the per-shell distances stay live through the
+    // whole walk and spill)
     auto beyond = [&](double t, int r) {
+#pragma unroll 1
       for (int q = r; q <= SHELL_MAX; ++q) {
         const double dq = fmax(t, q >= 1 ? (q - 1) * bh + mb : 0.0);
         if (!out_of_reach(dq - 1e-12 * L, bsuf[q])) return false;
