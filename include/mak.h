@@ -163,6 +163,17 @@ mak_status mak_solve(mak_ctx* ctx, const double* points, int64_t N, double L, do
                      double* psi, double* centroids, double* displacements,
                      mak_solve_info* info, void* stream);
 
+/* As mak_solve with a target mass per site instead of L^3 / N (Eq. SDK with
+ * weighted sites: sum_i m_i psi_i; each cell must end with volume m_i, e.g.
+ * sites standing for haloes of different masses):
+ *   masses  DEVICE (N,) float64, read only; every m_i > 0 and sum_i m_i = L^3
+ *           (to 1e-9 relative; MAK_EINVAL otherwise, uniform initial density)
+ * The stop test is max_i |V_i - m_i| / m_i <= tol and the line search uses
+ * eps0 = 1/2 min(min_i m_i, min_i V_i(0)). */
+mak_status mak_solve_masses(mak_ctx* ctx, const double* points, const double* masses, int64_t N,
+                            double L, double tol, double* psi, double* centroids,
+                            double* displacements, mak_solve_info* info, void* stream);
+
 /* As mak_solve, starting from the weights in `psi` (DEVICE, read and
  * overwritten): resumes a solve from a saved psi (the whole solver state). */
 mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double L, double tol,

@@ -17,7 +17,8 @@ Merigot and Thibert (the reference the paper gives for convergence):
 eps0 = 1/2 min(min_i m_i, min_i |V_i(psi^0)|); the step 2^-l p is accepted
 for the smallest l with min_i |V_i| >= eps0 and
 ||m - V||_2 <= (1 - 2^-(l+1)) ||m - V(psi^k)||_2.
-Masses are uniform, m_i = L^3 / N (initial density 1 and sum m_i = L^3).
+Masses default to uniform, m_i = L^3 / N (initial density 1, sum m_i = L^3);
+solve() also takes one target mass per site (Eq. SDK with weighted sites).
 """
 from __future__ import annotations
 
@@ -114,14 +115,20 @@ def newton_step_cg(J, g: np.ndarray, rtol: float = 1e-12, maxiter: int | None = 
 
 
 def solve(x, L: float, tol: float = 1e-6, max_newton: int = 50, threads: int = 0,
-          dense_max: int = 4096, psi0=None, log=None) -> dict:
+          dense_max: int = 4096, psi0=None, log=None, masses=None) -> dict:
     """Damped Newton maximisation of K(psi) until max_i |V_i - m_i| / m_i <= tol.
 
-    Returns psi (mean zero), centroids, displacements, the final cell result
-    and iteration statistics."""
+    masses: target volume per site (positive, summing to L^3); uniform
+    L^3 / N when omitted.  Returns psi (mean zero), centroids, displacements,
+    the final cell result and iteration statistics."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     n = x.shape[0]
-    m = np.full(n, L ** 3 / n)
+    if masses is None:
+        m = np.full(n, L ** 3 / n)
+    else:
+        m = np.array(masses, dtype=np.float64).reshape(n)
+        if not (np.all(m > 0) and abs(m.sum() - L ** 3) <= 1e-9 * L ** 3):
+            raise ValueError("masses must be positive and sum to L^3")
     psi = np.zeros(n) if psi0 is None else np.array(psi0, dtype=np.float64)
     res = cells(x, psi, L, threads=threads)
     if np.any(res["flags"] & 2):

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmak.so")
 EXPORTED_SYMBOLS = [
     "mak_default_options", "mak_create", "mak_destroy", "mak_last_error",
     "mak_laguerre_cells", "mak_hessian_copy", "mak_faces_copy", "mak_solve",
-    "mak_solve_from", "mak_solve_memory_estimate", "mak_profile_enable", "mak_profile_read",
+    "mak_solve_masses", "mak_solve_from", "mak_solve_memory_estimate", "mak_profile_enable", "mak_profile_read",
     "mak_profile_counters", "mak_server_create", "mak_server_submit", "mak_server_poll",
     "mak_server_wait", "mak_server_release", "mak_server_stats", "mak_server_last_error",
     "mak_server_destroy",
@@ -125,6 +125,8 @@ def load_library():
     lib.mak_faces_copy.restype = ctypes.c_int
     lib.mak_solve.argtypes = [P, P, I64, D, D, P, P, P, P, P]
     lib.mak_solve.restype = ctypes.c_int
+    lib.mak_solve_masses.argtypes = [P, P, P, I64, D, D, P, P, P, P, P]
+    lib.mak_solve_masses.restype = ctypes.c_int
     lib.mak_solve_from.argtypes = [P, P, I64, D, D, P, P, P, P, P]
     lib.mak_solve_from.restype = ctypes.c_int
     lib.mak_solve_memory_estimate.argtypes = [I64, I32]
@@ -303,9 +305,27 @@ class Context:
         self._check(st)
         return psi, C, D, _as_dict(info)
 
-    def solve(self, points, L: float, tol: float = 1e-6):
-        """Damped Newton OT solve from psi = 0: (psi, centroids, displacements, info)."""
-        return self._solve(self.lib.mak_solve, points, L, tol, None)
+    def solve(self, points, L: float, tol: float = 1e-6, masses=None):
+        """Damped Newton OT solve from psi = 0: (psi, centroids, displacements, info).
+        masses (optional, (N,) float64, positive, summing to L^3): the target
+        volume of each cell instead of L^3 / N."""
+        if masses is None:
+            return self._solve(self.lib.mak_solve, points, L, tol, None)
+        torch = _torch()
+        x = self._dev(points, (3,))
+        n = x.shape[0]
+        m = self._dev(masses)
+        if m.shape != (n,):
+            raise ValueError("masses must have shape (N,)")
+        psi = torch.empty(n, dtype=torch.float64, device=self.device)
+        C = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        D = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        info = _SolveInfo()
+        st = self.lib.mak_solve_masses(self._h, x.data_ptr(), m.data_ptr(), n, float(L), float(tol),
+                                       psi.data_ptr(), C.data_ptr(), D.data_ptr(), ctypes.byref(info),
+                                       self._stream())
+        self._check(st)
+        return psi, C, D, _as_dict(info)
 
     def solve_from(self, points, psi0, L: float, tol: float = 1e-6):
         """Resume a solve from saved weights psi0."""

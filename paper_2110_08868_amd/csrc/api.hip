@@ -45,13 +45,13 @@ size_t solve_bytes_per_site(int64_t N) {
   //     slot row
   //   J: row_ptr 8, row counts 8, diagonal 8, 16 neighbours per row x 12
   //     (col + float64 weight; 8 with the mixed path's float weights)
-  //   PCG r, z, p, q, 1/diag 40;  Newton psi, trial psi, g, step 32
+  //   PCG r, z, p, q, 1/diag 40;  Newton psi, trial psi, g, step, masses 40
   // The grid build's staging (40 bytes per site) is released before the
   // first pass for sets above 2^24 sites and fits in the pass buffers' share
   // below that.
   const size_t fslot = size_t(face_slots(N));
   const size_t faces = fslot * sizeof(FaceRec) + 8 + 2 * sizeof(FaceRec);
-  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 40 + 32;
+  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 40 + 40;
 }
 
 namespace {
@@ -118,7 +118,7 @@ struct mak_ctx {
   CellPass scp, scp_trial;
   Lap sJ;
   PcgWork pw;
-  DevBuf psi_s, psi_t, g, pstep, tmp;
+  DevBuf psi_s, psi_t, g, pstep, mass_s, tmp;
   Profiler prof;
   PassRunner* runner = nullptr;  // NULL: passes run on the solve's stream
 };
@@ -287,9 +287,9 @@ mak_status mak_faces_copy(mak_ctx* ctx, int64_t* face_ptr, int32_t* face_j, int3
   });
 }
 
-static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, double L, double tol,
-                             const double* psi0, double* psi, double* centroids, double* displacements,
-                             mak_solve_info* info, void* stream) {
+static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* masses, int64_t N,
+                             double L, double tol, const double* psi0, double* psi, double* centroids,
+                             double* displacements, mak_solve_info* info, void* stream) {
   if (!ctx) return MAK_EINVAL;
   const auto t0 = std::chrono::steady_clock::now();
   mak_solve_info si{};
@@ -312,6 +312,20 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
     else
       MAK_HIP(hipMemsetAsync(psi_s, 0, size_t(N) * sizeof(double), st));
     const double m = L * L * L / double(N);
+    // target masses: uniform L^3 / N, or per site (sorted into the solver's
+    // order; positive, summing to L^3)
+    const double* ms = nullptr;
+    double m_min = m;
+    if (masses) {
+      ctx->mass_s.ensure(size_t(N) * sizeof(double));
+      gather_sorted(ps, masses, ctx->mass_s.as<double>(), st);
+      ms = ctx->mass_s.as<double>();
+      const double msum = dev_reduce_sum(ms, N, ctx->tmp, st);
+      m_min = dev_reduce_min(ms, N, ctx->tmp, st);
+      const double total = L * L * L;
+      if (!(m_min > 0) || !std::isfinite(msum) || std::fabs(msum - total) > 1e-9 * total)
+        MAK_FAIL(MAK_EINVAL, "masses must be positive and sum to L^3");
+    }
 
     auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Lap* warm) {
       PassOpts po;
@@ -334,8 +348,8 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
     if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
     build_lap(ps, ctx->scp, ctx->sJ, o.precision == MAK_MIXED, st);
     double err = 0, vmin = 0;
-    double gn = residual_stats(ctx->scp.vol.as<double>(), m, N, ctx->tmp, &err, &vmin, st);
-    const double eps0 = 0.5 * std::min(m, vmin);
+    double gn = residual_stats(ctx->scp.vol.as<double>(), m, ms, N, ctx->tmp, &err, &vmin, st);
+    const double eps0 = 0.5 * std::min(m_min, vmin);
     if (o.verbose) fprintf(stderr, "[mak] N=%lld it=0 err=%.3e minV/m=%.3e\n", (long long)N, err, vmin / m);
     std::string noconv;
     for (int it = 0;; ++it) {
@@ -344,7 +358,7 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
         noconv = "Newton iteration limit reached, err=" + std::to_string(err);
         break;
       }
-      newton_residual(ctx->scp.vol.as<double>(), m, ctx->g.as<double>(), N, st);
+      newton_residual(ctx->scp.vol.as<double>(), m, ms, ctx->g.as<double>(), N, st);
       const int cgi = pcg_solve(ctx->sJ, ctx->g.as<double>(), ctx->pstep.as<double>(), N, o.cg_rtol,
                                 o.max_cg, ctx->pw, st);
       si.cg_iters_total += cgi;
@@ -379,7 +393,8 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
           continue;
         }
         double e2 = 0, v2 = 0;
-        const double g2 = residual_stats(ctx->scp_trial.vol.as<double>(), m, N, ctx->tmp, &e2, &v2, st);
+        const double g2 =
+            residual_stats(ctx->scp_trial.vol.as<double>(), m, ms, N, ctx->tmp, &e2, &v2, st);
         if (o.verbose >= 2)
           fprintf(stderr, "[mak]   trial alpha=%g pass %.1f ms retried=%lld: err=%.3e |g| %.3e -> %.3e minV/m=%.3e\n",
                   alpha, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count(),
@@ -423,14 +438,21 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, int64_t N, doub
 
 mak_status mak_solve(mak_ctx* ctx, const double* points, int64_t N, double L, double tol, double* psi,
                      double* centroids, double* displacements, mak_solve_info* info, void* stream) {
-  return solve_impl(ctx, points, N, L, tol, nullptr, psi, centroids, displacements, info, stream);
+  return solve_impl(ctx, points, nullptr, N, L, tol, nullptr, psi, centroids, displacements, info, stream);
+}
+
+mak_status mak_solve_masses(mak_ctx* ctx, const double* points, const double* masses, int64_t N,
+                            double L, double tol, double* psi, double* centroids, double* displacements,
+                            mak_solve_info* info, void* stream) {
+  if (!masses) return MAK_EINVAL;
+  return solve_impl(ctx, points, masses, N, L, tol, nullptr, psi, centroids, displacements, info, stream);
 }
 
 mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double L, double tol,
                           double* psi, double* centroids, double* displacements, mak_solve_info* info,
                           void* stream) {
   if (!psi) return MAK_EINVAL;
-  return solve_impl(ctx, points, N, L, tol, psi, psi, centroids, displacements, info, stream);
+  return solve_impl(ctx, points, nullptr, N, L, tol, psi, psi, centroids, displacements, info, stream);
 }
 
 mak_status mak_profile_enable(mak_ctx* ctx, int32_t flags) {

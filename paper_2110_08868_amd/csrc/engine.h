@@ -242,11 +242,14 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
               PcgWork& w, hipStream_t st);
 
 // Elementwise helpers for the Newton driver.
-void newton_residual(const double* vol, double m, double* g, int64_t n, hipStream_t st);
+// Target masses: per site (ms, sorted order) or, when ms is NULL, m for all.
+void newton_residual(const double* vol, double m, const double* ms, double* g, int64_t n,
+                     hipStream_t st);
 void axpy_into(const double* psi, const double* p, double alpha, double* out, int64_t n,
                hipStream_t st);
-double residual_stats(const double* vol, double m, int64_t n, DevBuf& tmp, double* max_rel,
-                      double* min_vol, hipStream_t st);
+// Returns ||m - V||_2; max_rel = max_i |m_i - V_i| / m_i, min_vol = min_i V_i.
+double residual_stats(const double* vol, double m, const double* ms, int64_t n, DevBuf& tmp,
+                      double* max_rel, double* min_vol, hipStream_t st);
 void finalize_outputs(const PointSet& ps, const double* psi_sorted, double psi_mean,
                       const double* vol, const double* mom, double* psi_out, double* cent_out,
                       double* disp_out, hipStream_t st);

@@ -277,19 +277,23 @@ __global__ void k_axpy_into(const double* __restrict__ a, const double* __restri
   if (i < n) out[i] = a[i] + alpha * b[i];
 }
 
-__global__ void k_residual(const double* __restrict__ vol, double m, double* __restrict__ g, int64_t n) {
+// target masses: per site (ms, sorted order) or uniform (m when ms is NULL)
+__global__ void k_residual(const double* __restrict__ vol, double m, const double* __restrict__ ms,
+                           double* __restrict__ g, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) g[i] = m - vol[i];
+  if (i < n) g[i] = (ms ? ms[i] : m) - vol[i];
 }
 
-// partials: max |m - V|, min V, sum (m - V)^2
+// partials: max |m_i - V_i| / m_i, min V, sum (m_i - V_i)^2
 __global__ __launch_bounds__(TPB) void k_res_stats(const double* __restrict__ vol, double m,
+                                                   const double* __restrict__ ms,
                                                    double* __restrict__ part, int64_t n) {
   __shared__ double sh[TPB];
   double amax = 0.0, vmin = DBL_MAX, ss = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
-    const double g = m - vol[i];
-    amax = fmax(amax, fabs(g));
+    const double mi = ms ? ms[i] : m;
+    const double g = mi - vol[i];
+    amax = fmax(amax, fabs(g) / mi);
     vmin = fmin(vmin, vol[i]);
     ss += g * g;
   }
@@ -381,23 +385,24 @@ void axpy_into(const double* a, const double* b, double alpha, double* out, int6
   MAK_HIP(hipGetLastError());
 }
 
-void newton_residual(const double* vol, double m, double* g, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_residual, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st, vol, m, g, n);
+void newton_residual(const double* vol, double m, const double* ms, double* g, int64_t n,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_residual, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st, vol, m, ms, g, n);
   MAK_HIP(hipGetLastError());
 }
 
-double residual_stats(const double* vol, double m, int64_t n, DevBuf& tmp, double* max_rel,
-                      double* min_vol, hipStream_t st) {
+double residual_stats(const double* vol, double m, const double* ms, int64_t n, DevBuf& tmp,
+                      double* max_rel, double* min_vol, hipStream_t st) {
   tmp.ensure(size_t(3 * MAXB + 8) * sizeof(double));
   double* part = tmp.as<double>();
   const unsigned nb = vec_blocks(n);
-  hipLaunchKernelGGL(k_res_stats, dim3(nb), dim3(TPB), 0, st, vol, m, part, n);
+  hipLaunchKernelGGL(k_res_stats, dim3(nb), dim3(TPB), 0, st, vol, m, ms, part, n);
   hipLaunchKernelGGL(k_res_final, dim3(1), dim3(64), 0, st, part, int(nb), part + 3 * MAXB);
   MAK_HIP(hipGetLastError());
   double h[3];
   MAK_HIP(hipMemcpyAsync(h, part + 3 * MAXB, sizeof(h), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));
-  *max_rel = h[0] / m;
+  *max_rel = h[0];
   *min_vol = h[1];
   return std::sqrt(h[2]);
 }

@@ -66,16 +66,26 @@ def layered_cells(X, psi_layer, ny, nz, L):
     return V, ux, J
 
 
-def layered_ot_psi(X, L):
-    """Layer weights of the optimal transport (all widths L/n), psi_0 = 0."""
+def layered_ot_psi(X, L, widths=None):
+    """Layer weights psi (psi_0 = 0) and upper layer boundaries b of the
+    transport that gives layer a the slab width widths[a] (all L/n when
+    omitted; widths sum to L).
+
+    Layer a occupies [b_{a-1}, b_a] with b_a = b_0 + c_a, c_a = sum_{k=1..a}
+    widths[k].  The boundary between sites X_a and X_{a+1} (spacing d_a,
+    midpoint p_a) sits at b_a when psi_{a+1} - psi_a = -d_a (b_a - p_a); going
+    once round the period returns to psi_0, so sum_a d_a (b_a - p_a) = 0,
+    which fixes b_0 = sum_a d_a (p_a - c_a) / L."""
     X = np.asarray(X, dtype=np.float64)
     n = X.shape[0]
+    w = np.full(n, L / n) if widths is None else np.asarray(widths, dtype=np.float64)
+    assert w.shape == (n,) and abs(w.sum() - L) <= 1e-12 * L
     Xn = np.append(X, X[0] + L)
     d = Xn[1:] - Xn[:-1]
     p = 0.5 * (Xn[:-1] + Xn[1:])
-    a = np.arange(n)
-    b0 = np.sum(d * (p - a * L / n)) / L
-    b = b0 + a * L / n
+    c = np.concatenate([[0.0], np.cumsum(w[1:])])
+    b0 = np.sum(d * (p - c)) / L
+    b = b0 + c
     psi = np.zeros(n)
     for k in range(n - 1):
         psi[k + 1] = psi[k] - d[k] * (b[k] - p[k])

@@ -100,3 +100,73 @@ def test_damped_steps_certified(ctx):
     dpsi -= dpsi.mean()
     D2 = (1.0 / n) ** 2
     assert np.sqrt(np.mean(dpsi ** 2)) <= 1e-5 * D2
+
+
+# ------------------------------------------------------- per-site target masses
+def msolve(ctx, x, L, tol, m):
+    import torch
+    psi, C, D, info = ctx.solve(torch.from_numpy(x), L, tol, masses=torch.from_numpy(m))
+    print(f"  solve with masses N={x.shape[0]}: {info}", flush=True)
+    return psi.cpu().numpy(), C.cpu().numpy(), D.cpu().numpy(), info
+
+
+def test_masses_layered_closed_form(ctx):
+    """Slabs of unequal prescribed widths: closed-form weights, and the oracle's
+    cells at the returned weights have the prescribed volumes."""
+    from tests.closed_forms import layered_ot_psi
+    rng = np.random.default_rng(11)
+    nl, ny = 5, 4
+    X = np.sort(rng.uniform(0, 1, nl))
+    w = rng.uniform(0.5, 1.5, nl)
+    w /= w.sum()
+    psi_l, _ = layered_ot_psi(X, 1.0, widths=w)
+    x = workloads.layered(X, ny, ny)
+    m = np.repeat(w / ny ** 2, ny * ny)
+    psi, C, D, info = msolve(ctx, x, 1.0, 1e-11, m)
+    assert info["newton_iters"] > 0
+    ref = np.repeat(psi_l, ny * ny)
+    assert np.allclose(psi, ref - ref.mean(), atol=1e-11)
+    r = oracle.cells(x, psi, 1.0)
+    assert np.max(np.abs(r["V"] - m) / m) <= 1e-11 * 1.001
+
+
+def test_masses_recover_weights(ctx):
+    """Masses taken from the cells of a random weight vector (volumes from 0.1
+    to 2.8 times the mean): the solve returns that vector up to a constant
+    and agrees with the oracle's own masses solve."""
+    n = 8
+    x = workloads.zeldovich(n, rms=0.6, smooth=1.0, seed=9)
+    rng = np.random.default_rng(9)
+    psi0 = rng.uniform(-1, 1, len(x)) * 0.04 / n ** 2
+    m = oracle.cells(x, psi0, 1.0)["V"]
+    psi, C, D, info = msolve(ctx, x, 1.0, 1e-10, m)
+    r = oracle.cells(x, psi, 1.0)
+    err = float(np.max(np.abs(r["V"] - m) / m))
+    print(f"  certificate err={err:.3e}", flush=True)
+    assert err <= 1e-10 * 1.001
+    assert np.allclose(psi, psi0 - psi0.mean(), atol=1e-9 / n ** 2)
+    s = oracle.solve(x, 1.0, tol=1e-12, masses=m)
+    assert np.allclose(D, s["disp"], atol=1e-9 / n)
+
+
+def test_masses_uniform_matches_mak_solve(ctx):
+    """Uniform masses through mak_solve_masses: the same bits as mak_solve."""
+    x = workloads.zeldovich(8, rms=0.5, smooth=1.0, seed=3)
+    N = len(x)
+    a = gsolve(ctx, x, 1.0, 1e-8)
+    b = msolve(ctx, x, 1.0, 1e-8, np.full(N, 1.0 / N))
+    for u, v in zip(a[:3], b[:3]):
+        assert np.array_equal(u, v)
+
+
+def test_masses_rejected(ctx):
+    import torch
+    import paper_2110_08868_amd as mak
+    x = workloads.zeldovich(4, rms=0.3, smooth=1.0, seed=2)
+    N = len(x)
+    for m in (np.full(N, 2.0 / N), np.concatenate([[-1.0 / N, 3.0 / N], np.full(N - 2, 1.0 / N)])):
+        with pytest.raises(mak.MakError) as e:
+            ctx.solve(torch.from_numpy(x), 1.0, 1e-6, masses=torch.from_numpy(m))
+        assert e.value.name == "MAK_EINVAL"
+    # the context is still usable
+    gsolve(ctx, x, 1.0, 1e-6)

@@ -144,6 +144,47 @@ def test_p4_layered_ot_solution():
     assert np.allclose(np.diff(cx), L / nl, atol=1e-9)
 
 
+# ------------------------------------------------ P4b layered OT, given masses
+def test_p4b_layered_ot_with_masses():
+    """Layers of prescribed, unequal slab widths: the closed-form weights give
+    cells of volume width * dy * dz, and Newton with those masses reaches them."""
+    rng = np.random.default_rng(11)
+    L = 1.0
+    nl, ny = 5, 4
+    X = np.sort(rng.uniform(0, L, nl))
+    w = rng.uniform(0.5, 1.5, nl)
+    w *= L / w.sum()
+    psi_l, b = layered_ot_psi(X, L, widths=w)
+    assert np.allclose(np.diff(b), w[1:])
+    x = workloads.layered(X, ny, ny, L)
+    psi = np.repeat(psi_l, ny * ny)
+    m = np.repeat(w * (L / ny) ** 2, ny * ny)
+    r = oracle.cells(x, psi, L)
+    assert np.allclose(r["V"], m, rtol=1e-11)
+    s = oracle.solve(x, L, tol=1e-11, masses=m)
+    assert s["newton_iters"] > 0
+    assert np.allclose(s["psi"], psi - psi.mean(), atol=1e-10)
+    # uniform widths reduce to the equal-mass solve
+    psi_u, _ = layered_ot_psi(X, L, widths=np.full(nl, L / nl))
+    assert np.array_equal(psi_u, layered_ot_psi(X, L)[0])
+
+
+def test_p4c_masses_of_a_weight_vector_recover_it():
+    """The dual maximiser is unique up to a constant: solving for the volumes
+    V(psi) of a random weight vector returns that vector."""
+    x, psi = _random_case(n=4, seed=9, wscale=0.04)
+    r = oracle.cells(x, psi, 1.0)
+    s = oracle.solve(x, 1.0, tol=1e-12, masses=r["V"])
+    assert s["newton_iters"] > 0
+    assert np.allclose(s["psi"], psi - psi.mean(), atol=1e-11 / 16)
+    with pytest.raises(ValueError):
+        oracle.solve(x, 1.0, masses=np.full(len(x), 2.0 / len(x)))
+    bad = r["V"].copy()
+    bad[0], bad[1] = -bad[0], bad[1] + 2 * bad[0]
+    with pytest.raises(ValueError):
+        oracle.solve(x, 1.0, masses=bad)
+
+
 # ---------------------------------------------------------------- P5 invariants
 def _random_case(n=6, seed=3, wscale=0.03):
     x = workloads.zeldovich(n, rms=0.6, smooth=1.0, seed=seed)
