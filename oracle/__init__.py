@@ -15,9 +15,13 @@ Contents
                          concave and C^2, maximised by Newton with the
                          Kitagawa-Merigot-Thibert step control), dense Newton
                          step for small N, plain CG otherwise.
+  legendre(x, psi, L, q) Legendre transform of the weights at query points:
+                         phi(q), the index of the Laguerre cell holding q,
+                         and the transport displacement (brute force).
   exact                  exact-rational mini oracle (Python fractions).
 """
 from .cells import cells, cell_faces_dict, load_library
+from .legendre import legendre
 from .newton import (
     hessian_dense,
     hessian_coo,
@@ -32,6 +36,7 @@ __all__ = [
     "cells",
     "cell_faces_dict",
     "load_library",
+    "legendre",
     "hessian_dense",
     "hessian_coo",
     "kantorovich",

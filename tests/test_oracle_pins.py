@@ -342,3 +342,118 @@ def test_oracle_flags():
     r = oracle.cells(x, psi, 1.0)
     assert r["flags"][0] & 1 and r["V"][0] == 0.0
     assert r["V"].sum() == pytest.approx(1.0, rel=1e-12)
+
+
+# ------------------------------------------------ P9 Legendre transform / location
+def test_p9_legendre_lattice_closed_form():
+    """psi = 0 on the lattice ((k + 1/2) s): phi is half the squared distance to
+    the nearest lattice node, per axis, and i(q) is that node."""
+    n, L = 4, 1.0
+    s = L / n
+    x = workloads.lattice(n, L)
+    rng = np.random.default_rng(21)
+    q = rng.uniform(-0.5, 1.5, (200, 3))
+    phi, idx, disp = oracle.legendre(x, np.zeros(len(x)), L, q)
+    u = q / s - 0.5
+    k = np.round(u)
+    f = (u - k) * s
+    assert np.allclose(phi, 0.5 * np.sum(f * f, axis=1), rtol=1e-12, atol=1e-15)
+    kk = np.mod(k, n).astype(np.int64)
+    assert np.array_equal(idx, (kk[:, 0] * n + kk[:, 1]) * n + kk[:, 2])
+    assert np.allclose(disp, -f, atol=1e-14)
+
+
+def test_p9_legendre_layered_closed_form():
+    """Layers with the closed-form transport weights: q lies in the slab of the
+    layer a with b_{a-1} < q_x - kL < b_a, and phi follows from that layer's
+    image and the nearest yz-lattice line."""
+    rng = np.random.default_rng(23)
+    L, nl, ny = 1.0, 5, 3
+    X = np.sort(rng.uniform(0, L, nl))
+    w = rng.uniform(0.5, 1.5, nl)
+    w *= L / w.sum()
+    psi_l, b = layered_ot_psi(X, L, widths=w)
+    x = workloads.layered(X, ny, ny, L)
+    psi = np.repeat(psi_l, ny * ny)
+    q = rng.uniform(0, L, (300, 3))
+    phi, idx, disp = oracle.legendre(x, psi, L, q)
+    lo = np.concatenate([[b[-1] - L], b[:-1]])
+    s = L / ny
+    for t in range(len(q)):
+        hits = [(a, k) for a in range(nl) for k in (-1, 0, 1)
+                if lo[a] < q[t, 0] - k * L < b[a]]
+        assert len(hits) == 1
+        a, k = hits[0]
+        dx = X[a] + k * L - q[t, 0]
+        uy, uz = q[t, 1] / s - 0.5, q[t, 2] / s - 0.5
+        fy, fz = (uy - np.round(uy)) * s, (uz - np.round(uz)) * s
+        ref = 0.5 * (dx * dx + fy * fy + fz * fz) - psi_l[a]
+        assert phi[t] == pytest.approx(ref, rel=1e-12, abs=1e-15)
+        iy, iz = int(np.round(uy)) % ny, int(np.round(uz)) % ny
+        assert idx[t] == (a * ny + iy) * ny + iz
+        assert np.allclose(disp[t], [dx, -fy, -fz], atol=1e-14)
+
+
+def test_p9_legendre_pure_python_brute_force():
+    rng = np.random.default_rng(25)
+    L = 2.0
+    x = rng.uniform(0, L, (7, 3))
+    psi = rng.uniform(-0.2, 0.2, 7)
+    q = rng.uniform(0, L, (6, 3))
+    phi, idx, disp = oracle.legendre(x, psi, L, q)
+    for t in range(len(q)):
+        best = None
+        for i in range(len(x)):
+            for kx in (-1, 0, 1):
+                for ky in (-1, 0, 1):
+                    for kz in (-1, 0, 1):
+                        d = [x[i][0] + kx * L - q[t][0], x[i][1] + ky * L - q[t][1],
+                             x[i][2] + kz * L - q[t][2]]
+                        v = 0.5 * (d[0] ** 2 + d[1] ** 2 + d[2] ** 2) - psi[i]
+                        if best is None or v < best[0]:
+                            best = (v, i, d)
+        assert phi[t] == pytest.approx(best[0], rel=1e-13, abs=1e-15)
+        assert idx[t] == best[1]
+        assert np.allclose(disp[t], best[2], atol=1e-14)
+
+
+def test_p9_legendre_raster_matches_cells():
+    """Mesh nodes located in cell i: their number times the node volume
+    approaches V_i and their mean position the centroid (the C++ cell oracle)."""
+    x, psi = _random_case(n=4, seed=27, wscale=0.03)
+    L, ng = 1.0, 40
+    q = workloads.mesh_points(ng, L, 0.5)
+    phi, idx, disp = oracle.legendre(x, psi, L, q)
+    r = oracle.cells(x, psi, L)
+    cnt = np.bincount(idx, minlength=len(x)) * (L / ng) ** 3
+    assert np.sum(np.abs(cnt - r["V"])) <= 0.03 * L ** 3
+    assert np.max(np.abs(cnt - r["V"]) / r["V"]) <= 0.2
+    # mean displacement x_i - q over the nodes of cell i = minus the centroid offset
+    mu = np.stack([np.bincount(idx, weights=disp[:, a], minlength=len(x)) for a in range(3)], 1)
+    mu /= np.bincount(idx, minlength=len(x))[:, None]
+    ubar = r["M"] / r["V"][:, None]
+    big = r["V"] > 0.5 / len(x)
+    assert np.max(np.abs(mu[big] + ubar[big])) <= 0.3 / 4
+
+
+def test_p9_legendre_potential_convex():
+    """Phi(q) = 1/2 |q|^2 - phi(q) (Eq. potpot) is a maximum of affine functions
+    of q, hence convex along any line, across the box boundary too."""
+    x, psi = _random_case(n=3, seed=29, wscale=0.05)
+    L = 1.0
+    rng = np.random.default_rng(29)
+    for _ in range(4):
+        q0 = rng.uniform(-0.5, 1.5, 3)
+        e = rng.normal(size=3)
+        e /= np.linalg.norm(e)
+        t = np.linspace(0, 1.5, 601)
+        q = q0[None, :] + t[:, None] * e[None, :]
+        phi, _, disp = oracle.legendre(x, psi, L, q)
+        Phi = 0.5 * np.sum(q * q, axis=1) - phi
+        d2 = Phi[:-2] - 2 * Phi[1:-1] + Phi[2:]
+        assert d2.min() >= -1e-12
+        # the slope of Phi along e is e . T(q), T(q) = q + disp the image of the
+        # minimising site: monotone along the line (no shell crossing)
+        slope = (q + disp) @ e
+        assert np.diff(slope).min() >= -1e-12
+        assert np.diff(slope).max() > 0

@@ -15,6 +15,7 @@ clumps to mimic collapsed haloes.
 from .zeldovich import (
     lattice,
     layered,
+    mesh_points,
     zeldovich,
     plummer_redraw,
     clustered,
@@ -26,6 +27,7 @@ from .zeldovich import (
 __all__ = [
     "lattice",
     "layered",
+    "mesh_points",
     "zeldovich",
     "plummer_redraw",
     "clustered",

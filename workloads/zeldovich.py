@@ -59,6 +59,14 @@ def layered(xs, ny: int, nz: int, L: float = 1.0) -> np.ndarray:
     return np.stack([A.ravel(), B.ravel(), C.ravel()], axis=1).astype(np.float64)
 
 
+def mesh_points(ng: int, L: float = 1.0, offset: float = 0.0) -> np.ndarray:
+    """The ng^3 mesh nodes ((a, b, c) + offset) L/ng, a, b, c in [0, ng), in
+    row order (a, b, c) with c fastest."""
+    k = (np.arange(ng, dtype=np.float64) + offset) * (L / ng)
+    A, B, C = np.meshgrid(k, k, k, indexing="ij")
+    return np.stack([A.ravel(), B.ravel(), C.ravel()], axis=1)
+
+
 def _fft_workers() -> int:
     return max(1, min(16, os.cpu_count() or 1))
 
