@@ -10,8 +10,10 @@ value = Laguerre cells computed per second over the timed solves
 
 Also reported: the other precision path on the same input, the roofline of
 the dominant kernel (HIP-event durations of its launches in the timed region,
-counted work from a separate counting solve), and the CPU oracle timed on a
-bounded sample of the same workload.
+counted work from a separate counting solve), the Legendre transform of the
+solved weights on a mesh of N nodes (the initial potential and the location
+of every node), serving, and the CPU oracle timed on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -39,6 +41,7 @@ CSRC = os.path.join(ROOT, "paper_2110_08868_amd", "csrc")
 KERNEL_SOURCES = {
     "clip": ["clip.hip", "engine.h", "common.h", "gridkey.h", "profile.h"],
     "spmv": ["pcg.hip", "engine.h", "common.h", "profile.h"],
+    "locate": ["locate.hip", "engine.h", "common.h", "gridkey.h", "profile.h"],
 }
 
 
@@ -46,7 +49,7 @@ def kernel_source_hash(kernel: str = "clip") -> str:
     """sha256 over the HIP sources of a kernel: measured HBM traffic is only
     reported for the kernel code it was taken on."""
     import hashlib
-    files = KERNEL_SOURCES["clip" if kernel.startswith("clip") else "spmv"]
+    files = KERNEL_SOURCES["clip" if kernel.startswith("clip") else kernel]
     h = hashlib.sha256()
     for f in sorted(files):
         h.update(f.encode())
@@ -168,6 +171,41 @@ def roofline(prof, cprof, workload):
                "bytes_per_launch": per_launch_bytes}
     share = {k: round(kern[k]["total_ms"], 3) for k in kern}
     return out, share
+
+
+def legendre_leg(mak, x_dev, psi, L, ng, reps, workload):
+    """Legendre transform of the solved weights on the ng^3 mesh (node offset
+    1/2): phi, cell index and displacement of every node.  HIP-event time of
+    the locate kernel over `reps` calls, and of the whole call (site grid
+    build included).  Algorithmic bytes per launch: 36 B written per node
+    (phi 8, index 4, displacement 24) and 32 B read per site."""
+    import torch
+    ctx = mak.Context(0)
+    ctx.legendre_mesh(x_dev, psi, L, ng, 0.5)
+    ctx.profile_enable(timing=True, counting=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.legendre_mesh(x_dev, psi, L, ng, 0.5)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.close()
+    v = prof["locate"]
+    avg_ms = v["total_ms"] / v["launches"]
+    bytes_pl = v["bytes"] / v["launches"]
+    achieved = bytes_pl / (avg_ms * 1e-3) / 1e9
+    Q = ng ** 3
+    return {"mesh": ng, "nodes": Q, "calls": reps,
+            "nodes_per_s_kernel": Q / (avg_ms * 1e-3),
+            "nodes_per_s_call": Q * reps / (t1 - t0),
+            "ms_per_call": (t1 - t0) / reps * 1e3,
+            "grid_build_ms": prof["grid_build"]["total_ms"] / prof["grid_build"]["launches"],
+            "roofline": {"kernel": "locate", "bound": "hbm", "achieved": achieved,
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                         "traffic": measured_traffic("locate", workload),
+                         "avg_launch_ms": avg_ms, "launches": v["launches"],
+                         "bytes_per_launch": bytes_pl}}
 
 
 def compare_paths(a, b, L, N):
@@ -314,6 +352,8 @@ def main():
                     help="cells of the mixed path checked against the oracle")
     ap.add_argument("--serving-requests", type=int, default=32,
                     help="requests of the serving leg (the full serving workload is 256; 0 = skip)")
+    ap.add_argument("--legendre-reps", type=int, default=5,
+                    help="calls of the Legendre transform on the mesh at the solved weights (0 = skip)")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-oracle-check", action="store_true",
@@ -389,6 +429,10 @@ def main():
     if (precision == "mixed" or other == "mixed") and not args.no_oracle_check:
         res["mixed_vs_oracle"] = accuracy_vs_oracle(mak, x, out if precision == "mixed" else out2, L,
                                                     sample=args.oracle_sample)
+    if args.legendre_reps > 0:
+        ng = round(N ** (1.0 / 3.0))
+        log(f"[bench] Legendre transform on the {ng}^3 mesh ...")
+        res["legendre"] = legendre_leg(mak, x_dev, out[0], L, ng, args.legendre_reps, args.workload)
     if args.serving_requests > 0:
         res["serving"] = serving(mak, args.serving_requests, args.serving_slots,
                                  args.serving_budget_gb, precision, tol, args.cg_rtol)

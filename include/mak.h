@@ -180,6 +180,35 @@ mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double 
                           double* psi, double* centroids, double* displacements,
                           mak_solve_info* info, void* stream);
 
+/* ---- Legendre transform of the weights and point location ----
+ * Sec. 2, the equation after Eq. laguerrecell (with Eqs. potpot and
+ * Legendre): the initial potential at a Lagrangian point q is
+ *   phi(q) = min_i min_k [ 1/2 |q - x_i - k L|^2 - psi_i ]
+ * (k over the periodic images), attained at i(q), the Laguerre cell that
+ * holds q; x_{i(q)} + k L is where the transport map sends q.
+ *   points   DEVICE (N, 3) float64, read only (wrapped like mak_laguerre_cells)
+ *   psi      DEVICE (N,) float64, read only; NULL means all zero
+ *   queries  DEVICE (Q, 3) float64, read only; any finite coordinates (taken
+ *            modulo L); a non-finite one gives MAK_EINVAL (outputs then
+ *            unspecified)
+ *   phi      DEVICE (Q,) float64 out, or NULL
+ *   idx      DEVICE (Q,) int32 out, or NULL: i(q), the original site index
+ *   disp     DEVICE (Q, 3) float64 out, or NULL: x_{i(q)} + k L - q for the
+ *            minimising image
+ * Arithmetic is float64.  Where several sites attain the minimum to within
+ * rounding, idx names one of them.  Builds its own copy of the site grid in
+ * the context (independent of the last cell pass); synchronises `stream`. */
+mak_status mak_legendre(mak_ctx* ctx, const double* points, const double* psi, int64_t N, double L,
+                        const double* queries, int64_t Q, double* phi, int32_t* idx, double* disp,
+                        void* stream);
+
+/* The same at the ng^3 mesh nodes q_abc = ((a, b, c) + offset) L / ng,
+ * a, b, c in [0, ng) (1 <= ng <= 4096; offset in mesh spacings, e.g. 0 or
+ * 0.5), generated on the device; outputs in row order (a, b, c), c fastest. */
+mak_status mak_legendre_mesh(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
+                             double L, int64_t ng, double offset, double* phi, int32_t* idx,
+                             double* disp, void* stream);
+
 /* ---- kernel profile (diagnostics; used by the benchmark) ----
  * When timing is enabled, the library brackets its main kernels with HIP
  * events on the stream each is launched on and accumulates their durations;
@@ -188,7 +217,7 @@ mak_status mak_solve_from(mak_ctx* ctx, const double* points, int64_t N, double 
  * separate runs). */
 typedef struct {
   char name[32];       /* "clip", "clip_large", "spmv", "pcg_update", "pcg_solve",
-                          "csr_assembly", "grid_build" */
+                          "csr_assembly", "grid_build", "locate" */
   int64_t launches;
   double total_ms;     /* summed event durations */
   double units;        /* work items processed (cells, rows) */

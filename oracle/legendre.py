@@ -41,20 +41,22 @@ def legendre(x, psi, L: float, q, chunk_elems: int = 1 << 22):
     q = _wrap(q, L)
     psi = np.asarray(psi, dtype=np.float64)
     n, nq = x.shape[0], q.shape[0]
-    img = x[:, None, :] + L * _SHIFTS[None, :, :]          # (n, 27, 3)
-    img_flat = img.reshape(-1, 3)
-    w_flat = np.repeat(psi, 27)
-    phi = np.empty(nq)
-    idx = np.empty(nq, dtype=np.int64)
-    disp = np.empty((nq, 3))
-    step = max(1, chunk_elems // img_flat.shape[0])
-    for s in range(0, nq, step):
-        qc = q[s:s + step]
-        d = img_flat[None, :, :] - qc[:, None, :]          # (c, 27 n, 3)
-        v = 0.5 * np.einsum("cij,cij->ci", d, d) - w_flat[None, :]
-        k = np.argmin(v, axis=1)
-        r = np.arange(qc.shape[0])
-        phi[s:s + step] = v[r, k]
-        idx[s:s + step] = k // 27
-        disp[s:s + step] = d[r, k]
+    phi = np.full(nq, np.inf)
+    idx = np.full(nq, -1, dtype=np.int64)
+    disp = np.zeros((nq, 3))
+    sc = max(1, min(n, chunk_elems // 27))                 # sites per chunk
+    qc = max(1, chunk_elems // (27 * sc))                  # queries per chunk
+    for s in range(0, nq, qc):
+        qq = q[s:s + qc]
+        r = np.arange(qq.shape[0])
+        for j in range(0, n, sc):
+            img = x[j:j + sc, None, :] + L * _SHIFTS[None, :, :]   # (m, 27, 3)
+            d = img.reshape(1, -1, 3) - qq[:, None, :]               # (c, 27 m, 3)
+            v = 0.5 * np.einsum("cij,cij->ci", d, d) - np.repeat(psi[j:j + sc], 27)[None, :]
+            k = np.argmin(v, axis=1)
+            better = v[r, k] < phi[s:s + qc]                         # first minimum wins
+            sel = np.nonzero(better)[0]
+            phi[s + sel] = v[sel, k[sel]]
+            idx[s + sel] = j + k[sel] // 27
+            disp[s + sel] = d[sel, k[sel]]
     return phi, idx, disp

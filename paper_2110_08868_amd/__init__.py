@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmak.so")
 EXPORTED_SYMBOLS = [
     "mak_default_options", "mak_create", "mak_destroy", "mak_last_error",
     "mak_laguerre_cells", "mak_hessian_copy", "mak_faces_copy", "mak_solve",
-    "mak_solve_masses", "mak_solve_from", "mak_solve_memory_estimate", "mak_profile_enable", "mak_profile_read",
+    "mak_solve_masses", "mak_solve_from", "mak_solve_memory_estimate", "mak_legendre",
+    "mak_legendre_mesh", "mak_profile_enable", "mak_profile_read",
     "mak_profile_counters", "mak_server_create", "mak_server_submit", "mak_server_poll",
     "mak_server_wait", "mak_server_release", "mak_server_stats", "mak_server_last_error",
     "mak_server_destroy",
@@ -125,6 +126,10 @@ def load_library():
     lib.mak_faces_copy.restype = ctypes.c_int
     lib.mak_solve.argtypes = [P, P, I64, D, D, P, P, P, P, P]
     lib.mak_solve.restype = ctypes.c_int
+    lib.mak_legendre.argtypes = [P, P, P, I64, D, P, I64, P, P, P, P]
+    lib.mak_legendre.restype = ctypes.c_int
+    lib.mak_legendre_mesh.argtypes = [P, P, P, I64, D, I64, D, P, P, P, P]
+    lib.mak_legendre_mesh.restype = ctypes.c_int
     lib.mak_solve_masses.argtypes = [P, P, P, I64, D, D, P, P, P, P, P]
     lib.mak_solve_masses.restype = ctypes.c_int
     lib.mak_solve_from.argtypes = [P, P, I64, D, D, P, P, P, P, P]
@@ -330,6 +335,36 @@ class Context:
     def solve_from(self, points, psi0, L: float, tol: float = 1e-6):
         """Resume a solve from saved weights psi0."""
         return self._solve(self.lib.mak_solve_from, points, L, tol, psi0)
+
+    def _legendre_out(self, q):
+        torch = _torch()
+        return (torch.empty(q, dtype=torch.float64, device=self.device),
+                torch.empty(q, dtype=torch.int32, device=self.device),
+                torch.empty((q, 3), dtype=torch.float64, device=self.device))
+
+    def legendre(self, points, psi, L: float, queries):
+        """Legendre transform of the weights at query points (Q, 3):
+        (phi (Q,), idx (Q,) int32, disp (Q, 3)), disp = x_idx + kL - q."""
+        x = self._dev(points, (3,))
+        w = None if psi is None else self._dev(psi)
+        q = self._dev(queries, (3,))
+        phi, idx, disp = self._legendre_out(q.shape[0])
+        st = self.lib.mak_legendre(self._h, x.data_ptr(), None if w is None else w.data_ptr(),
+                                   x.shape[0], float(L), q.data_ptr(), q.shape[0],
+                                   phi.data_ptr(), idx.data_ptr(), disp.data_ptr(), self._stream())
+        self._check(st)
+        return phi, idx, disp
+
+    def legendre_mesh(self, points, psi, L: float, ng: int, offset: float = 0.0):
+        """The same on the ng^3 mesh ((a, b, c) + offset) L / ng, c fastest."""
+        x = self._dev(points, (3,))
+        w = None if psi is None else self._dev(psi)
+        phi, idx, disp = self._legendre_out(int(ng) ** 3)
+        st = self.lib.mak_legendre_mesh(self._h, x.data_ptr(), None if w is None else w.data_ptr(),
+                                        x.shape[0], float(L), int(ng), float(offset), phi.data_ptr(),
+                                        idx.data_ptr(), disp.data_ptr(), self._stream())
+        self._check(st)
+        return phi, idx, disp
 
 
 class Request:

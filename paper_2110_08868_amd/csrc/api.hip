@@ -119,6 +119,9 @@ struct mak_ctx {
   Lap sJ;
   PcgWork pw;
   DevBuf psi_s, psi_t, g, pstep, mass_s, tmp;
+  // Legendre transform / point location
+  PointSet lps;
+  DevBuf lstatus;
   Profiler prof;
   PassRunner* runner = nullptr;  // NULL: passes run on the solve's stream
 };
@@ -284,6 +287,37 @@ mak_status mak_faces_copy(mak_ctx* ctx, int64_t* face_ptr, int32_t* face_j, int3
     set_device(ctx);
     copy_faces(ctx->ps, ctx->cp, ctx->face_ptr, face_ptr, face_j, face_shift, face_area,
                static_cast<hipStream_t>(stream));
+  });
+}
+
+mak_status mak_legendre(mak_ctx* ctx, const double* points, const double* psi, int64_t N, double L,
+                        const double* queries, int64_t Q, double* phi, int32_t* idx, double* disp,
+                        void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    check_args(N, L);
+    if (!points || (Q > 0 && !queries)) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    if (Q < 0 || Q >= (int64_t(1) << 40)) MAK_FAIL(MAK_EINVAL, "Q must be in [0, 2^40)");
+    set_device(ctx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
+    locate(ctx->lps, queries, Q, 0, 0.0, phi, idx, disp, ctx->lstatus, st);
+  });
+}
+
+mak_status mak_legendre_mesh(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
+                             double L, int64_t ng, double offset, double* phi, int32_t* idx,
+                             double* disp, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    check_args(N, L);
+    if (!points) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    if (ng < 1 || ng > 4096) MAK_FAIL(MAK_EINVAL, "ng must be in [1, 4096]");
+    if (!std::isfinite(offset)) MAK_FAIL(MAK_EINVAL, "offset must be finite");
+    set_device(ctx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
+    locate(ctx->lps, nullptr, 0, ng, offset, phi, idx, disp, ctx->lstatus, st);
   });
 }
 

@@ -225,6 +225,15 @@ void copy_faces(const PointSet& ps, CellPass& cp, const DevBuf& face_ptr, int64_
 // Face slots per cell for a point set of N sites.
 int32_t face_slots(int64_t N);
 
+// --- locate.hip
+// Legendre transform of the weights stored in ps at query points (queries:
+// device (Q, 3), any coordinates) or, when queries is NULL, at the ng^3 mesh
+// nodes ((a, b, c) + offset) L / ng (row-major, c fastest): phi, the original
+// index of the Laguerre cell holding the point, and x_i + kL - q.  Outputs
+// may be NULL.  Throws MAK_EINVAL for a non-finite query coordinate.
+void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, double offset,
+            double* phi, int32_t* idx, double* disp, DevBuf& status, hipStream_t st);
+
 // --- pcg.hip / reductions
 double dev_reduce_max(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 double dev_reduce_min(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);

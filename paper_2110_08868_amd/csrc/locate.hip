@@ -1,0 +1,273 @@
+// Legendre transform of the weights and point location (Sec. 2, the equation
+// after Eq. laguerrecell): for a query point q of the torus,
+//
+//   phi(q) = min over sites i and periodic images k of 1/2 |q - x_i - kL|^2 - psi_i,
+//
+// attained at i(q), the Laguerre cell that contains q.  With psi at the
+// solution of the transport problem phi is the initial potential and
+// x_{i(q)} + kL the position that the mass element at q is carried to.
+//
+// One thread per query.  The weights of converged solutions follow the
+// displacement field, so their range spans many h^2 and a bound by the
+// largest weight would reach far; the walk therefore prunes with the tilted
+// bounds of the site grid (per block B a slope g_B and T_B with
+// psi_j <= T_B + g_B . (x_j - c_B) for its sites, per cell the same T over
+// the cell's sites).  Over the box of a block or cell the power distance is
+// then at least
+//   1/2 dist(q + g_B, box)^2 - 1/2 |g_B|^2 - g_B . (q - c_B) - T.
+// The thread first scans the 27 cells around q + g of its own block (the
+// predicted position of the site), then walks Chebyshev shells of blocks
+// around the block of q: a block, and then each of its cells, is skipped when
+// its bound cannot beat the best value found.  The walk stops before block
+// shell r when every shell s >= r is out of reach by its untilted bound:
+// distance >= (s - 1) bh + delta_b (delta_b = distance from q to the faces
+// of its block) and weights <= the shell maximum of the block of q (s up to
+// SHELL_MAX) or the global maximum (beyond).  Past r = Gb + 2 that distance
+// exceeds L > sqrt(3) L / 2, which the global bound alone ends, so every
+// thread's walk is finite.
+//
+// Mesh queries are generated in the kernel, 4 x 4 x 4 nodes per wavefront,
+// so a wavefront's lanes walk nearly the same blocks; the bricks are dealt to
+// the XCDs in contiguous ranges so neighbouring bricks share an L2.
+#include <cfloat>
+#include <cmath>
+
+#include "../../include/mak.h"
+#include "engine.h"
+#include "gridkey.h"
+#include "profile.h"
+
+#pragma clang fp contract(fast)
+
+namespace mak {
+namespace {
+
+constexpr int kLocBlock = 256;
+
+struct LocArgs {
+  const double4* pts;      // sorted sites: x, y, z, psi
+  const int32_t* start;    // cell ranges [G + 1]
+  const double* bsuf;      // per-block shell maxima [GB * (SHELL_MAX + 1)]
+  const double* bg;        // per-block slope of the tilted bounds [GB * 3]
+  const double* btmax;     // per-block tilted bound T [GB]
+  const double* ctmax;     // per-cell tilted bound T (block's slope) [G]
+  const double* scal;      // [0] global weight maximum
+  const int32_t* perm;     // sorted -> original index
+  const double* q;         // (Q, 3) query points, or NULL for the mesh
+  int64_t Q;               // number of queries (mesh: ng^3)
+  int64_t ng, nb;          // mesh nodes and 4-node bricks per axis
+  double mesh_h, mesh_off; // mesh spacing and node offset (in spacings)
+  double L, h;
+  int Gn, Gb;
+  int64_t per_xcd;         // workgroups per XCD
+  double* phi;             // [Q] or NULL
+  int32_t* idx;            // [Q] or NULL
+  double* disp;            // [Q, 3] or NULL
+  int32_t* status;         // set to 1 by a query with a non-finite coordinate
+};
+
+__device__ __forceinline__ double wrap_coord(double v, double L) {
+  v = fmod(v, L);
+  if (v < 0) v += L;
+  if (!(v < L) || !(v >= 0)) v = 0.0;
+  return v;
+}
+
+// floor(u / n) for a cell or block coordinate u that may lie outside [0, n)
+__device__ __forceinline__ int period_floor(int u, int n) { return u >= 0 ? u / n : -((n - 1 - u) / n); }
+
+__global__ __launch_bounds__(kLocBlock) void k_locate(LocArgs A) {
+  const int64_t wg = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+  if ((wg >> 3) >= A.per_xcd) return;
+  const int64_t item = ((wg & 7) * A.per_xcd + (wg >> 3)) * kLocBlock + threadIdx.x;
+
+  double qx, qy, qz;
+  int64_t out;
+  if (A.q) {
+    if (item >= A.Q) return;
+    out = item;
+    qx = A.q[3 * item];
+    qy = A.q[3 * item + 1];
+    qz = A.q[3 * item + 2];
+    if (!(isfinite(qx) && isfinite(qy) && isfinite(qz))) atomicOr(A.status, 1);
+  } else {
+    const int64_t brick = item >> 6;
+    const int l = int(item & 63);
+    const int64_t nb = A.nb;
+    if (brick >= nb * nb * nb) return;
+    const int64_t a = 4 * (brick / (nb * nb)) + (l >> 4);
+    const int64_t b = 4 * ((brick / nb) % nb) + ((l >> 2) & 3);
+    const int64_t c = 4 * (brick % nb) + (l & 3);
+    if (a >= A.ng || b >= A.ng || c >= A.ng) return;
+    out = (a * A.ng + b) * A.ng + c;
+    qx = (double(a) + A.mesh_off) * A.mesh_h;
+    qy = (double(b) + A.mesh_off) * A.mesh_h;
+    qz = (double(c) + A.mesh_off) * A.mesh_h;
+  }
+  const double L = A.L, h = A.h, bh = BLOCK_SIDE * h;
+  qx = wrap_coord(qx, L);
+  qy = wrap_coord(qy, L);
+  qz = wrap_coord(qz, L);
+  const int Gn = A.Gn, Gb = A.Gb;
+  // rounding slack of the bounds (values are O(L^2))
+  const double slack = 1e-12 * L * L;
+  const int cx = cell_coord(qx, h, Gn), cy = cell_coord(qy, h, Gn), cz = cell_coord(qz, h, Gn);
+  const int bx0 = cx >> 2, by0 = cy >> 2, bz0 = cz >> 2;
+  double mb = fmin(fmin(qx - bx0 * bh, (bx0 + 1) * bh - qx),
+                   fmin(fmin(qy - by0 * bh, (by0 + 1) * bh - qy), fmin(qz - bz0 * bh, (bz0 + 1) * bh - qz)));
+  mb = fmax(mb - 1e-9 * h, 0.0);
+  const int64_t b0 = block_key(bx0, by0, bz0, Gb);
+  const double* suf = A.bsuf + b0 * (SHELL_MAX + 1);
+  const double gmax = A.scal[0];
+
+  double best = INFINITY, bx = 0, by = 0, bz = 0;
+  int32_t bk = -1;
+  auto scan = [&](int64_t key, double sx, double sy, double sz) {
+    const int32_t s0 = A.start[key], s1 = A.start[key + 1];
+    for (int32_t k = s0; k < s1; ++k) {
+      const double4 p = A.pts[k];
+      const double dx = p.x + sx - qx, dy = p.y + sy - qy, dz = p.z + sz - qz;
+      const double v = 0.5 * (dx * dx + dy * dy + dz * dz) - p.w;
+      if (v < best) {
+        best = v;
+        bk = k;
+        bx = dx;
+        by = dy;
+        bz = dz;
+      }
+    }
+  };
+
+  // seed: the 27 cells around the predicted site position q + g (unwrapped
+  // cell coordinates)
+  int ex, ey, ez;
+  {
+    const double* g0 = A.bg + 3 * b0;
+    ex = int(floor((qx + g0[0]) / h));
+    ey = int(floor((qy + g0[1]) / h));
+    ez = int(floor((qz + g0[2]) / h));
+    for (int o = 0; o < 27; ++o) {
+      const int ux = ex + o / 9 - 1, uy = ey + (o / 3) % 3 - 1, uz = ez + o % 3 - 1;
+      const int sx = period_floor(ux, Gn), sy = period_floor(uy, Gn), sz = period_floor(uz, Gn);
+      scan(cell_key(ux - sx * Gn, uy - sy * Gn, uz - sz * Gn, Gb), sx * L, sy * L, sz * L);
+    }
+  }
+
+  // walk over block shells around the block of q
+  for (int r = 0; r <= Gb + 2; ++r) {
+    if (r > 0) {
+      bool stop = true;
+      for (int s = r; s <= SHELL_MAX && stop; ++s) {
+        const double t = (s - 1) * bh + mb;
+        stop = 0.5 * t * t - suf[s] - slack >= best;
+      }
+      if (stop) {
+        const double t = (max(r, SHELL_MAX + 1) - 1) * bh + mb;
+        stop = 0.5 * t * t - gmax - slack >= best;
+      }
+      if (stop) break;
+    }
+    for (int ox = -r; ox <= r; ++ox) {
+      const bool xe = ox == -r || ox == r;
+      for (int oy = -r; oy <= r; ++oy) {
+        const bool ye = xe || oy == -r || oy == r;
+        const int step = ye ? 1 : 2 * r;
+        for (int oz = -r; oz <= r; oz += step) {
+          const int ubx = bx0 + ox, uby = by0 + oy, ubz = bz0 + oz;
+          const int sx = period_floor(ubx, Gb), sy = period_floor(uby, Gb), sz = period_floor(ubz, Gb);
+          const int64_t bkey = block_key(ubx - sx * Gb, uby - sy * Gb, ubz - sz * Gb, Gb);
+          const double gx = A.bg[3 * bkey], gy = A.bg[3 * bkey + 1], gz = A.bg[3 * bkey + 2];
+          // q + g and the offset term, relative to the unwrapped block
+          const double px = qx + gx, py = qy + gy, pz = qz + gz;
+          const double lx = ubx * bh, ly = uby * bh, lz = ubz * bh;
+          const double base = 0.5 * (gx * gx + gy * gy + gz * gz) +
+                              (gx * (qx - lx - 0.5 * bh) + gy * (qy - ly - 0.5 * bh) +
+                               gz * (qz - lz - 0.5 * bh)) + slack;
+          const double dbx = fmax(fmax(lx - px, px - lx - bh), 0.0);
+          const double dby = fmax(fmax(ly - py, py - ly - bh), 0.0);
+          const double dbz = fmax(fmax(lz - pz, pz - lz - bh), 0.0);
+          if (0.5 * (dbx * dbx + dby * dby + dbz * dbz) - base - A.btmax[bkey] >= best) continue;
+          const double Lx = sx * L, Ly = sy * L, Lz = sz * L;
+          for (int l = 0; l < 64; ++l) {
+            const int ux = 4 * ubx + (l >> 4), uy = 4 * uby + ((l >> 2) & 3), uz = 4 * ubz + (l & 3);
+            if (abs(ux - ex) <= 1 && abs(uy - ey) <= 1 && abs(uz - ez) <= 1) continue;  // seeded
+            const int64_t key = bkey * 64 + l;
+            const double cx0 = ux * h, cy0 = uy * h, cz0 = uz * h;
+            const double dcx = fmax(fmax(cx0 - px, px - cx0 - h), 0.0);
+            const double dcy = fmax(fmax(cy0 - py, py - cy0 - h), 0.0);
+            const double dcz = fmax(fmax(cz0 - pz, pz - cz0 - h), 0.0);
+            if (0.5 * (dcx * dcx + dcy * dcy + dcz * dcz) - base - A.ctmax[key] >= best) continue;
+            scan(key, Lx, Ly, Lz);
+          }
+        }
+      }
+    }
+  }
+  if (A.phi) A.phi[out] = best;
+  if (A.idx) A.idx[out] = bk >= 0 ? A.perm[bk] : -1;
+  if (A.disp) {
+    A.disp[3 * out] = bx;
+    A.disp[3 * out + 1] = by;
+    A.disp[3 * out + 2] = bz;
+  }
+}
+
+}  // namespace
+
+void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, double offset,
+            double* phi, int32_t* idx, double* disp, DevBuf& status, hipStream_t st) {
+  LocArgs a{};
+  status.ensure(sizeof(int32_t));
+  a.status = status.as<int32_t>();
+  a.pts = ps.pts.as<double4>();
+  a.start = ps.cell_start.as<int32_t>();
+  a.bsuf = ps.block_suffix.as<double>();
+  a.bg = ps.block_g.as<double>();
+  a.btmax = ps.block_tmax.as<double>();
+  a.ctmax = ps.cell_tmax.as<double>();
+  a.scal = ps.scal.as<double>();
+  a.perm = ps.perm.as<int32_t>();
+  a.q = queries;
+  a.L = ps.g.L;
+  a.h = ps.g.h;
+  a.Gn = ps.g.Gn;
+  a.Gb = ps.g.Gb;
+  a.phi = phi;
+  a.idx = idx;
+  a.disp = disp;
+  int64_t threads;
+  if (queries) {
+    a.Q = Q;
+    threads = Q;
+  } else {
+    a.ng = ng;
+    a.nb = ceil_div(ng, 4);
+    a.Q = ng * ng * ng;
+    a.mesh_h = ps.g.L / double(ng);
+    a.mesh_off = offset;
+    threads = a.nb * a.nb * a.nb * 64;
+  }
+  if (a.Q == 0) return;
+  if (queries) MAK_HIP(hipMemsetAsync(a.status, 0, sizeof(int32_t), st));
+  const int64_t wgs = ceil_div(threads, kLocBlock);
+  a.per_xcd = ceil_div(wgs, 8);
+  const int64_t total = 8 * a.per_xcd;
+  const int64_t gx = total < 65536 ? total : 65536;
+  const int64_t gy = ceil_div(total, gx);
+  if (gy > 65535) MAK_FAIL(MAK_EINVAL, "too many query points for one launch");
+  ProfScope scope("locate", st, double(a.Q), double(a.Q) * (phi ? 8 : 0) + double(a.Q) * (idx ? 4 : 0) +
+                                                 double(a.Q) * (disp ? 24 : 0) +
+                                                 double(a.Q) * (queries ? 24 : 0) +
+                                                 double(ps.N) * sizeof(double4));
+  hipLaunchKernelGGL(k_locate, dim3(unsigned(gx), unsigned(gy)), dim3(kLocBlock), 0, st, a);
+  MAK_HIP(hipGetLastError());
+  scope.stop();
+  if (queries) {
+    int32_t hs = 0;
+    MAK_HIP(hipMemcpyAsync(&hs, a.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    MAK_HIP(hipStreamSynchronize(st));
+    if (hs) MAK_FAIL(MAK_EINVAL, "non-finite query coordinate");
+  }
+}
+
+}  // namespace mak
