@@ -18,10 +18,13 @@ Contents
   legendre(x, psi, L, q) Legendre transform of the weights at query points:
                          phi(q), the index of the Laguerre cell holding q,
                          and the transport displacement (brute force).
+  power_spectrum(f, L)   shell-averaged power spectrum of a periodic mesh
+                         field (FFT estimator, optional window and contrast).
   exact                  exact-rational mini oracle (Python fractions).
 """
 from .cells import cells, cell_faces_dict, load_library
 from .legendre import legendre
+from .power import power_spectrum
 from .newton import (
     hessian_dense,
     hessian_coo,
@@ -37,6 +40,7 @@ __all__ = [
     "cell_faces_dict",
     "load_library",
     "legendre",
+    "power_spectrum",
     "hessian_dense",
     "hessian_coo",
     "kantorovich",

@@ -457,3 +457,93 @@ def test_p9_legendre_potential_convex():
         slope = (q + disp) @ e
         assert np.diff(slope).min() >= -1e-12
         assert np.diff(slope).max() > 0
+
+
+# ------------------------------------------------ P10 power spectrum estimator
+def _shell_modes(ng, j):
+    """Modes n in (-ng/2, ng/2]^3 with j - 1/2 <= |n| < j + 1/2, by enumeration."""
+    lo = -((ng - 1) // 2)
+    hi = ng // 2
+    c = 0
+    for a in range(lo, hi + 1):
+        for b in range(lo, hi + 1):
+            for d in range(lo, hi + 1):
+                r2 = a * a + b * b + d * d
+                if (j - 0.5) ** 2 <= r2 < (j + 0.5) ** 2:
+                    c += 1
+    return c
+
+
+@pytest.mark.parametrize("ng,n0,window", [(16, (1, 2, 0), 0), (12, (3, -1, 2), 2), (9, (2, 2, 1), 1),
+                                          (16, (0, 0, 8), 0), (10, (1, 0, 0), 3)])
+def test_p10_plane_wave(ng, n0, window):
+    """f = A cos(2 pi n0 . x / L + phase): all power in the modes +-n0 (one
+    mode when n0 is the Nyquist frequency), A^2 L^3 / 4 each (A^2 L^3 there),
+    divided by the window W(n0)^2; the shells hold the enumerated mode counts."""
+    L, A, ph = 2.0, 0.7, 0.3
+    t = np.arange(ng) * (L / ng)
+    X, Y, Z = np.meshgrid(t, t, t, indexing="ij")
+    n0 = np.array(n0)
+    nyq = ng % 2 == 0 and np.all(np.isin(np.abs(n0), [0, ng // 2]))
+    f = A * np.cos(2 * np.pi * (n0[0] * X + n0[1] * Y + n0[2] * Z) / L + (0.0 if nyq else ph))
+    k, P, m = oracle.power_spectrum(f, L, nbins=ng, window=window)
+    j0 = int(np.floor(np.linalg.norm(n0) + 0.5))
+    for j in (1, 2, j0):
+        assert m[j - 1] == _shell_modes(ng, j)
+    W = 1.0
+    for a in n0:
+        x = np.pi * a / ng
+        W *= (np.sin(x) / x if a else 1.0) ** window
+    tot = (A * A * L ** 3 if nyq else 2 * A * A * L ** 3 / 4) / W ** 2
+    assert P[j0 - 1] * m[j0 - 1] == pytest.approx(tot, rel=1e-12)
+    others = np.delete(P * m, j0 - 1)
+    assert np.all(np.abs(others[np.isfinite(others)]) <= 1e-20 * tot * ng ** 3)
+
+
+def test_p10_parseval_and_contrast():
+    """Sum over all shells of modes x P = H^3 sum f^2 - (H^3 sum f)^2 / L^3;
+    contrast divides the k != 0 power by mean(f)^2."""
+    rng = np.random.default_rng(51)
+    ng, L = 12, 3.0
+    f = 2.0 + rng.normal(size=(ng, ng, ng))
+    H = L / ng
+    k, P, m = oracle.power_spectrum(f, L, nbins=int(np.ceil(np.sqrt(3) * ng / 2)) + 1)
+    ok = m > 0
+    lhs = np.sum(P[ok] * m[ok])
+    rhs = H ** 3 * np.sum(f * f) - (H ** 3 * f.sum()) ** 2 / L ** 3
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    kc, Pc, mc = oracle.power_spectrum(f, L, contrast=True)
+    kk, Pk, mk = oracle.power_spectrum(f, L)
+    assert np.allclose(Pc, Pk / f.mean() ** 2, rtol=1e-12)
+    # white noise: E P = sigma^2 H^3 (sigma = 1 here)
+    assert np.mean(Pk[1:]) == pytest.approx(H ** 3, rel=0.1)
+
+
+def test_p10_brute_force_dft():
+    """ng = 4: explicit triple-sum DFT per mode, binned by enumeration."""
+    rng = np.random.default_rng(53)
+    ng, L = 4, 1.5
+    f = rng.normal(size=(ng, ng, ng))
+    H = L / ng
+    acc = {}
+    for a in range(-1, 3):
+        for b in range(-1, 3):
+            for c in range(-1, 3):
+                s = 0j
+                for x in range(ng):
+                    for y in range(ng):
+                        for z in range(ng):
+                            s += f[x, y, z] * np.exp(-2j * np.pi * (a * x + b * y + c * z) / ng)
+                p = abs(s * H ** 3) ** 2 / L ** 3
+                r = np.sqrt(a * a + b * b + c * c)
+                j = int(np.floor(r + 0.5))
+                if j >= 1:
+                    e = acc.setdefault(j, [0, 0.0, 0.0])
+                    e[0] += 1
+                    e[1] += p
+                    e[2] += 2 * np.pi / L * r
+    k, P, m = oracle.power_spectrum(f, L, nbins=3)
+    for j in (1, 2, 3):
+        assert m[j - 1] == acc[j][0]
+        assert P[j - 1] == pytest.approx(acc[j][1] / acc[j][0], rel=1e-12)
+        assert k[j - 1] == pytest.approx(acc[j][2] / acc[j][0], rel=1e-13)
