@@ -18,6 +18,8 @@ Contents
   legendre(x, psi, L, q) Legendre transform of the weights at query points:
                          phi(q), the index of the Laguerre cell holding q,
                          and the transport displacement (brute force).
+  za_deposit(...)        Zel'dovich advection of the cells' mass elements
+                         and their deposit on an Eulerian mesh.
   power_spectrum(f, L)   shell-averaged power spectrum of a periodic mesh
                          field (FFT estimator, optional window and contrast).
   exact                  exact-rational mini oracle (Python fractions).
@@ -25,6 +27,7 @@ Contents
 from .cells import cells, cell_faces_dict, load_library
 from .legendre import legendre
 from .power import power_spectrum
+from .deposit import za_deposit
 from .newton import (
     hessian_dense,
     hessian_coo,
@@ -41,6 +44,7 @@ __all__ = [
     "load_library",
     "legendre",
     "power_spectrum",
+    "za_deposit",
     "hessian_dense",
     "hessian_coo",
     "kantorovich",

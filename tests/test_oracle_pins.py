@@ -547,3 +547,86 @@ def test_p10_brute_force_dft():
         assert m[j - 1] == acc[j][0]
         assert P[j - 1] == pytest.approx(acc[j][1] / acc[j][0], rel=1e-12)
         assert k[j - 1] == pytest.approx(acc[j][2] / acc[j][0], rel=1e-13)
+
+
+# ------------------------------------------------ P11 Zel'dovich deposit
+def test_p11_deposit_tau0_uniform_and_mass():
+    """tau = 0 leaves the elements in place: a Lagrangian mesh on the
+    Eulerian nodes (NGP), or centred between them (CIC), gives density 1;
+    at any tau the deposited mass is L^3."""
+    x, psi = _random_case(n=3, seed=63, wscale=0.03)
+    L = 1.0
+    r = oracle.za_deposit(x, psi, L, 0.0, 6, 6, scheme="ngp", lag_offset=0.0)
+    assert np.allclose(r, 1.0, rtol=1e-14)
+    r = oracle.za_deposit(x, psi, L, 0.0, 6, 6, scheme="cic", lag_offset=0.5)
+    assert np.allclose(r, 1.0, rtol=1e-14)
+    for tau, sch in ((0.3, "cic"), (0.8, "ngp"), (1.0, "cic")):
+        r = oracle.za_deposit(x, psi, L, tau, 10, 7, scheme=sch)
+        assert r.sum() * (L / 7) ** 3 == pytest.approx(L ** 3, rel=1e-13)
+
+
+def _layer_setup():
+    rng = np.random.default_rng(61)
+    L, nl, ny = 1.0, 3, 2
+    X = np.sort(rng.uniform(0, L, nl))
+    w = rng.uniform(0.6, 1.4, nl)
+    w *= L / w.sum()
+    psi_l, b = layered_ot_psi(X, L, widths=w)
+    return L, nl, ny, X, psi_l, b
+
+
+def test_p11_deposit_layered_separable():
+    """Slabs with the closed-form transport weights: cells are products of a
+    slab in x and lattice squares in y, z, and the Zel'dovich map moves each
+    coordinate towards the site's, so the NGP deposit is the product of three
+    1-D deposits computed from the slab boundaries; and it approaches the
+    exact deposit of the shrunk cells as the Lagrangian mesh refines."""
+    L, nl, ny, X, psi_l, b = _layer_setup()
+    x = workloads.layered(X, ny, ny, L)
+    psi = np.repeat(psi_l, ny * ny)
+    ng, tau = 8, 0.4
+    H = L / ng
+    lo = np.concatenate([[b[-1] - L], b[:-1]])
+    s = L / ny
+
+    def fx(n):
+        cnt = np.zeros(ng)
+        for t in range(n):
+            q = (t + 0.5) * L / n
+            hit = [(a, k) for a in range(nl) for k in (-1, 0, 1) if lo[a] < q - k * L < b[a]]
+            a, k = hit[0]
+            y = q + tau * (X[a] + k * L - q)
+            cnt[int(np.floor(np.mod(y, L) / H + 0.5)) % ng] += 1
+        return cnt
+
+    def fyz(n):
+        cnt = np.zeros(ng)
+        for t in range(n):
+            q = (t + 0.5) * L / n
+            k = int(np.floor(q / s))
+            y = q + tau * ((k + 0.5) * s - q)
+            cnt[int(np.floor(np.mod(y, L) / H + 0.5)) % ng] += 1
+        return cnt
+
+    def exact_1d(intervals):
+        out = np.zeros(ng)
+        for e in range(ng):
+            a0, a1 = e * H - H / 2, e * H + H / 2
+            for (u0, u1) in intervals:
+                for k in (-2, -1, 0, 1, 2):
+                    out[e] += max(0.0, min(a1, u1 + k * L) - max(a0, u0 + k * L))
+        return out / ((1 - tau) * H)
+
+    ex = exact_1d([(X[a] + (1 - tau) * (lo[a] - X[a]), X[a] + (1 - tau) * (b[a] - X[a]))
+                   for a in range(nl)])
+    ey = exact_1d([((k + 0.5) * s - (1 - tau) * s / 2, (k + 0.5) * s + (1 - tau) * s / 2)
+                   for k in range(ny)])
+    exact = ex[:, None, None] * ey[None, :, None] * ey[None, None, :]
+    errs = []
+    for n in (24, 48):
+        r = oracle.za_deposit(x, psi, L, tau, n, ng, scheme="ngp")
+        f1, f2 = fx(n), fyz(n)
+        ref = f1[:, None, None] * f2[None, :, None] * f2[None, None, :] * (L / n) ** 3 / H ** 3
+        assert np.allclose(r, ref, rtol=1e-13, atol=1e-13)
+        errs.append(np.abs(r - exact).max())
+    assert errs[1] < 0.7 * errs[0] and errs[1] < 0.5
