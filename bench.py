@@ -12,8 +12,9 @@ Also reported: the other precision path on the same input, the roofline of
 the dominant kernel (HIP-event durations of its launches in the timed region,
 counted work from a separate counting solve), the Legendre transform of the
 solved weights on a mesh of N nodes (the initial potential and the location
-of every node), serving, and the CPU oracle timed on a bounded sample of the
-same workload.
+of every node), the Zel'dovich deposit of the solved cells and the power
+spectrum of that density, serving, and the CPU oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -42,6 +43,8 @@ KERNEL_SOURCES = {
     "clip": ["clip.hip", "engine.h", "common.h", "gridkey.h", "profile.h"],
     "spmv": ["pcg.hip", "engine.h", "common.h", "profile.h"],
     "locate": ["locate.hip", "engine.h", "common.h", "gridkey.h", "profile.h"],
+    "deposit": ["locate.hip", "engine.h", "common.h", "gridkey.h", "profile.h"],
+    "shell_bin": ["power.hip", "engine.h", "common.h", "profile.h"],
 }
 
 
@@ -208,6 +211,54 @@ def legendre_leg(mak, x_dev, psi, L, ng, reps, workload):
                          "bytes_per_launch": bytes_pl}}
 
 
+def hbm_roofline(kernel, v, workload):
+    """Roofline object of an HBM-bound kernel from its profile entry."""
+    avg_ms = v["total_ms"] / v["launches"]
+    bytes_pl = v["bytes"] / v["launches"]
+    achieved = bytes_pl / (avg_ms * 1e-3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(kernel, workload),
+            "avg_launch_ms": avg_ms, "launches": v["launches"], "bytes_per_launch": bytes_pl}
+
+
+def deposit_and_power(mak, x_dev, psi, L, ng, tau, reps, workload):
+    """Zel'dovich deposit of the solved cells at growth amplitude tau (ng^3
+    mass elements, cloud in cell onto an ng^3 mesh), then the power spectrum
+    of its contrast (CIC window removed).  HIP-event times of the deposit
+    kernel, the FFT and the shell binning over `reps` calls each."""
+    import torch
+    ctx = mak.Context(0)
+    rho = ctx.za_deposit(x_dev, psi, L, tau, ng, ng, "cic")
+    ctx.power_spectrum(rho, L, window=2, contrast=True)
+    ctx.profile_enable(timing=True, counting=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rho = ctx.za_deposit(x_dev, psi, L, tau, ng, ng, "cic")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        k, P, m = ctx.power_spectrum(rho, L, window=2, contrast=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.close()
+    dep = prof["deposit"]
+    rho_c = rho.cpu()
+    return {
+        "deposit": {"tau": tau, "elements": ng ** 3, "mesh": ng, "scheme": "cic",
+                    "ms_per_call": (t1 - t0) / reps * 1e3,
+                    "elements_per_s_kernel": ng ** 3 / (dep["total_ms"] / dep["launches"] * 1e-3),
+                    "density_min": float(rho_c.min()), "density_max": float(rho_c.max()),
+                    "roofline": hbm_roofline("deposit", dep, workload)},
+        "power_spectrum": {"mesh": ng, "shells": int(P.numel()), "window": "cic", "contrast": True,
+                           "ms_per_call": (t2 - t1) / reps * 1e3,
+                           "fft_ms": prof["fft"]["total_ms"] / prof["fft"]["launches"],
+                           "P_first_shells": [float(v) for v in P[:4].cpu()],
+                           "roofline": hbm_roofline("shell_bin", prof["shell_bin"], workload)},
+    }
+
+
 def compare_paths(a, b, L, N):
     """rms / max differences between the two precision paths' solutions, in
     grid units (spacing L / N^(1/3))."""
@@ -353,7 +404,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=32,
                     help="requests of the serving leg (the full serving workload is 256; 0 = skip)")
     ap.add_argument("--legendre-reps", type=int, default=5,
-                    help="calls of the Legendre transform on the mesh at the solved weights (0 = skip)")
+                    help="calls of the Legendre transform, the Zel'dovich deposit and the power "
+                         "spectrum on the mesh at the solved weights (0 = skip)")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-oracle-check", action="store_true",
@@ -433,6 +485,10 @@ def main():
         ng = round(N ** (1.0 / 3.0))
         log(f"[bench] Legendre transform on the {ng}^3 mesh ...")
         res["legendre"] = legendre_leg(mak, x_dev, out[0], L, ng, args.legendre_reps, args.workload)
+    if args.legendre_reps > 0:
+        ng = round(N ** (1.0 / 3.0))
+        log(f"[bench] Zel'dovich deposit and power spectrum on the {ng}^3 mesh ...")
+        res.update(deposit_and_power(mak, x_dev, out[0], L, ng, 0.5, args.legendre_reps, args.workload))
     if args.serving_requests > 0:
         res["serving"] = serving(mak, args.serving_requests, args.serving_slots,
                                  args.serving_budget_gb, precision, tol, args.cg_rtol)

@@ -209,6 +209,55 @@ mak_status mak_legendre_mesh(mak_ctx* ctx, const double* points, const double* p
                              double L, int64_t ng, double offset, double* phi, int32_t* idx,
                              double* disp, void* stream);
 
+/* ---- Zel'dovich advection of the cells and Eulerian deposition ----
+ * Sec. 2 (last paragraph) and Fig. 1: each Laguerre cell V_i (at the
+ * weights psi) is the Lagrangian region whose mass ends at x_i; at growth
+ * amplitude tau (0 initial, 1 final) the Zel'dovich approximation moves the
+ * mass element at q to q + tau (x_i(q) - q), and the moved mass is expressed
+ * as a density on an Eulerian mesh.  The cells' mass is carried by the
+ * n_lag^3 elements at the Lagrangian mesh nodes ((a, b, c) + lag_offset)
+ * L / n_lag, each of mass (L / n_lag)^3 (initial density 1), each located in
+ * its cell as by mak_legendre_mesh and moved with its cell's image of x_i; as
+ * n_lag grows the deposit converges to that of the moved cells.
+ *   points, psi  as for mak_legendre (psi NULL: all zero)
+ *   tau          in [0, 1]
+ *   n_lag        1..2048;  ng 1..2048 (Eulerian nodes (a, b, c) L / ng)
+ *   scheme       1: nearest grid point, 2: cloud in cell (trilinear)
+ *   density      DEVICE (ng, ng, ng) float64 out, row-major: deposited mass
+ *                / (L / ng)^3 (mean 1)
+ * Masses are summed in 64-bit fixed point (2^(62 - ceil(log2 n_lag^3)) units
+ * per element, at most 2^52; the cloud-in-cell weights are rounded to
+ * units with the remainder on the heaviest node), so every element adds
+ * exactly its mass and the result is the same bits on every run.  Uses
+ * ng^3 x 8 bytes of scratch in the context. */
+mak_status mak_za_deposit(mak_ctx* ctx, const double* points, const double* psi, int64_t N, double L,
+                          double tau, int64_t n_lag, double lag_offset, int64_t ng, int32_t scheme,
+                          double* density, void* stream);
+
+/* ---- power spectrum of a mesh field ----
+ * The estimator behind the fractional spectra of Sec. BAO reconstruction,
+ * for a field f on the periodic ng^3 mesh of side L (spacing H = L / ng):
+ *   delta(k) = H^3 sum_x f(x) exp(-i k . x), k = 2 pi n / L, n in (-ng/2, ng/2]^3,
+ *   P(k) = |delta(k)|^2 / L^3,
+ * averaged over shell j = 1..nbins (the modes with j - 1/2 <= |n| < j + 1/2;
+ * k = 0 is left out).
+ *   field    DEVICE (ng, ng, ng) float64, row-major (last index fastest), read only
+ *   ng       2..2048;  nbins 1..2048 (ng / 2 reaches the Nyquist shell)
+ *   window   0: none; 1, 2, 3: divide P by W^2, W = prod_a sinc(pi n_a / ng)^p,
+ *            the window of nearest-grid-point, cloud-in-cell and
+ *            triangular-shaped-cloud assignment (sinc x = sin x / x)
+ *   contrast nonzero: the field is a density; use f / mean(f) - 1
+ *            (MAK_EINVAL if the mean is zero or not finite)
+ *   k_mean, power  DEVICE (nbins,) float64 out: mean |k| and mean P per shell
+ *                  (NaN for a shell without modes)
+ *   modes          DEVICE (nbins,) int64 out: modes per shell (each n and -n counted)
+ * The FFT is hipFFT's real-to-complex transform; its plan (for the last ng)
+ * and buffers (ng^3 (8 + 8) bytes) stay in the context.  Deterministic:
+ * the same bits on every run. */
+mak_status mak_power_spectrum(mak_ctx* ctx, const double* field, int64_t ng, double L, int32_t nbins,
+                              int32_t window, int32_t contrast, double* k_mean, double* power,
+                              int64_t* modes, void* stream);
+
 /* ---- kernel profile (diagnostics; used by the benchmark) ----
  * When timing is enabled, the library brackets its main kernels with HIP
  * events on the stream each is launched on and accumulates their durations;
@@ -217,7 +266,7 @@ mak_status mak_legendre_mesh(mak_ctx* ctx, const double* points, const double* p
  * separate runs). */
 typedef struct {
   char name[32];       /* "clip", "clip_large", "spmv", "pcg_update", "pcg_solve",
-                          "csr_assembly", "grid_build", "locate" */
+                          "csr_assembly", "grid_build", "locate", "deposit", "fft", "shell_bin" */
   int64_t launches;
   double total_ms;     /* summed event durations */
   double units;        /* work items processed (cells, rows) */

@@ -22,7 +22,7 @@ EXPORTED_SYMBOLS = [
     "mak_default_options", "mak_create", "mak_destroy", "mak_last_error",
     "mak_laguerre_cells", "mak_hessian_copy", "mak_faces_copy", "mak_solve",
     "mak_solve_masses", "mak_solve_from", "mak_solve_memory_estimate", "mak_legendre",
-    "mak_legendre_mesh", "mak_profile_enable", "mak_profile_read",
+    "mak_legendre_mesh", "mak_power_spectrum", "mak_za_deposit", "mak_profile_enable", "mak_profile_read",
     "mak_profile_counters", "mak_server_create", "mak_server_submit", "mak_server_poll",
     "mak_server_wait", "mak_server_release", "mak_server_stats", "mak_server_last_error",
     "mak_server_destroy",
@@ -126,6 +126,11 @@ def load_library():
     lib.mak_faces_copy.restype = ctypes.c_int
     lib.mak_solve.argtypes = [P, P, I64, D, D, P, P, P, P, P]
     lib.mak_solve.restype = ctypes.c_int
+    lib.mak_za_deposit.argtypes = [P, P, P, I64, D, D, I64, D, I64, ctypes.c_int32, P, P]
+    lib.mak_za_deposit.restype = ctypes.c_int
+    lib.mak_power_spectrum.argtypes = [P, P, I64, D, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       P, P, P, P]
+    lib.mak_power_spectrum.restype = ctypes.c_int
     lib.mak_legendre.argtypes = [P, P, P, I64, D, P, I64, P, P, P, P]
     lib.mak_legendre.restype = ctypes.c_int
     lib.mak_legendre_mesh.argtypes = [P, P, P, I64, D, I64, D, P, P, P, P]
@@ -335,6 +340,39 @@ class Context:
     def solve_from(self, points, psi0, L: float, tol: float = 1e-6):
         """Resume a solve from saved weights psi0."""
         return self._solve(self.lib.mak_solve_from, points, L, tol, psi0)
+
+    def za_deposit(self, points, psi, L: float, tau: float, n_lag: int, ng: int, scheme: str = "cic",
+                   lag_offset: float = 0.5):
+        """Density (ng, ng, ng) of the mass of the cells moved to growth
+        amplitude tau (Zel'dovich), carried by n_lag^3 Lagrangian elements."""
+        torch = _torch()
+        x = self._dev(points, (3,))
+        w = None if psi is None else self._dev(psi)
+        sch = {"ngp": 1, "cic": 2}[scheme]
+        rho = torch.empty((int(ng),) * 3, dtype=torch.float64, device=self.device)
+        st = self.lib.mak_za_deposit(self._h, x.data_ptr(), None if w is None else w.data_ptr(),
+                                     x.shape[0], float(L), float(tau), int(n_lag), float(lag_offset),
+                                     int(ng), sch, rho.data_ptr(), self._stream())
+        self._check(st)
+        return rho
+
+    def power_spectrum(self, field, L: float, nbins=None, window: int = 0, contrast: bool = False):
+        """Shell-averaged power spectrum of an (ng, ng, ng) mesh field:
+        (k_mean, power, modes) per shell j = 1..nbins (default ng // 2)."""
+        torch = _torch()
+        f = self._dev(field)
+        ng = f.shape[0]
+        if f.shape != (ng, ng, ng):
+            raise ValueError("field must have shape (ng, ng, ng)")
+        nb = ng // 2 if nbins is None else int(nbins)
+        k = torch.empty(nb, dtype=torch.float64, device=self.device)
+        P = torch.empty(nb, dtype=torch.float64, device=self.device)
+        m = torch.empty(nb, dtype=torch.int64, device=self.device)
+        st = self.lib.mak_power_spectrum(self._h, f.data_ptr(), ng, float(L), nb, int(window),
+                                         1 if contrast else 0, k.data_ptr(), P.data_ptr(), m.data_ptr(),
+                                         self._stream())
+        self._check(st)
+        return k, P, m
 
     def _legendre_out(self, q):
         torch = _torch()

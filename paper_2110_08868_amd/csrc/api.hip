@@ -121,7 +121,9 @@ struct mak_ctx {
   DevBuf psi_s, psi_t, g, pstep, mass_s, tmp;
   // Legendre transform / point location
   PointSet lps;
-  DevBuf lstatus;
+  DevBuf lstatus, dep_acc;
+  // power spectrum
+  PowerWork pk;
   Profiler prof;
   PassRunner* runner = nullptr;  // NULL: passes run on the solve's stream
 };
@@ -318,6 +320,41 @@ mak_status mak_legendre_mesh(mak_ctx* ctx, const double* points, const double* p
     hipStream_t st = static_cast<hipStream_t>(stream);
     build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
     locate(ctx->lps, nullptr, 0, ng, offset, phi, idx, disp, ctx->lstatus, st);
+  });
+}
+
+mak_status mak_za_deposit(mak_ctx* ctx, const double* points, const double* psi, int64_t N, double L,
+                          double tau, int64_t n_lag, double lag_offset, int64_t ng, int32_t scheme,
+                          double* density, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    check_args(N, L);
+    if (!points || !density) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    if (!(tau >= 0.0 && tau <= 1.0)) MAK_FAIL(MAK_EINVAL, "tau must be in [0, 1]");
+    if (n_lag < 1 || n_lag > 2048) MAK_FAIL(MAK_EINVAL, "n_lag must be in [1, 2048]");
+    if (!std::isfinite(lag_offset)) MAK_FAIL(MAK_EINVAL, "lag_offset must be finite");
+    if (ng < 1 || ng > 2048) MAK_FAIL(MAK_EINVAL, "ng must be in [1, 2048]");
+    if (scheme != 1 && scheme != 2) MAK_FAIL(MAK_EINVAL, "scheme must be 1 (NGP) or 2 (CIC)");
+    set_device(ctx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
+    za_deposit(ctx->lps, tau, n_lag, lag_offset, ng, scheme, density, ctx->dep_acc, st);
+  });
+}
+
+mak_status mak_power_spectrum(mak_ctx* ctx, const double* field, int64_t ng, double L, int32_t nbins,
+                              int32_t window, int32_t contrast, double* k_mean, double* power,
+                              int64_t* modes, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    if (!field || !k_mean || !power || !modes) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    if (ng < 2 || ng > 2048) MAK_FAIL(MAK_EINVAL, "ng must be in [2, 2048]");
+    if (!std::isfinite(L) || !(L > 0)) MAK_FAIL(MAK_EINVAL, "L must be finite and > 0");
+    if (nbins < 1 || nbins > 2048) MAK_FAIL(MAK_EINVAL, "nbins must be in [1, 2048]");
+    if (window < 0 || window > 3) MAK_FAIL(MAK_EINVAL, "window must be 0, 1, 2 or 3");
+    set_device(ctx);
+    power_spectrum(ctx->pk, field, ng, L, nbins, window, contrast != 0, k_mean, power, modes,
+                   static_cast<hipStream_t>(stream));
   });
 }
 

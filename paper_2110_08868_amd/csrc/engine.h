@@ -234,6 +234,31 @@ int32_t face_slots(int64_t N);
 void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, double offset,
             double* phi, int32_t* idx, double* disp, DevBuf& status, hipStream_t st);
 
+// Zel'dovich advection and Eulerian deposition: the n_lag^3 mass elements
+// at the Lagrangian mesh nodes ((a, b, c) + lag_offset) L / n_lag move to
+// q + tau (x_i(q) + kL - q) and are deposited on the ne^3 Eulerian mesh
+// (nodes (a, b, c) L / ne; scheme 1 nearest grid point, 2 cloud in cell):
+// density (ne^3, mean 1) = deposited mass / cell volume.  acc: scratch of
+// ne^3 uint64.
+void za_deposit(const PointSet& ps, double tau, int64_t n_lag, double lag_offset, int64_t ne, int scheme,
+                double* density, DevBuf& acc, hipStream_t st);
+
+// --- power.hip
+// Shell-averaged power spectrum of a field on the periodic ng^3 mesh; the
+// FFT plan (for the last ng) and the buffers are kept between calls.
+struct PowerWork {
+  int64_t ng = 0;
+  uintptr_t plan = 0;  // hipfftHandle
+  DevBuf real, spec, part, sums, tmp;
+  PowerWork() = default;
+  PowerWork(const PowerWork&) = delete;
+  PowerWork& operator=(const PowerWork&) = delete;
+  ~PowerWork() { release_plan(); }
+  void release_plan();
+};
+void power_spectrum(PowerWork& w, const double* field, int64_t ng, double L, int nbins, int window,
+                    bool contrast, double* k_mean, double* power, int64_t* modes, hipStream_t st);
+
 // --- pcg.hip / reductions
 double dev_reduce_max(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 double dev_reduce_min(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);

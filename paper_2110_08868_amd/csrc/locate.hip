@@ -76,34 +76,15 @@ __device__ __forceinline__ double wrap_coord(double v, double L) {
 // floor(u / n) for a cell or block coordinate u that may lie outside [0, n)
 __device__ __forceinline__ int period_floor(int u, int n) { return u >= 0 ? u / n : -((n - 1 - u) / n); }
 
-__global__ __launch_bounds__(kLocBlock) void k_locate(LocArgs A) {
-  const int64_t wg = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
-  if ((wg >> 3) >= A.per_xcd) return;
-  const int64_t item = ((wg & 7) * A.per_xcd + (wg >> 3)) * kLocBlock + threadIdx.x;
+// The search for one query point (any coordinates): the minimum value, the
+// sorted index of the minimising site (-1 only for an empty set) and
+// x_site + kL - q.
+struct LocHit {
+  double best, dx, dy, dz;
+  int32_t k;
+};
 
-  double qx, qy, qz;
-  int64_t out;
-  if (A.q) {
-    if (item >= A.Q) return;
-    out = item;
-    qx = A.q[3 * item];
-    qy = A.q[3 * item + 1];
-    qz = A.q[3 * item + 2];
-    if (!(isfinite(qx) && isfinite(qy) && isfinite(qz))) atomicOr(A.status, 1);
-  } else {
-    const int64_t brick = item >> 6;
-    const int l = int(item & 63);
-    const int64_t nb = A.nb;
-    if (brick >= nb * nb * nb) return;
-    const int64_t a = 4 * (brick / (nb * nb)) + (l >> 4);
-    const int64_t b = 4 * ((brick / nb) % nb) + ((l >> 2) & 3);
-    const int64_t c = 4 * (brick % nb) + (l & 3);
-    if (a >= A.ng || b >= A.ng || c >= A.ng) return;
-    out = (a * A.ng + b) * A.ng + c;
-    qx = (double(a) + A.mesh_off) * A.mesh_h;
-    qy = (double(b) + A.mesh_off) * A.mesh_h;
-    qz = (double(c) + A.mesh_off) * A.mesh_h;
-  }
+__device__ __forceinline__ LocHit locate_one(const LocArgs& A, double qx, double qy, double qz) {
   const double L = A.L, h = A.h, bh = BLOCK_SIDE * h;
   qx = wrap_coord(qx, L);
   qy = wrap_coord(qy, L);
@@ -203,22 +184,142 @@ __global__ __launch_bounds__(kLocBlock) void k_locate(LocArgs A) {
       }
     }
   }
-  if (A.phi) A.phi[out] = best;
-  if (A.idx) A.idx[out] = bk >= 0 ? A.perm[bk] : -1;
-  if (A.disp) {
-    A.disp[3 * out] = bx;
-    A.disp[3 * out + 1] = by;
-    A.disp[3 * out + 2] = bz;
+  return LocHit{best, bx, by, bz, bk};
+}
+
+// Item -> mesh node (a, b, c): bricks of 4 x 4 x 4 nodes per wavefront.
+// False past the mesh.
+__device__ __forceinline__ bool mesh_node(int64_t item, int64_t ng, int64_t nb, int64_t& a, int64_t& b,
+                                          int64_t& c) {
+  const int64_t brick = item >> 6;
+  const int l = int(item & 63);
+  if (brick >= nb * nb * nb) return false;
+  a = 4 * (brick / (nb * nb)) + (l >> 4);
+  b = 4 * ((brick / nb) % nb) + ((l >> 2) & 3);
+  c = 4 * (brick % nb) + (l & 3);
+  return a < ng && b < ng && c < ng;
+}
+
+// Workgroup -> item, contiguous ranges per XCD; -1 past the grid.
+__device__ __forceinline__ int64_t xcd_item(int64_t per_xcd) {
+  const int64_t wg = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+  if ((wg >> 3) >= per_xcd) return -1;
+  return ((wg & 7) * per_xcd + (wg >> 3)) * kLocBlock + threadIdx.x;
+}
+
+__global__ __launch_bounds__(kLocBlock) void k_locate(LocArgs A) {
+  const int64_t item = xcd_item(A.per_xcd);
+  if (item < 0) return;
+  double qx, qy, qz;
+  int64_t out;
+  if (A.q) {
+    if (item >= A.Q) return;
+    out = item;
+    qx = A.q[3 * item];
+    qy = A.q[3 * item + 1];
+    qz = A.q[3 * item + 2];
+    if (!(isfinite(qx) && isfinite(qy) && isfinite(qz))) atomicOr(A.status, 1);
+  } else {
+    int64_t a, b, c;
+    if (!mesh_node(item, A.ng, A.nb, a, b, c)) return;
+    out = (a * A.ng + b) * A.ng + c;
+    qx = (double(a) + A.mesh_off) * A.mesh_h;
+    qy = (double(b) + A.mesh_off) * A.mesh_h;
+    qz = (double(c) + A.mesh_off) * A.mesh_h;
   }
+  const LocHit r = locate_one(A, qx, qy, qz);
+  if (A.phi) A.phi[out] = r.best;
+  if (A.idx) A.idx[out] = r.k >= 0 ? A.perm[r.k] : -1;
+  if (A.disp) {
+    A.disp[3 * out] = r.dx;
+    A.disp[3 * out + 1] = r.dy;
+    A.disp[3 * out + 2] = r.dz;
+  }
+}
+
+struct DepArgs {
+  double tau;                 // growth amplitude of the Zel'dovich step, in [0, 1]
+  double H;                   // Eulerian mesh spacing
+  int64_t ne;                 // Eulerian nodes per axis
+  int scheme;                 // 1: nearest grid point, 2: cloud in cell
+  unsigned long long U;       // fixed-point units carried by one mass element
+  unsigned long long* acc;    // [ne^3] accumulated units
+};
+
+__device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// One thread per Lagrangian mass element (mesh node q): locate its cell,
+// move it to y = q + tau (x_i + kL - q), and add its U units to the
+// Eulerian nodes: all to the nearest node (NGP) or split over the 8 nodes
+// around y with the trilinear weights (CIC), rounded to units with the
+// remainder on the heaviest node so each element adds exactly U.  Integer
+// sums are exact and independent of the order of the atomics.
+__global__ __launch_bounds__(kLocBlock) void k_deposit(LocArgs A, DepArgs D) {
+  const int64_t item = xcd_item(A.per_xcd);
+  if (item < 0) return;
+  int64_t a, b, c;
+  if (!mesh_node(item, A.ng, A.nb, a, b, c)) return;
+  const double qx = (double(a) + A.mesh_off) * A.mesh_h, qy = (double(b) + A.mesh_off) * A.mesh_h,
+               qz = (double(c) + A.mesh_off) * A.mesh_h;
+  const LocHit r = locate_one(A, qx, qy, qz);
+  const double L = A.L;
+  const double yx = wrap_coord(qx + D.tau * r.dx, L), yy = wrap_coord(qy + D.tau * r.dy, L),
+               yz = wrap_coord(qz + D.tau * r.dz, L);
+  const double ux = yx / D.H, uy = yy / D.H, uz = yz / D.H;
+  const int64_t ne = D.ne;
+  if (D.scheme == 1) {
+    const int64_t ix = wrap_index(int64_t(floor(ux + 0.5)), ne), iy = wrap_index(int64_t(floor(uy + 0.5)), ne),
+                  iz = wrap_index(int64_t(floor(uz + 0.5)), ne);
+    atomicAdd(&D.acc[(ix * ne + iy) * ne + iz], D.U);
+    return;
+  }
+  const double fx0 = floor(ux), fy0 = floor(uy), fz0 = floor(uz);
+  const double fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
+  const int64_t ix = int64_t(fx0), iy = int64_t(fy0), iz = int64_t(fz0);
+  const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+  unsigned long long u[8];
+  unsigned long long sum = 0;
+  int heavy = 0;
+  double wmax = -1.0;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const double w = wx[t >> 2] * wy[(t >> 1) & 1] * wz[t & 1];
+    u[t] = (unsigned long long)(w * double(D.U) + 0.5);
+    sum += u[t];
+    if (w > wmax) {
+      wmax = w;
+      heavy = t;
+    }
+  }
+  // the heaviest node takes the remainder (its weight is >= 1/8, far above
+  // the rounding of the others)
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+    if (t == heavy) u[t] = D.U - (sum - u[t]);
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    if (u[t] == 0) continue;
+    const int64_t jx = wrap_index(ix + (t >> 2), ne), jy = wrap_index(iy + ((t >> 1) & 1), ne),
+                  jz = wrap_index(iz + (t & 1), ne);
+    atomicAdd(&D.acc[(jx * ne + jy) * ne + jz], u[t]);
+  }
+}
+
+__global__ void k_units_to_density(const unsigned long long* __restrict__ acc, double scale,
+                                   double* __restrict__ rho, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) rho[i] = double(acc[i]) * scale;
 }
 
 }  // namespace
 
-void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, double offset,
-            double* phi, int32_t* idx, double* disp, DevBuf& status, hipStream_t st) {
+namespace {
+
+LocArgs loc_args(const PointSet& ps) {
   LocArgs a{};
-  status.ensure(sizeof(int32_t));
-  a.status = status.as<int32_t>();
   a.pts = ps.pts.as<double4>();
   a.start = ps.cell_start.as<int32_t>();
   a.bsuf = ps.block_suffix.as<double>();
@@ -227,11 +328,41 @@ void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, do
   a.ctmax = ps.cell_tmax.as<double>();
   a.scal = ps.scal.as<double>();
   a.perm = ps.perm.as<int32_t>();
-  a.q = queries;
   a.L = ps.g.L;
   a.h = ps.g.h;
   a.Gn = ps.g.Gn;
   a.Gb = ps.g.Gb;
+  return a;
+}
+
+void set_mesh(LocArgs& a, int64_t ng, double offset) {
+  a.ng = ng;
+  a.nb = ceil_div(ng, 4);
+  a.Q = ng * ng * ng;
+  a.mesh_h = a.L / double(ng);
+  a.mesh_off = offset;
+}
+
+// Grid of `threads` items in workgroups of kLocBlock, dealt to the XCDs in
+// contiguous ranges (2-D above 65536 workgroups).
+dim3 xcd_grid(LocArgs& a, int64_t threads) {
+  const int64_t wgs = ceil_div(threads, kLocBlock);
+  a.per_xcd = ceil_div(wgs, 8);
+  const int64_t total = 8 * a.per_xcd;
+  const int64_t gx = total < 65536 ? total : 65536;
+  const int64_t gy = ceil_div(total, gx);
+  if (gy > 65535) MAK_FAIL(MAK_EINVAL, "too many query points for one launch");
+  return dim3(unsigned(gx), unsigned(gy));
+}
+
+}  // namespace
+
+void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, double offset,
+            double* phi, int32_t* idx, double* disp, DevBuf& status, hipStream_t st) {
+  LocArgs a = loc_args(ps);
+  status.ensure(sizeof(int32_t));
+  a.status = status.as<int32_t>();
+  a.q = queries;
   a.phi = phi;
   a.idx = idx;
   a.disp = disp;
@@ -240,26 +371,17 @@ void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, do
     a.Q = Q;
     threads = Q;
   } else {
-    a.ng = ng;
-    a.nb = ceil_div(ng, 4);
-    a.Q = ng * ng * ng;
-    a.mesh_h = ps.g.L / double(ng);
-    a.mesh_off = offset;
+    set_mesh(a, ng, offset);
     threads = a.nb * a.nb * a.nb * 64;
   }
   if (a.Q == 0) return;
   if (queries) MAK_HIP(hipMemsetAsync(a.status, 0, sizeof(int32_t), st));
-  const int64_t wgs = ceil_div(threads, kLocBlock);
-  a.per_xcd = ceil_div(wgs, 8);
-  const int64_t total = 8 * a.per_xcd;
-  const int64_t gx = total < 65536 ? total : 65536;
-  const int64_t gy = ceil_div(total, gx);
-  if (gy > 65535) MAK_FAIL(MAK_EINVAL, "too many query points for one launch");
+  const dim3 grid = xcd_grid(a, threads);
   ProfScope scope("locate", st, double(a.Q), double(a.Q) * (phi ? 8 : 0) + double(a.Q) * (idx ? 4 : 0) +
                                                  double(a.Q) * (disp ? 24 : 0) +
                                                  double(a.Q) * (queries ? 24 : 0) +
                                                  double(ps.N) * sizeof(double4));
-  hipLaunchKernelGGL(k_locate, dim3(unsigned(gx), unsigned(gy)), dim3(kLocBlock), 0, st, a);
+  hipLaunchKernelGGL(k_locate, grid, dim3(kLocBlock), 0, st, a);
   MAK_HIP(hipGetLastError());
   scope.stop();
   if (queries) {
@@ -268,6 +390,39 @@ void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, do
     MAK_HIP(hipStreamSynchronize(st));
     if (hs) MAK_FAIL(MAK_EINVAL, "non-finite query coordinate");
   }
+}
+
+void za_deposit(const PointSet& ps, double tau, int64_t n_lag, double lag_offset, int64_t ne, int scheme,
+                double* density, DevBuf& acc, hipStream_t st) {
+  LocArgs a = loc_args(ps);
+  set_mesh(a, n_lag, lag_offset);
+  const dim3 grid = xcd_grid(a, a.nb * a.nb * a.nb * 64);
+  const int64_t n_e = ne * ne * ne;
+  DepArgs d{};
+  d.tau = tau;
+  d.H = ps.g.L / double(ne);
+  d.ne = ne;
+  d.scheme = scheme;
+  // units per element: the total over all elements stays below 2^62
+  int bits = 0;
+  while ((int64_t(1) << bits) < a.Q) ++bits;
+  int ub = 62 - bits;
+  if (ub > 52) ub = 52;
+  d.U = 1ull << ub;
+  acc.ensure(size_t(n_e) * sizeof(unsigned long long));
+  d.acc = acc.as<unsigned long long>();
+  MAK_HIP(hipMemsetAsync(d.acc, 0, size_t(n_e) * sizeof(unsigned long long), st));
+  {
+    ProfScope scope("deposit", st, double(a.Q), double(ps.N) * sizeof(double4) + double(n_e) * 16);
+    hipLaunchKernelGGL(k_deposit, grid, dim3(kLocBlock), 0, st, a, d);
+    MAK_HIP(hipGetLastError());
+  }
+  // element mass (L / n_lag)^3 over U units, per Eulerian cell volume H^3
+  const double m_el = std::pow(ps.g.L / double(n_lag), 3);
+  const double scale = m_el / double(d.U) / (d.H * d.H * d.H);
+  hipLaunchKernelGGL(k_units_to_density, dim3(unsigned(ceil_div(n_e, 256))), dim3(256), 0, st, d.acc,
+                     scale, density, n_e);
+  MAK_HIP(hipGetLastError());
 }
 
 }  // namespace mak
