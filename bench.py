@@ -332,7 +332,7 @@ def cpu_baseline(x, L, seconds):
                       f"(one cell pass, {dt:.1f} s)"}
 
 
-def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, seed=1000):
+def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, window_us=0, seed=1000):
     """Continuous-batching serving: requests of the serving mix (lattice side
     log-uniform in [32, 128], rms 0.5..3 spacings) arrive as a Poisson process
     at 0.8 x the closed-loop capacity (the whole mix submitted at once, which
@@ -347,7 +347,8 @@ def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, seed=1000):
                                                seed=r["seed"])).cuda() for r in reqs]
     torch.cuda.synchronize()
     budget = int(budget_gb * (1 << 30))
-    srv = mak.Server(0, precision, mem_budget=budget, max_slots=slots, cg_rtol=cg_rtol)
+    srv = mak.Server(0, precision, mem_budget=budget, max_slots=slots, cg_rtol=cg_rtol,
+                     batch_window_us=window_us)
     # closed-loop capacity: the whole mix submitted at once
     t0 = time.perf_counter()
     rs = [srv.submit(x, 1.0, tol) for x in xs]
@@ -380,7 +381,7 @@ def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, seed=1000):
             "cell_passes_per_shared_launch": st["batched_passes"] / max(st["pass_batches"], 1),
             "max_passes_in_one_launch": st["max_batch"],
             "N_min": int(ns.min()), "N_median": int(np.median(ns)), "N_max": int(ns.max()),
-            "precision": precision, "tol": tol}
+            "batch_window_us": window_us, "precision": precision, "tol": tol}
 
 
 def main():
@@ -407,6 +408,8 @@ def main():
                     help="calls of the Legendre transform, the Zel'dovich deposit and the power "
                          "spectrum on the mesh at the solved weights (0 = skip)")
     ap.add_argument("--serving-slots", type=int, default=4)
+    ap.add_argument("--serving-window-us", type=int, default=2000,
+                    help="batch window of the serving leg's pass batcher (microseconds)")
     ap.add_argument("--serving-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="skip the mixed path's sampled check against the oracle")
@@ -491,7 +494,8 @@ def main():
         res.update(deposit_and_power(mak, x_dev, out[0], L, ng, 0.5, args.legendre_reps, args.workload))
     if args.serving_requests > 0:
         res["serving"] = serving(mak, args.serving_requests, args.serving_slots,
-                                 args.serving_budget_gb, precision, tol, args.cg_rtol)
+                                 args.serving_budget_gb, precision, tol, args.cg_rtol,
+                                 args.serving_window_us)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline(x, L, args.cpu_seconds)

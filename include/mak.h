@@ -70,7 +70,11 @@ typedef struct {
                               1 = float64, 2 = the larger float64 kernel.  A later
                               first stage runs all cells in that fallback kernel
                               (for testing it). */
-  int32_t reserved[6];
+  int32_t batch_window_us; /* server only: after the first cell pass is posted the
+                              batcher waits up to this long (microseconds) for the
+                              passes of the other solves in flight, so they share
+                              launches; default 0 (no wait) */
+  int32_t reserved[5];
 } mak_options;
 
 /* Fill `opt` with the defaults listed above. */

@@ -423,6 +423,7 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
     const double eps0 = 0.5 * std::min(m_min, vmin);
     if (o.verbose) fprintf(stderr, "[mak] N=%lld it=0 err=%.3e minV/m=%.3e\n", (long long)N, err, vmin / m);
     std::string noconv;
+    double prev_alpha = 1.0;
     for (int it = 0;; ++it) {
       if (err <= tol) break;
       if (it >= o.max_newton) {
@@ -430,8 +431,14 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         break;
       }
       newton_residual(ctx->scp.vol.as<double>(), m, ms, ctx->g.as<double>(), N, st);
+      // After a damped step alpha p the residual is about (1 - alpha) g and J
+      // has barely moved, so (1 - alpha) p predicts the next direction: CG
+      // starts there (after a full step, from 0).
+      const bool warm = it > 0 && prev_alpha < 1.0;
+      if (warm)
+        axpy_into(ctx->pstep.as<double>(), ctx->pstep.as<double>(), -prev_alpha, ctx->pstep.as<double>(), N, st);
       const int cgi = pcg_solve(ctx->sJ, ctx->g.as<double>(), ctx->pstep.as<double>(), N, o.cg_rtol,
-                                o.max_cg, ctx->pw, st);
+                                o.max_cg, ctx->pw, st, warm);
       si.cg_iters_total += cgi;
       double alpha = 1.0;
       bool accepted = false;
@@ -488,6 +495,7 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         break;
       }
       si.newton_iters += 1;
+      prev_alpha = alpha;
       if (o.verbose)
         fprintf(stderr, "[mak] it=%d err=%.3e alpha=%g cg=%d minV/m=%.3e\n", it + 1, err, alpha, cgi,
                 vmin / m);

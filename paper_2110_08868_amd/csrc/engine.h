@@ -270,10 +270,12 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp,
 struct PcgWork {
   DevBuf r, z, p, q, dinv, part, scal;
 };
-// Solve J x = b (b mean-free) with Jacobi-preconditioned CG; x is overwritten
-// (start from 0).  Returns the iteration count.
+// Solve J x = b - mean(b) with Jacobi-preconditioned CG to
+// ||r|| <= rtol ||b - mean(b)||; x is overwritten (mean zero on return).  It
+// starts from 0, or with `warm` from the x given when that residual is below
+// ||b - mean(b)||.  Returns the iteration count.
 int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
-              PcgWork& w, hipStream_t st);
+              PcgWork& w, hipStream_t st, bool warm = false);
 
 // Elementwise helpers for the Newton driver.
 // Target masses: per site (ms, sorted order) or, when ms is NULL, m for all.

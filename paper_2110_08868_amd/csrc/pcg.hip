@@ -185,6 +185,48 @@ __global__ __launch_bounds__(TPB) void k_init(const double* __restrict__ b, cons
   }
 }
 
+// warm start from x: r = b - mean - J x (q holds J x); z = dinv r; p = z;
+// partials of r.z and r.r
+__global__ __launch_bounds__(TPB) void k_init_warm(const double* __restrict__ b,
+                                                   const double* __restrict__ scal,
+                                                   const double* __restrict__ q, double* __restrict__ r,
+                                                   double* __restrict__ z, double* __restrict__ p,
+                                                   const double* __restrict__ dinv,
+                                                   double* __restrict__ part, int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  const double mean = scal[S_MEAN] / double(n);
+  double arz = 0.0, arr = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+    const double ri = b[i] - mean - q[i];
+    r[i] = ri;
+    const double zi = dinv[i] * ri;
+    z[i] = zi;
+    p[i] = zi;
+    arz += ri * zi;
+    arr += ri * ri;
+  }
+  arz = block_sum(arz, sh);
+  arr = block_sum(arr, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = arz;
+    part[2 * blockIdx.x + 1] = arr;
+  }
+}
+
+// partials of |b - mean|^2
+__global__ __launch_bounds__(TPB) void k_sq_part(const double* __restrict__ b, const double* __restrict__ scal,
+                                                 double* __restrict__ part, int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  const double mean = scal[S_MEAN] / double(n);
+  double a = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
+    const double v = b[i] - mean;
+    a += v * v;
+  }
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
 __global__ void k_sub_mean(double* __restrict__ x, const double* __restrict__ scal, int slot, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -194,7 +236,7 @@ __global__ void k_sub_mean(double* __restrict__ x, const double* __restrict__ sc
 }  // namespace
 
 int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
-              PcgWork& w, hipStream_t st) {
+              PcgWork& w, hipStream_t st, bool warm) {
   ProfScope whole("pcg_solve", st, double(n));
   w.r.ensure(size_t(n) * sizeof(double));
   w.z.ensure(size_t(n) * sizeof(double));
@@ -214,15 +256,37 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
   const unsigned nb = vec_blocks(n);
   const unsigned nbe = unsigned(ceil_div(n, 256));
 
+  auto spmv = [&](const double* pv, double* qv) {
+    if (J.f32)
+      hipLaunchKernelGGL(k_spmv_dot<float>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
+                         J.col.as<int32_t>(), J.w.as<float>(), J.diag.as<double>(), pv, qv, part, n);
+    else
+      hipLaunchKernelGGL(k_spmv_dot<double>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
+                         J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), pv, qv, part, n);
+  };
   hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.diag.as<double>(), dinv, n);
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, b, part, n);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_MEAN), 0);
-  hipLaunchKernelGGL(k_init, dim3(nb), dim3(TPB), 0, st, b, scal, x, r, z, p, dinv, part, n);
-  hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_RZ0), int(S_BB));
-  MAK_HIP(hipGetLastError());
   double hb[8];
-  MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
-  MAK_HIP(hipStreamSynchronize(st));
+  if (warm) {
+    // start from the given x: r0 = b - J x; kept only if |r0| < |b|
+    hipLaunchKernelGGL(k_sq_part, dim3(nb), dim3(TPB), 0, st, b, scal, part, n);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_BB), 0);
+    spmv(x, q);
+    hipLaunchKernelGGL(k_init_warm, dim3(nb), dim3(TPB), 0, st, b, scal, q, r, z, p, dinv, part, n);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_RZ0), int(S_RR));
+    MAK_HIP(hipGetLastError());
+    MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
+    MAK_HIP(hipStreamSynchronize(st));
+    if (!(hb[S_RR] < hb[S_BB])) warm = false;
+  }
+  if (!warm) {
+    hipLaunchKernelGGL(k_init, dim3(nb), dim3(TPB), 0, st, b, scal, x, r, z, p, dinv, part, n);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_RZ0), int(S_BB));
+    MAK_HIP(hipGetLastError());
+    MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
+    MAK_HIP(hipStreamSynchronize(st));
+  }
   const double bb = hb[S_BB];
   if (!(bb > 0.0)) return 0;
   const double stop = rtol * rtol * bb;

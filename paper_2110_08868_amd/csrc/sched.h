@@ -10,7 +10,8 @@
 // resident between requests).
 //
 // Batcher: solves post jobs (cell passes) and block; one thread takes every
-// job posted so far at once and hands them to the run function together.
+// job posted so far at once (optionally after a short window in which more
+// may arrive) and hands them to the run function together.
 #pragma once
 
 #include <chrono>
@@ -202,6 +203,15 @@ class Batcher {
       if (fini) fini();
     });
   }
+  // After the first posted job the batcher may wait up to `window_us` for
+  // more, until `expect()` jobs are posted (e.g. the number of solves in
+  // flight: when all of them wait for a pass, nothing else will come).
+  // 0 (the default): run what is posted at once.
+  void configure(int64_t window_us, std::function<int()> expect) {
+    std::lock_guard<std::mutex> lk(mu_);
+    window_us_ = window_us;
+    expect_ = std::move(expect);
+  }
   void stop() {
     {
       std::lock_guard<std::mutex> lk(mu_);
@@ -238,6 +248,12 @@ class Batcher {
         std::unique_lock<std::mutex> lk(mu_);
         cv_post_.wait(lk, [&] { return stopping_ || !posted_.empty(); });
         if (posted_.empty()) break;  // stopping with nothing posted
+        if (window_us_ > 0) {
+          const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(window_us_);
+          cv_post_.wait_until(lk, until, [&] {
+            return stopping_ || int(posted_.size()) >= (expect_ ? expect_() : 1);
+          });
+        }
         take.assign(posted_.begin(), posted_.end());
         posted_.clear();
       }
@@ -260,6 +276,8 @@ class Batcher {
   std::condition_variable cv_post_, cv_done_;
   std::deque<Posted*> posted_;
   bool stopping_ = false;
+  int64_t window_us_ = 0;
+  std::function<int()> expect_;
   int64_t batches_ = 0, jobs_ = 0;
   int32_t max_batch_ = 0;
   std::thread th_;

@@ -9,9 +9,11 @@
 // and PCG work of its request runs.
 //
 // Cell passes go through the pass batcher: a solve that needs one posts it
-// and waits; the batcher thread takes every posted pass at once and runs them
-// in shared clip launches on its own stream (each stage launch carries up to
-// kMaxJobs point sets), so concurrent requests share launches.  Every solve
+// and waits; the batcher thread takes every posted pass at once (with a
+// batch window, after waiting up to that long until every solve in flight
+// has posted) and runs them in shared clip launches on its own stream (each
+// stage launch carries up to kMaxJobs point sets), so concurrent requests
+// share launches.  Every solve
 // is deterministic (fixed reduction orders, fixed clip order, a cell's result
 // independent of the other cells in its launch), so a request gives the same
 // bits alone and in a mix.
@@ -141,6 +143,7 @@ extern "C" {
 mak_status mak_server_create(mak_server** out, int device, const mak_options* opt,
                              size_t mem_budget_bytes, int32_t max_slots) {
   if (!out || max_slots < 1 || max_slots > 64) return MAK_EINVAL;
+  if (opt && (opt->batch_window_us < 0 || opt->batch_window_us > 1000000)) return MAK_EINVAL;
   *out = nullptr;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
@@ -156,6 +159,10 @@ mak_status mak_server_create(mak_server** out, int device, const mak_options* op
   s->sched = std::make_unique<Scheduler>(mem_budget_bytes, max_slots, [device, o, pb](int32_t) {
     return std::make_unique<SlotExec>(device, o, pb);
   });
+  if (o.batch_window_us > 0) {
+    Scheduler* sc = s->sched.get();
+    s->batcher.b.configure(o.batch_window_us, [sc] { return int(sc->stats().active); });
+  }
   *out = s;
   return MAK_OK;
 }
@@ -243,6 +250,7 @@ const char* mak_server_last_error(const mak_server* s) { return s ? s->err.c_str
 void mak_server_destroy(mak_server* s) {
   if (!s) return;
   s->sched->shutdown();  // finishes queued and running requests
+  s->batcher.b.configure(0, {});
   s->sched.reset();
   s->batcher.b.stop();
   delete s;

@@ -118,6 +118,30 @@ static void batcher_scenario(int threads, int posts, int ms) {
               (long long)nb, (long long)nj, mx, once, seen.load());
 }
 
+// Three threads post one job each, 20 ms apart, to a batcher that waits up
+// to `window_ms` for as many jobs as there are threads.
+static void window_scenario(int window_ms) {
+  Batcher<int> b;
+  b.start([&](std::vector<int*>& jobs) {
+    for (int* j : jobs) *j += 1;
+  });
+  b.configure(int64_t(window_ms) * 1000, [] { return 3; });
+  std::vector<int> runs(3, 0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < 3; ++t)
+    th.emplace_back([&, t] {
+      std::this_thread::sleep_for(std::chrono::milliseconds(20 * t));
+      b.post(&runs[size_t(t)]);
+    });
+  for (auto& x : th) x.join();
+  b.stop();
+  int64_t nb = 0, nj = 0;
+  int32_t mx = 0;
+  b.counters(&nb, &nj, &mx);
+  std::printf("{\"batches\": %lld, \"jobs\": %lld, \"max_batch\": %d, \"every_job_once\": %d}\n",
+              (long long)nb, (long long)nj, mx, int(runs[0] == 1 && runs[1] == 1 && runs[2] == 1));
+}
+
 int main(int argc, char** argv) {
   const std::string which = argc > 1 ? argv[1] : "";
   if (which == "budget") {
@@ -135,6 +159,10 @@ int main(int argc, char** argv) {
     scenario(0, 3, {{1, 30, 0}, {1, 30, 0}, {1, 30, 0}, {1, 30, 0}, {1, 30, 0}, {1, 30, 0}, {1, 30, 0}});
   } else if (which == "batcher") {
     batcher_scenario(6, 20, 5);
+  } else if (which == "window") {
+    window_scenario(500);
+  } else if (which == "nowindow") {
+    window_scenario(0);
   } else {
     std::fprintf(stderr, "unknown scenario\n");
     return 2;

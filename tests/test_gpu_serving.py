@@ -20,7 +20,10 @@ def test_same_alone_and_in_the_mix():
     ctx = mak.Context(0, cg_rtol=1e-6)
     solo = [tuple(t.cpu().numpy() for t in ctx.solve(torch.from_numpy(x), 1.0, 1e-8)[:3]) for x in xs]
     ctx.close()
-    srv = mak.Server(0, max_slots=3, cg_rtol=1e-6)
+    # a batch window long enough that the first passes of the admitted
+    # requests always meet (the batch fires once every solve in flight has
+    # posted)
+    srv = mak.Server(0, max_slots=3, cg_rtol=1e-6, batch_window_us=200000)
     reqs = [srv.submit(torch.from_numpy(x), 1.0, 1e-8) for x in xs]
     for r, (p0, c0, d0) in zip(reqs, solo):
         psi, C, D, info = r.wait()

@@ -70,3 +70,12 @@ def test_batcher_packs_concurrent_posts(driver):
     r = run(driver, "batcher")
     assert r["every_job_once"] == 1 and r["seen"] == r["jobs"] == 120
     assert r["max_batch"] >= 2 and r["batches"] < 120
+
+
+def test_batcher_window_gathers_staggered_posts(driver):
+    """With a window, posts 20 ms apart wait for each other (one batch of
+    three); without one, each runs as it comes."""
+    r = run(driver, "window")
+    assert r["every_job_once"] == 1 and r["batches"] == 1 and r["max_batch"] == 3
+    r = run(driver, "nowindow")
+    assert r["every_job_once"] == 1 and r["batches"] == 3 and r["max_batch"] == 1
