@@ -9,6 +9,7 @@
 // full passes (faces included), so an accepted trial's Hessian is reused.
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <exception>
 #include <string>
@@ -119,6 +120,7 @@ struct mak_ctx {
   Lap sJ;
   PcgWork pw;
   DevBuf psi_s, psi_t, g, pstep, mass_s, tmp;
+  DevBuf probe_list, probe_tmp;  // probe cells of a trial: earlier rejecting cells + the smallest
   // Legendre transform / point location
   PointSet lps;
   DevBuf lstatus, dep_acc;
@@ -398,7 +400,8 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         MAK_FAIL(MAK_EINVAL, "masses must be positive and sum to L^3");
     }
 
-    auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Lap* warm) {
+    auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Lap* warm, int64_t probe_n = 0,
+                    const int32_t* probe_list = nullptr) {
       PassOpts po;
       po.precision = o.precision;
       po.tolerate_failure = tolerate;
@@ -408,8 +411,24 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         po.warm_col = warm->col.as<int32_t>();
       }
       po.first_stage = o.first_stage;
+      if (probe_n > 0) {
+        po.faces = false;
+        po.probe_list = probe_list;
+        po.probe_n = probe_n;
+      }
       return ctx->runner ? ctx->runner->run(ps, cp, po, st) : run_cells(ps, cp, po, st);
     };
+    // Probe of a line-search trial: the cells that rejected the earlier
+    // trials of the same Newton step are clipped first (the shorter step
+    // usually fails on the same cell); one of them below eps0 rejects the
+    // trial without the full pass, which would have been rejected for the
+    // same cell.  (A linearised volume cannot point at them: the Newton step
+    // moves every linearised volume towards its mass.)
+    constexpr int kProbeCap = 64;
+    const int64_t kSmall = std::min<int64_t>(8192, N);
+    ctx->probe_list.ensure(size_t(kProbeCap + kSmall) * sizeof(int32_t));
+    std::vector<int32_t> doomed_cells;
+    int64_t n_small = 0;
     set_psi_sorted(ps, psi_s, st);
     ClipStats cs = pass(ctx->scp, false, 0.0, nullptr);
     si.cell_passes = 1;
@@ -440,12 +459,36 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
       const int cgi = pcg_solve(ctx->sJ, ctx->g.as<double>(), ctx->pstep.as<double>(), N, o.cg_rtol,
                                 o.max_cg, ctx->pw, st, warm);
       si.cg_iters_total += cgi;
+      doomed_cells.clear();
+      // the smallest cells of the accepted pass follow the doomed ones in the list
+      n_small = smallest_cells(ctx->scp.vol.as<double>(), eps0, ctx->probe_list.as<int32_t>() + kProbeCap,
+                               kSmall, N, ctx->probe_tmp, st);
       double alpha = 1.0;
       bool accepted = false;
       for (int ls = 0; ls <= o.max_halvings; ++ls) {
         axpy_into(ctx->psi_s.as<double>(), ctx->pstep.as<double>(), alpha, ctx->psi_t.as<double>(), N, st);
         set_psi_sorted(ps, ctx->psi_t.as<double>(), st);
         const auto tp0 = std::chrono::steady_clock::now();
+        const int64_t nd = int64_t(doomed_cells.size());
+        if (nd + n_small > 0) {
+          // doomed cells fill the slots just before the smallest ones
+          int32_t* list = ctx->probe_list.as<int32_t>() + (kProbeCap - nd);
+          if (nd > 0)
+            MAK_HIP(hipMemcpyAsync(list, doomed_cells.data(), size_t(nd) * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, st));
+          const ClipStats pc = pass(ctx->scp_trial, true, eps0, &ctx->sJ, nd + n_small, list);
+          if (pc.doomed) {
+            si.cell_passes += 1;
+            si.ls_trials += 1;
+            si.abandoned_trials += 1;
+            if (o.verbose >= 2)
+              fprintf(stderr, "[mak]   trial alpha=%g probe of %lld cells %.1f ms: a cell below eps0, abandoned\n",
+                      alpha, (long long)(nd + n_small),
+                      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());
+            alpha *= 0.5;
+            continue;
+          }
+        }
         // a trial with a cell below eps0 is rejected whatever else it gives:
         // the pass stops at the first such cell
         // the accepted pass's neighbours (J) warm-start the trial
@@ -454,6 +497,9 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         si.ls_trials += 1;
         if (ct.doomed) {
           si.abandoned_trials += 1;
+          if (ct.doom_cell >= 0 && ct.doom_cell < N && int(doomed_cells.size()) < kProbeCap &&
+              std::find(doomed_cells.begin(), doomed_cells.end(), int32_t(ct.doom_cell)) == doomed_cells.end())
+            doomed_cells.push_back(int32_t(ct.doom_cell));
           if (o.verbose >= 2)
             fprintf(stderr, "[mak]   trial alpha=%g pass %.1f ms: a cell below eps0, abandoned\n", alpha,
                     std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());

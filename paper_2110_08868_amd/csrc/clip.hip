@@ -88,6 +88,7 @@ struct ClipArgs {
   // rejects the trial; it raises *doom and the workgroups that start after
   // it skip their cell (the host discards the pass).  doom == NULL: off.
   unsigned int* doom;
+  unsigned long long* doom_cell;  // a cell that raised *doom (sorted index)
   double doom_vol;
 };
 
@@ -1012,8 +1013,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     flush_stats(0, 0);
     if (lane == 0) {
       if (A.doom && (flags & CF_EMPTY) &&
-          !(flags & (CF_CAPACITY | CF_NONMANIFOLD | CF_NEARDEG)))
+          !(flags & (CF_CAPACITY | CF_NONMANIFOLD | CF_NEARDEG))) {
         __hip_atomic_store(A.doom, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(A.doom_cell, (unsigned long long)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (flags & (CF_CAPACITY | CF_NONMANIFOLD | CF_NEARDEG)) {
         atomicAdd(&A.cause[(flags & CF_CAPACITY) ? 0 : ((flags & CF_NONMANIFOLD) ? 1 : 2)], 1ull);
         const unsigned long long r = atomicAdd(A.retry_count, 1ull);
@@ -1204,8 +1207,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   }
   flush_stats(nT, nf);
   if (lane == 0) {
-    if (A.doom && v6 / 6.0 < A.doom_vol)
+    if (A.doom && v6 / 6.0 < A.doom_vol) {
       __hip_atomic_store(A.doom, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(A.doom_cell, (unsigned long long)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     A.vol[p] = v6 / 6.0;
     A.mom[3 * p] = m0 / 24.0;
     A.mom[3 * p + 1] = m1 / 24.0;
@@ -1283,7 +1288,8 @@ namespace {
 //   float64: <2 vertices per lane, f64>  ->  <4, f64, wider tie tolerance>
 //   mixed:   <2, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
 // counters of a pass: [0] overflow faces used, [1 + s] cells listed by stage
-// s, [4] doom flag of a line-search trial, [8..8 + ST_N) work counters,
+// s, [4] doom flag of a line-search trial, [5] a cell that raised it,
+// [8..8 + ST_N) work counters,
 // [32 + 3 s ..] causes (capacity, cut, ambiguity)
 int num_stages(int precision) { return precision == MAK_MIXED ? 3 : 2; }
 
@@ -1291,8 +1297,8 @@ void job_begin(PassJob& jb, hipStream_t st) {
   CellPass& out = *jb.out;
   MAK_HIP(hipMemsetAsync(out.counters.p, 0, 64 * sizeof(unsigned long long), st));
   jb.stage = jb.opt.first_stage;
-  jb.all_cells = true;
-  jb.listed = jb.ps->N;
+  jb.all_cells = jb.opt.probe_n <= 0;
+  jb.listed = jb.all_cells ? jb.ps->N : jb.opt.probe_n;
   jb.cs = ClipStats();
 }
 
@@ -1332,7 +1338,10 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.area_min = 1e-12 * spacing * spacing;
   a.tol_rel = 1e-6;
   a.stats = nullptr;
-  a.work = jb.all_cells ? nullptr : out.retry.as<int32_t>() + (stage - 1) * N;
+  if (jb.opt.probe_n > 0)
+    a.work = jb.opt.probe_list;
+  else
+    a.work = jb.all_cells ? nullptr : out.retry.as<int32_t>() + (stage - 1) * N;
   a.nwork = jb.listed;
   a.per_xcd = ceil_div(jb.listed, 8);
   a.retry = out.retry.as<int32_t>() + stage * N;
@@ -1340,6 +1349,7 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.cause = ctr + 32 + 3 * stage;
   a.eps_rel = stage == nstage - 1 ? 1e-11 : 1e-13;
   a.doom = jb.opt.doom_vol > 0 ? reinterpret_cast<unsigned int*>(ctr + 4) : nullptr;
+  a.doom_cell = ctr + 5;
   a.doom_vol = jb.opt.doom_vol;
   return a;
 }
@@ -1395,6 +1405,9 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
       out.counters.ensure(64 * sizeof(unsigned long long));
       if (jb.opt.first_stage < 0 || jb.opt.first_stage >= nstage)
         MAK_FAIL(MAK_EINVAL, "first stage out of range");
+      if (jb.opt.probe_n > 0 && (!jb.opt.probe_list || jb.opt.probe_n > N || jb.opt.faces ||
+                                 !(jb.opt.doom_vol > 0)))
+        MAK_FAIL(MAK_EINVAL, "a probe needs a cell list of at most N cells, no faces and doom_vol > 0");
       if (jb.opt.faces) {
         fst.faces.ensure(size_t(N) * fst.fslot * sizeof(FaceRec));
         fst.fbase.ensure(size_t(N) * sizeof(int64_t));
@@ -1438,8 +1451,10 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
         }
         if (jb->hc[4] != 0) {  // a cell below doom_vol: the trial is rejected
           jb->cs.doomed = true;
+          jb->cs.doom_cell = int64_t(jb->hc[5]);
           continue;
         }
+        if (jb->opt.probe_n > 0) continue;  // a probe stops after its first stage
         const int64_t listed = int64_t(jb->hc[1 + s]);
         if (jb->all_cells) jb->cs.retried = listed;
         if (mixed && s == 0) jb->cs.fp64_rerun = listed;

@@ -158,6 +158,7 @@ void update_psi_bounds(PointSet& ps, hipStream_t st);
 struct ClipStats {
   int64_t retried = 0, overflow = 0, fp64_rerun = 0;
   bool doomed = false;  // a cell ended below doom_vol: the pass was abandoned
+  int64_t doom_cell = -1;  // one such cell (sorted index)
 };
 // How one cell pass runs.
 struct PassOpts {
@@ -178,6 +179,13 @@ struct PassOpts {
   // Stage the pass starts at (0: the first kernel); > 0 runs every cell in
   // the fallback kernels (testing them).
   int first_stage = 0;
+  // A probe (probe_n > 0, with doom_vol > 0): only the listed cells (sorted
+  // indices, device), only the first stage, no faces; ClipStats::doomed
+  // reports whether one of them ended below doom_vol.  Cells the first stage
+  // cannot finish are left undecided.  Each listed cell gets the bits the
+  // full pass would give it, so a doomed probe means a doomed pass.
+  const int32_t* probe_list = nullptr;
+  int64_t probe_n = 0;
 };
 
 // Full cell pass at the psi stored in ps.pts[].w.  Throws on failure.
@@ -283,6 +291,12 @@ void newton_residual(const double* vol, double m, const double* ms, double* g, i
                      hipStream_t st);
 void axpy_into(const double* psi, const double* p, double alpha, double* out, int64_t n,
                hipStream_t st);
+// The cells with the smallest volumes: every cell below v0 2^k for the
+// largest k that lists at most `cap` of them (sorted indices into `list`, in
+// no particular order); returns how many were listed.
+int64_t smallest_cells(const double* vol, double v0, int32_t* list, int64_t cap, int64_t n, DevBuf& tmp,
+                       hipStream_t st);
+
 // Returns ||m - V||_2; max_rel = max_i |m_i - V_i| / m_i, min_vol = min_i V_i.
 double residual_stats(const double* vol, double m, const double* ms, int64_t n, DevBuf& tmp,
                       double* max_rel, double* min_vol, hipStream_t st);

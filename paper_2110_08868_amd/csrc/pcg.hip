@@ -335,6 +335,30 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
 // ---------------------------------------------------------------- Newton helpers
 namespace {
 
+// histogram of floor(log2(V / v0)) + 1 (0 below v0), 64 buckets
+__global__ __launch_bounds__(256) void k_vol_hist(const double* __restrict__ vol, double v0,
+                                                  unsigned long long* __restrict__ hist, int64_t n) {
+  __shared__ unsigned int h[64];
+  if (threadIdx.x < 64) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double r = vol[i] / v0;
+    int b = r < 1.0 ? 0 : int(floor(log2(r))) + 1;
+    b = b > 63 ? 63 : b;
+    atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+__global__ void k_select_below(const double* __restrict__ vol, double thresh, int32_t* __restrict__ list,
+                               unsigned long long* __restrict__ count, int64_t cap, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n || !(vol[i] < thresh)) return;
+  const unsigned long long k = atomicAdd(count, 1ull);
+  if (int64_t(k) < cap) list[k] = int32_t(i);
+}
+
 __global__ void k_axpy_into(const double* __restrict__ a, const double* __restrict__ b, double alpha,
                             double* __restrict__ out, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -507,6 +531,30 @@ void gather_sorted(const PointSet& ps, const double* orig, double* sorted, hipSt
   hipLaunchKernelGGL(k_gather, dim3(unsigned(ceil_div(ps.N, 256))), dim3(256), 0, st,
                      ps.perm.as<int32_t>(), orig, sorted, ps.N);
   MAK_HIP(hipGetLastError());
+}
+
+int64_t smallest_cells(const double* vol, double v0, int32_t* list, int64_t cap, int64_t n, DevBuf& tmp,
+                       hipStream_t st) {
+  tmp.ensure(66 * sizeof(unsigned long long));
+  unsigned long long* hist = tmp.as<unsigned long long>();
+  MAK_HIP(hipMemsetAsync(hist, 0, 66 * sizeof(unsigned long long), st));
+  const unsigned nb = unsigned(std::min<int64_t>(ceil_div(n, 256), 2048));
+  hipLaunchKernelGGL(k_vol_hist, dim3(nb), dim3(256), 0, st, vol, v0, hist, n);
+  unsigned long long h[64];
+  MAK_HIP(hipMemcpyAsync(h, hist, sizeof(h), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  // the largest power-of-two bound below which at most cap cells lie
+  int64_t cum = 0;
+  int b = 0;
+  while (b < 64 && cum + int64_t(h[b]) <= cap) cum += int64_t(h[b++]);
+  if (cum == 0) return 0;
+  hipLaunchKernelGGL(k_select_below, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st, vol,
+                     std::ldexp(v0, b - 1), list, hist + 64, cap, n);
+  MAK_HIP(hipGetLastError());
+  unsigned long long got = 0;
+  MAK_HIP(hipMemcpyAsync(&got, hist + 64, sizeof(got), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  return std::min<int64_t>(int64_t(got), cap);
 }
 
 }  // namespace mak
