@@ -113,26 +113,32 @@ __global__ __launch_bounds__(64) void k_block_max(const double* __restrict__ cma
 
 // For every block b and r = 0..SHELL_MAX: the largest weight in the
 // (unwrapped, periodic) blocks at Chebyshev block distance exactly r from b.
-// One thread per block walks the shells outwards.
-__global__ void k_block_suffix(const double* __restrict__ bmax, double* __restrict__ suf, int Gb,
-                               int64_t GB) {
-  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// One wave per block: the lanes share the (2 SHELL_MAX + 1)^3 offsets and
+// reduce per shell.
+__global__ __launch_bounds__(64) void k_block_suffix(const double* __restrict__ bmax, double* __restrict__ suf,
+                                                     int Gb, int64_t GB) {
+  const int64_t b = blockIdx.x;
   if (b >= GB) return;
+  const int lane = threadIdx.x;
   const int bx = int(b / (int64_t(Gb) * Gb)), by = int((b / Gb) % Gb), bz = int(b % Gb);
+  constexpr int S = 2 * SHELL_MAX + 1;
   double sh[SHELL_MAX + 1];
-  for (int r = 0; r <= SHELL_MAX; ++r) {
-    double m = -DBL_MAX;
-    for (int ox = -r; ox <= r; ++ox)
-      for (int oy = -r; oy <= r; ++oy)
-        for (int oz = -r; oz <= r; ++oz) {
-          if (max(abs(ox), max(abs(oy), abs(oz))) != r) continue;
-          const int wx = ((bx + ox) % Gb + Gb) % Gb, wy = ((by + oy) % Gb + Gb) % Gb,
-                    wz = ((bz + oz) % Gb + Gb) % Gb;
-          m = fmax(m, bmax[(int64_t(wx) * Gb + wy) * Gb + wz]);
-        }
-    sh[r] = m;
+#pragma unroll
+  for (int r = 0; r <= SHELL_MAX; ++r) sh[r] = -DBL_MAX;
+  for (int t = lane; t < S * S * S; t += 64) {
+    const int ox = t / (S * S) - SHELL_MAX, oy = (t / S) % S - SHELL_MAX, oz = t % S - SHELL_MAX;
+    const int r = max(abs(ox), max(abs(oy), abs(oz)));
+    const int wx = ((bx + ox) % Gb + Gb) % Gb, wy = ((by + oy) % Gb + Gb) % Gb, wz = ((bz + oz) % Gb + Gb) % Gb;
+    const double v = bmax[(int64_t(wx) * Gb + wy) * Gb + wz];
+#pragma unroll
+    for (int q = 0; q <= SHELL_MAX; ++q)
+      if (q == r) sh[q] = fmax(sh[q], v);
   }
-  for (int r = 0; r <= SHELL_MAX; ++r) suf[b * (SHELL_MAX + 1) + r] = sh[r];
+#pragma unroll
+  for (int r = 0; r <= SHELL_MAX; ++r) {
+    const double m = wave_max_d(sh[r]);
+    if (lane == 0) suf[b * (SHELL_MAX + 1) + r] = m;
+  }
 }
 
 // Tilted weight bounds.  For block B with centre x_B take a slope g_B (the
@@ -142,12 +148,17 @@ __global__ void k_block_suffix(const double* __restrict__ bmax, double* __restri
 // psi_j <= M + g_B . (x_j - x_B).  The clip kernel's box tests use these, so
 // a linear trend of the weights across a block (converged weights follow the
 // displacement field) does not inflate the bound of the whole block.
-// One thread per block; the block's sites are contiguous (block-major keys).
-__global__ void k_block_tilt(const int32_t* __restrict__ start, const double4* __restrict__ pts,
-                             double bh, int Gb, int64_t GB, double* __restrict__ block_g,
-                             double* __restrict__ block_tmax, double* __restrict__ cell_tmax) {
-  const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// One wave per block (its sites are contiguous: block-major keys): the lanes
+// share the block's sites for the sums of the normal equations; lane c then
+// takes cell c of the block.
+__global__ __launch_bounds__(64) void k_block_tilt(const int32_t* __restrict__ start,
+                                                   const double4* __restrict__ pts, double bh, int Gb,
+                                                   int64_t GB, double* __restrict__ block_g,
+                                                   double* __restrict__ block_tmax,
+                                                   double* __restrict__ cell_tmax) {
+  const int64_t b = blockIdx.x;
   if (b >= GB) return;
+  const int lane = threadIdx.x;
   const int bx = int(b / (int64_t(Gb) * Gb)), by = int((b / Gb) % Gb), bz = int(b % Gb);
   const double ox = (bx + 0.5) * bh, oy = (by + 0.5) * bh, oz = (bz + 0.5) * bh;
   const int32_t s0 = start[b * 64], s1 = start[b * 64 + 64];
@@ -155,19 +166,19 @@ __global__ void k_block_tilt(const int32_t* __restrict__ start, const double4* _
   double gx = 0.0, gy = 0.0, gz = 0.0;
   if (n >= 4) {
     double mx = 0, my = 0, mz = 0, mp = 0;
-    for (int32_t k = s0; k < s1; ++k) {
+    for (int32_t k = s0 + lane; k < s1; k += 64) {
       const double4 P = pts[k];
       mx += P.x - ox;
       my += P.y - oy;
       mz += P.z - oz;
       mp += P.w;
     }
-    mx /= n;
-    my /= n;
-    mz /= n;
-    mp /= n;
+    mx = wave_sum_d(mx) / n;
+    my = wave_sum_d(my) / n;
+    mz = wave_sum_d(mz) / n;
+    mp = wave_sum_d(mp) / n;
     double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0, vx = 0, vy = 0, vz = 0;
-    for (int32_t k = s0; k < s1; ++k) {
+    for (int32_t k = s0 + lane; k < s1; k += 64) {
       const double4 P = pts[k];
       const double ex = P.x - ox - mx, ey = P.y - oy - my, ez = P.z - oz - mz, ep = P.w - mp;
       cxx += ex * ex;
@@ -180,6 +191,15 @@ __global__ void k_block_tilt(const int32_t* __restrict__ start, const double4* _
       vy += ey * ep;
       vz += ez * ep;
     }
+    cxx = wave_sum_d(cxx);
+    cxy = wave_sum_d(cxy);
+    cxz = wave_sum_d(cxz);
+    cyy = wave_sum_d(cyy);
+    cyz = wave_sum_d(cyz);
+    czz = wave_sum_d(czz);
+    vx = wave_sum_d(vx);
+    vy = wave_sum_d(vy);
+    vz = wave_sum_d(vz);
     // adjugate solve of the 3x3 normal equations, skipped when ill-conditioned
     const double a00 = cyy * czz - cyz * cyz, a01 = cxz * cyz - cxy * czz, a02 = cxy * cyz - cxz * cyy;
     const double a11 = cxx * czz - cxz * cxz, a12 = cxy * cxz - cxx * cyz, a22 = cxx * cyy - cxy * cxy;
@@ -191,20 +211,19 @@ __global__ void k_block_tilt(const int32_t* __restrict__ start, const double4* _
       gz = (a02 * vx + a12 * vy + a22 * vz) / det;
     }
   }
-  double M = -DBL_MAX;
-  for (int c = 0; c < 64; ++c) {
-    double mc = -DBL_MAX;
-    for (int32_t k = start[b * 64 + c]; k < start[b * 64 + c + 1]; ++k) {
-      const double4 P = pts[k];
-      mc = fmax(mc, P.w - (gx * (P.x - ox) + gy * (P.y - oy) + gz * (P.z - oz)));
-    }
-    cell_tmax[b * 64 + c] = mc;
-    M = fmax(M, mc);
+  double mc = -DBL_MAX;
+  for (int32_t k = start[b * 64 + lane]; k < start[b * 64 + lane + 1]; ++k) {
+    const double4 P = pts[k];
+    mc = fmax(mc, P.w - (gx * (P.x - ox) + gy * (P.y - oy) + gz * (P.z - oz)));
   }
-  block_tmax[b] = M;
-  block_g[3 * b] = gx;
-  block_g[3 * b + 1] = gy;
-  block_g[3 * b + 2] = gz;
+  cell_tmax[b * 64 + lane] = mc;
+  const double M = wave_max_d(mc);
+  if (lane == 0) {
+    block_tmax[b] = M;
+    block_g[3 * b] = gx;
+    block_g[3 * b + 1] = gy;
+    block_g[3 * b + 2] = gz;
+  }
 }
 
 }  // namespace
@@ -273,9 +292,9 @@ void update_psi_bounds(PointSet& ps, hipStream_t st) {
                      ps.cell_start.as<int32_t>(), ps.pts.as<double4>(), ps.cell_psimax.as<double>(), G);
   hipLaunchKernelGGL(k_block_max, dim3(unsigned(GB)), dim3(64), 0, st, ps.cell_psimax.as<double>(),
                      ps.block_psimax.as<double>(), GB);
-  hipLaunchKernelGGL(k_block_suffix, dim3(unsigned(ceil_div(GB, 64))), dim3(64), 0, st,
+  hipLaunchKernelGGL(k_block_suffix, dim3(unsigned(GB)), dim3(64), 0, st,
                      ps.block_psimax.as<double>(), ps.block_suffix.as<double>(), ps.g.Gb, GB);
-  hipLaunchKernelGGL(k_block_tilt, dim3(unsigned(ceil_div(GB, 64))), dim3(64), 0, st,
+  hipLaunchKernelGGL(k_block_tilt, dim3(unsigned(GB)), dim3(64), 0, st,
                      ps.cell_start.as<int32_t>(), ps.pts.as<double4>(), BLOCK_SIDE * ps.g.h, ps.g.Gb,
                      GB, ps.block_g.as<double>(), ps.block_tmax.as<double>(), ps.cell_tmax.as<double>());
   MAK_HIP(hipGetLastError());
