@@ -88,34 +88,118 @@ __global__ void k_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* 
   }
 }
 
-// Laplacian rows (sorted space): one weight per distinct neighbour, summed
-// over its images in face order, and the diagonal as the sum of the stored
-// (rounded) weights.
-template <typename W>
-__global__ void k_lap_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* fbase, int32_t fslot,
-                           const int32_t* __restrict__ nface, const int64_t* __restrict__ row_ptr,
-                           int32_t* __restrict__ col, W* __restrict__ w, double* __restrict__ diag,
-                           int64_t n) {
+// The solver's Laplacian rows straight from the face records, without
+// sorting them: a row's faces (at most kRegFaces, the face slots of a cell)
+// are held in registers; its distinct neighbours are the faces whose column
+// does not occur earlier in the list, the rank of a column is the number of
+// distinct columns below it, and a column's weight is the sum of its faces'
+// weights in list order.  A row kept in the overflow region (more faces than
+// slots) is done the same way from memory.  (The weights stay in memory and
+// are read back from the cache for each column's faces.)
+constexpr int kRegFaces = 32;
+
+__device__ int32_t lap_row_mem(const FaceRec* f, int32_t nf, int32_t* col, float* wf, double* wd,
+                               double* diag) {
+  int32_t cnt = 0;
+  double d = 0.0;
+  for (int32_t k = 0; k < nf; ++k) {
+    bool first = true;
+    for (int32_t m = 0; m < k && first; ++m) first = f[m].j != f[k].j;
+    if (!first) continue;
+    ++cnt;
+    if (!col) continue;
+    int32_t rank = 0;
+    double s = 0.0;
+    for (int32_t m = 0; m < nf; ++m) {
+      if (f[m].j == f[k].j) s += f[m].w;
+      if (f[m].j < f[k].j) {
+        bool fm = true;
+        for (int32_t u = 0; u < m && fm; ++u) fm = f[u].j != f[m].j;
+        rank += fm ? 1 : 0;
+      }
+    }
+    col[rank] = f[k].j;
+    if (wf) {
+      wf[rank] = float(s);
+      d += double(float(s));
+    } else {
+      wd[rank] = s;
+      d += s;
+    }
+  }
+  if (diag) *diag = d;
+  return cnt;
+}
+
+__global__ __launch_bounds__(256) void k_lap_count(const FaceRec* faces, const FaceRec* ovf, const int64_t* fbase, int32_t fslot,
+                            const int32_t* __restrict__ nface, int64_t* __restrict__ rowcnt, int64_t n) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const int32_t nf = nface[p];
   const FaceRec* f = face_list(const_cast<FaceRec*>(faces), const_cast<FaceRec*>(ovf), fbase, fslot,
                                int32_t(p), nf);
-  int64_t o = row_ptr[p];
+  if (nf > kRegFaces) {
+    rowcnt[p] = lap_row_mem(f, nf, nullptr, nullptr, nullptr, nullptr);
+    return;
+  }
+  int32_t jj[kRegFaces];
+#pragma unroll
+  for (int k = 0; k < kRegFaces; ++k) jj[k] = k < nf ? f[k].j : -1 - k;
+  int32_t cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kRegFaces; ++k) {
+    bool first = k < nf;
+#pragma unroll
+    for (int m = 0; m < k; ++m) first = first && jj[m] != jj[k];
+    cnt += first ? 1 : 0;
+  }
+  rowcnt[p] = cnt;
+}
+
+template <typename W>
+__global__ __launch_bounds__(256) void k_lap_fill_rows(const FaceRec* faces, const FaceRec* ovf, const int64_t* fbase, int32_t fslot,
+                                const int32_t* __restrict__ nface, const int64_t* __restrict__ row_ptr,
+                                int32_t* __restrict__ col, W* __restrict__ w, double* __restrict__ diag,
+                                int64_t n) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t nf = nface[p];
+  const FaceRec* f = face_list(const_cast<FaceRec*>(faces), const_cast<FaceRec*>(ovf), fbase, fslot,
+                               int32_t(p), nf);
+  const int64_t o = row_ptr[p];
+  if (nf > kRegFaces) {
+    if (sizeof(W) == 4)
+      lap_row_mem(f, nf, col + o, reinterpret_cast<float*>(w + o), nullptr, diag + p);
+    else
+      lap_row_mem(f, nf, col + o, nullptr, reinterpret_cast<double*>(w + o), diag + p);
+    return;
+  }
+  int32_t jj[kRegFaces];
+#pragma unroll
+  for (int k = 0; k < kRegFaces; ++k) jj[k] = k < nf ? f[k].j : -1 - k;
+  uint32_t firsts = 0;
+#pragma unroll
+  for (int k = 0; k < kRegFaces; ++k) {
+    bool first = k < nf;
+#pragma unroll
+    for (int m = 0; m < k; ++m) first = first && jj[m] != jj[k];
+    firsts |= first ? (1u << k) : 0u;
+  }
   double d = 0.0;
-  int32_t k = 0;
-  while (k < nf) {
-    const int32_t c = f[k].j;
+#pragma unroll
+  for (int k = 0; k < kRegFaces; ++k) {
+    if (!((firsts >> k) & 1u)) continue;
+    int32_t rank = 0;
     double s = 0.0;
-    while (k < nf && f[k].j == c) {
-      s += f[k].w;
-      ++k;
+#pragma unroll
+    for (int m = 0; m < kRegFaces; ++m) {
+      if (jj[m] == jj[k]) s += f[m].w;  // the weights are read back (cached) only for the column's faces
+      rank += (((firsts >> m) & 1u) && jj[m] < jj[k]) ? 1 : 0;
     }
     const W ws = W(s);
-    col[o] = c;
-    w[o] = ws;
+    col[o + rank] = jj[k];
+    w[o + rank] = ws;
     d += double(ws);
-    ++o;
   }
   diag[p] = d;
 }
@@ -188,9 +272,9 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
   J.diag.ensure(size_t(n) * sizeof(double));
   const unsigned nb = unsigned(ceil_div(n, 256));
   const FaceStore& fst = cp.fs();
-  hipLaunchKernelGGL(k_sort_count, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
-                     fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
-                     nullptr, J.rowcnt.as<int64_t>(), nullptr, n, 0);
+  if (fst.fslot > kRegFaces) MAK_FAIL(MAK_EHIP, "face slots exceed the register rows of the assembly");
+  hipLaunchKernelGGL(k_lap_count, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(), fst.ovf.as<FaceRec>(),
+                     fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(), J.rowcnt.as<int64_t>(), n);
   MAK_HIP(hipGetLastError());
   exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr.as<int64_t>(), n, cp.scan_tmp, st);
   int64_t nnz = 0;
@@ -200,12 +284,12 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
   J.col.ensure(size_t(nnz) * sizeof(int32_t));
   J.w.ensure(size_t(nnz) * (f32 ? sizeof(float) : sizeof(double)));
   if (f32)
-    hipLaunchKernelGGL(k_lap_fill<float>, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
+    hipLaunchKernelGGL(k_lap_fill_rows<float>, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
                        fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
                        J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.w.as<float>(),
                        J.diag.as<double>(), n);
   else
-    hipLaunchKernelGGL(k_lap_fill<double>, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
+    hipLaunchKernelGGL(k_lap_fill_rows<double>, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(),
                        fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
                        J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.w.as<double>(),
                        J.diag.as<double>(), n);
