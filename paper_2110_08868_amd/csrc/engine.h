@@ -276,7 +276,7 @@ void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp,
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
 
 struct PcgWork {
-  DevBuf r, z, p, q, dinv, part, scal;
+  DevBuf r, z, p, q, s, dinv, part, part2, scal;
 };
 // Solve J x = b - mean(b) with Jacobi-preconditioned CG to
 // ||r|| <= rtol ||b - mean(b)||; x is overwritten (mean zero on return).  It

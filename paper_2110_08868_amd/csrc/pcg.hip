@@ -17,7 +17,7 @@ constexpr int MAXB = 1024;       // blocks of the grid-stride vector kernels
 constexpr int SPMV_MAXB = 8192;  // blocks of the SpMV (grid-stride over rows)
 
 // scalar slots (device doubles)
-enum { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6 };
+enum { S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6 };
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum_d(v);
@@ -107,38 +107,80 @@ __global__ __launch_bounds__(TPB) void k_final(const double* __restrict__ part, 
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_update(double* __restrict__ x, double* __restrict__ r,
-                                                double* __restrict__ z, const double* __restrict__ p,
-                                                const double* __restrict__ q,
-                                                const double* __restrict__ dinv,
-                                                const double* __restrict__ scal, int rz_cur,
-                                                double* __restrict__ part, int64_t n) {
+// One step of CG in the Chronopoulos-Gear form (one reduction phase per
+// iteration): p = u + beta p, s = w + beta s (s = J p kept by recurrence),
+// x += alpha p, r -= alpha s, u = dinv r; partials of r.u and r.r.
+__global__ __launch_bounds__(TPB) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ u, double* __restrict__ p,
+                                                   double* __restrict__ s, const double* __restrict__ w,
+                                                   const double* __restrict__ dinv,
+                                                   const double* __restrict__ scal, double* __restrict__ part,
+                                                   int64_t n) {
   __shared__ double sh[TPB / WAVE];
-  const double alpha = scal[rz_cur] / scal[S_PQ];
-  double arz = 0.0, arr = 0.0;
+  const double alpha = scal[S_ALPHA], beta = scal[S_BETA];
+  double aru = 0.0, arr = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
+    const double pi = u[i] + beta * p[i];
+    const double si = w[i] + beta * s[i];
+    p[i] = pi;
+    s[i] = si;
+    x[i] += alpha * pi;
+    const double ri = r[i] - alpha * si;
     r[i] = ri;
-    const double zi = dinv[i] * ri;
-    z[i] = zi;
-    arz += ri * zi;
+    const double ui = dinv[i] * ri;
+    u[i] = ui;
+    aru += ri * ui;
     arr += ri * ri;
   }
-  arz = block_sum(arz, sh);
+  aru = block_sum(aru, sh);
   arr = block_sum(arr, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = arz;
+    part[2 * blockIdx.x] = aru;
     part[2 * blockIdx.x + 1] = arr;
   }
 }
 
-__global__ __launch_bounds__(TPB) void k_pupdate(double* __restrict__ p, const double* __restrict__ z,
-                                                 const double* __restrict__ scal, int rz_new, int rz_old,
-                                                 int64_t n) {
-  const double beta = scal[rz_new] / scal[rz_old];
-  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB)
-    p[i] = z[i] + beta * p[i];
+// gamma' = r.u, rr = r.r (from the update's partials), delta = w.u (from the
+// SpMV's); beta = gamma' / gamma, alpha = gamma' / (delta - beta gamma' /
+// alpha) (first: beta = 0, alpha = gamma' / delta).  Fixed tree, one block.
+constexpr int SCAL_TPB = 1024;
+__global__ __launch_bounds__(SCAL_TPB) void k_cg_scalars(const double* __restrict__ pu, int nu,
+                                                         const double* __restrict__ ps, int nsp,
+                                                         double* __restrict__ scal, int first) {
+  __shared__ double sh[3][SCAL_TPB / WAVE];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = threadIdx.x; i < nu; i += SCAL_TPB) {
+    a += pu[2 * i];
+    b += pu[2 * i + 1];
+  }
+  for (int i = threadIdx.x; i < nsp; i += SCAL_TPB) c += ps[i];
+  a = wave_sum_d(a);
+  b = wave_sum_d(b);
+  c = wave_sum_d(c);
+  if (lane_id() == 0) {
+    sh[0][threadIdx.x / WAVE] = a;
+    sh[1][threadIdx.x / WAVE] = b;
+    sh[2][threadIdx.x / WAVE] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = b = c = 0.0;
+    for (int k = 0; k < SCAL_TPB / WAVE; ++k) {
+      a += sh[0][k];
+      b += sh[1][k];
+      c += sh[2][k];
+    }
+    const double gn = a;
+    double beta = 0.0, den = c;
+    if (!first) {
+      beta = scal[S_GAMMA] > 0.0 ? gn / scal[S_GAMMA] : 0.0;
+      den = c - (scal[S_ALPHA] != 0.0 ? beta * gn / scal[S_ALPHA] : 0.0);
+    }
+    scal[S_ALPHA] = den > 0.0 ? gn / den : 0.0;
+    scal[S_BETA] = beta;
+    scal[S_GAMMA] = gn;
+    scal[S_RR] = b;
+  }
 }
 
 __global__ void k_diag_inv(const double* __restrict__ diag, double* __restrict__ dinv, int64_t n) {
@@ -158,57 +200,35 @@ __global__ __launch_bounds__(TPB) void k_sum_part(const double* __restrict__ x, 
   if (threadIdx.x == 0) part[blockIdx.x] = a;
 }
 
-// r = b - mean; x = 0; z = dinv r; p = z; partials of r.z and r.r
-__global__ __launch_bounds__(TPB) void k_init(const double* __restrict__ b, const double* __restrict__ scal,
-                                              double* __restrict__ x, double* __restrict__ r,
-                                              double* __restrict__ z, double* __restrict__ p,
-                                              const double* __restrict__ dinv, double* __restrict__ part,
-                                              int64_t n) {
+// r = b - mean (- q = J x when warm; else x = 0); u = dinv r; p = s = 0;
+// partials of r.u and r.r
+__global__ __launch_bounds__(TPB) void k_cg_init(const double* __restrict__ b, const double* __restrict__ scal,
+                                                 const double* __restrict__ q, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ u,
+                                                 double* __restrict__ p, double* __restrict__ s,
+                                                 const double* __restrict__ dinv, double* __restrict__ part,
+                                                 int64_t n) {
   __shared__ double sh[TPB / WAVE];
   const double mean = scal[S_MEAN] / double(n);
-  double arz = 0.0, arr = 0.0;
+  double aru = 0.0, arr = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
-    const double ri = b[i] - mean;
+    double ri = b[i] - mean;
+    if (q)
+      ri -= q[i];
+    else
+      x[i] = 0.0;
     r[i] = ri;
-    x[i] = 0.0;
-    const double zi = dinv[i] * ri;
-    z[i] = zi;
-    p[i] = zi;
-    arz += ri * zi;
+    const double ui = dinv[i] * ri;
+    u[i] = ui;
+    p[i] = 0.0;
+    s[i] = 0.0;
+    aru += ri * ui;
     arr += ri * ri;
   }
-  arz = block_sum(arz, sh);
+  aru = block_sum(aru, sh);
   arr = block_sum(arr, sh);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = arz;
-    part[2 * blockIdx.x + 1] = arr;
-  }
-}
-
-// warm start from x: r = b - mean - J x (q holds J x); z = dinv r; p = z;
-// partials of r.z and r.r
-__global__ __launch_bounds__(TPB) void k_init_warm(const double* __restrict__ b,
-                                                   const double* __restrict__ scal,
-                                                   const double* __restrict__ q, double* __restrict__ r,
-                                                   double* __restrict__ z, double* __restrict__ p,
-                                                   const double* __restrict__ dinv,
-                                                   double* __restrict__ part, int64_t n) {
-  __shared__ double sh[TPB / WAVE];
-  const double mean = scal[S_MEAN] / double(n);
-  double arz = 0.0, arr = 0.0;
-  for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
-    const double ri = b[i] - mean - q[i];
-    r[i] = ri;
-    const double zi = dinv[i] * ri;
-    z[i] = zi;
-    p[i] = zi;
-    arz += ri * zi;
-    arr += ri * ri;
-  }
-  arz = block_sum(arz, sh);
-  arr = block_sum(arr, sh);
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = arz;
+    part[2 * blockIdx.x] = aru;
     part[2 * blockIdx.x + 1] = arr;
   }
 }
@@ -242,77 +262,75 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
   w.z.ensure(size_t(n) * sizeof(double));
   w.p.ensure(size_t(n) * sizeof(double));
   w.q.ensure(size_t(n) * sizeof(double));
+  w.s.ensure(size_t(n) * sizeof(double));
   w.dinv.ensure(size_t(n) * sizeof(double));
   const unsigned nbs = spmv_blocks(n);
-  w.part.ensure(size_t(std::max<int64_t>(2 * MAXB, nbs) + 16) * sizeof(double));
+  w.part.ensure(size_t(2 * MAXB + 16) * sizeof(double));
+  w.part2.ensure(size_t(nbs + 16) * sizeof(double));
   w.scal.ensure(16 * sizeof(double));
   double* r = w.r.as<double>();
-  double* z = w.z.as<double>();
+  double* u = w.z.as<double>();   // preconditioned residual
   double* p = w.p.as<double>();
-  double* q = w.q.as<double>();
+  double* wv = w.q.as<double>();  // J u
+  double* sv = w.s.as<double>();  // J p
   double* dinv = w.dinv.as<double>();
   double* part = w.part.as<double>();
+  double* part2 = w.part2.as<double>();
   double* scal = w.scal.as<double>();
   const unsigned nb = vec_blocks(n);
   const unsigned nbe = unsigned(ceil_div(n, 256));
 
-  auto spmv = [&](const double* pv, double* qv) {
+  // q = J v with the partials of q . v in part2
+  auto spmv = [&](const double* v, double* qv) {
+    // compulsory bytes: row_ptr, diagonal, v (own row), q, and per nonzero
+    // col + weight; flops 2 per nonzero + the diagonal and the dot
+    const double wb = J.f32 ? 4.0 : 8.0;
+    ProfScope ps("spmv", st, double(n), 32.0 * double(n) + (4.0 + wb) * double(J.nnz));
+    ps.flops = 2.0 * double(J.nnz) + 4.0 * double(n);
     if (J.f32)
       hipLaunchKernelGGL(k_spmv_dot<float>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
-                         J.col.as<int32_t>(), J.w.as<float>(), J.diag.as<double>(), pv, qv, part, n);
+                         J.col.as<int32_t>(), J.w.as<float>(), J.diag.as<double>(), v, qv, part2, n);
     else
       hipLaunchKernelGGL(k_spmv_dot<double>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
-                         J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), pv, qv, part, n);
+                         J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), v, qv, part2, n);
   };
   hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.diag.as<double>(), dinv, n);
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, b, part, n);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_MEAN), 0);
+  hipLaunchKernelGGL(k_sq_part, dim3(nb), dim3(TPB), 0, st, b, scal, part, n);
+  hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_BB), 0);
   double hb[8];
   if (warm) {
     // start from the given x: r0 = b - J x; kept only if |r0| < |b|
-    hipLaunchKernelGGL(k_sq_part, dim3(nb), dim3(TPB), 0, st, b, scal, part, n);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_BB), 0);
-    spmv(x, q);
-    hipLaunchKernelGGL(k_init_warm, dim3(nb), dim3(TPB), 0, st, b, scal, q, r, z, p, dinv, part, n);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_RZ0), int(S_RR));
+    spmv(x, wv);
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(TPB), 0, st, b, scal, wv, x, r, u, p, sv, dinv, part, n);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_TMP), int(S_RR));
     MAK_HIP(hipGetLastError());
     MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
     MAK_HIP(hipStreamSynchronize(st));
     if (!(hb[S_RR] < hb[S_BB])) warm = false;
   }
-  if (!warm) {
-    hipLaunchKernelGGL(k_init, dim3(nb), dim3(TPB), 0, st, b, scal, x, r, z, p, dinv, part, n);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_RZ0), int(S_BB));
-    MAK_HIP(hipGetLastError());
-    MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
-    MAK_HIP(hipStreamSynchronize(st));
-  }
+  if (!warm)
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(TPB), 0, st, b, scal, nullptr, x, r, u, p, sv, dinv, part,
+                       n);
+  spmv(u, wv);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 1);
+  MAK_HIP(hipGetLastError());
+  MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
   const double bb = hb[S_BB];
   if (!(bb > 0.0)) return 0;
   const double stop = rtol * rtol * bb;
+  if (hb[S_RR] <= stop) return 0;
   int it = 0;
   for (; it < max_iter; ++it) {
-    const int cur = (it & 1) ? S_RZ1 : S_RZ0, nxt = (it & 1) ? S_RZ0 : S_RZ1;
     {
-      // compulsory bytes: row_ptr, diagonal, p (own row), q, and per nonzero
-      // col + weight; flops 2 per nonzero + the diagonal and the dot
-      const double wb = J.f32 ? 4.0 : 8.0;
-      ProfScope ps("spmv", st, double(n), 32.0 * double(n) + (4.0 + wb) * double(J.nnz));
-      ps.flops = 2.0 * double(J.nnz) + 4.0 * double(n);
-      if (J.f32)
-        hipLaunchKernelGGL(k_spmv_dot<float>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
-                           J.col.as<int32_t>(), J.w.as<float>(), J.diag.as<double>(), p, q, part, n);
-      else
-        hipLaunchKernelGGL(k_spmv_dot<double>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
-                           J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), p, q, part, n);
+      ProfScope ps("pcg_update", st, double(n), 96.0 * double(n));
+      ps.flops = 14.0 * double(n);
+      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(TPB), 0, st, x, r, u, p, sv, wv, dinv, scal, part, n);
     }
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nbs), 1, scal, int(S_PQ), 0);
-    {
-      ProfScope ps("pcg_update", st, double(n), 72.0 * double(n));
-      ps.flops = 10.0 * double(n);
-      hipLaunchKernelGGL(k_update, dim3(nb), dim3(TPB), 0, st, x, r, z, p, q, dinv, scal, cur, part, n);
-    }
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, nxt, int(S_RR));
+    spmv(u, wv);
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 0);
     if ((it & 7) == 7 || it + 1 == max_iter) {
       double rr = 0;
       MAK_HIP(hipMemcpyAsync(&rr, scal + S_RR, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -322,7 +340,6 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
         break;
       }
     }
-    hipLaunchKernelGGL(k_pupdate, dim3(nb), dim3(TPB), 0, st, p, z, scal, nxt, cur, n);
   }
   MAK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, x, part, n);
