@@ -73,6 +73,12 @@ __device__ __forceinline__ double wrap_coord(double v, double L) {
   return v;
 }
 
+// Half the squared length of d minus w, with explicit fused operations so
+// that every kernel gets the same bits for the same candidate.
+__device__ __forceinline__ double power_dist(double dx, double dy, double dz, double w) {
+  return 0.5 * __fma_rn(dx, dx, __fma_rn(dy, dy, dz * dz)) - w;
+}
+
 // floor(u / n) for a cell or block coordinate u that may lie outside [0, n)
 __device__ __forceinline__ int period_floor(int u, int n) { return u >= 0 ? u / n : -((n - 1 - u) / n); }
 
@@ -108,7 +114,7 @@ __device__ __forceinline__ LocHit locate_one(const LocArgs& A, double qx, double
     for (int32_t k = s0; k < s1; ++k) {
       const double4 p = A.pts[k];
       const double dx = p.x + sx - qx, dy = p.y + sy - qy, dz = p.z + sz - qz;
-      const double v = 0.5 * (dx * dx + dy * dy + dz * dz) - p.w;
+      const double v = power_dist(dx, dy, dz, p.w);
       if (v < best) {
         best = v;
         bk = k;
@@ -251,23 +257,16 @@ __device__ __forceinline__ int64_t wrap_index(int64_t i, int64_t n) {
   return i < 0 ? i + n : i;
 }
 
-// One thread per Lagrangian mass element (mesh node q): locate its cell,
-// move it to y = q + tau (x_i + kL - q), and add its U units to the
-// Eulerian nodes: all to the nearest node (NGP) or split over the 8 nodes
-// around y with the trilinear weights (CIC), rounded to units with the
+
+// Move the mass element at q by tau (its displacement) and add its U units
+// to the Eulerian nodes: all to the nearest node (NGP) or split over the 8
+// nodes around y with the trilinear weights (CIC), rounded to units with the
 // remainder on the heaviest node so each element adds exactly U.  Integer
 // sums are exact and independent of the order of the atomics.
-__global__ __launch_bounds__(kLocBlock) void k_deposit(LocArgs A, DepArgs D) {
-  const int64_t item = xcd_item(A.per_xcd);
-  if (item < 0) return;
-  int64_t a, b, c;
-  if (!mesh_node(item, A.ng, A.nb, a, b, c)) return;
-  const double qx = (double(a) + A.mesh_off) * A.mesh_h, qy = (double(b) + A.mesh_off) * A.mesh_h,
-               qz = (double(c) + A.mesh_off) * A.mesh_h;
-  const LocHit r = locate_one(A, qx, qy, qz);
-  const double L = A.L;
-  const double yx = wrap_coord(qx + D.tau * r.dx, L), yy = wrap_coord(qy + D.tau * r.dy, L),
-               yz = wrap_coord(qz + D.tau * r.dz, L);
+__device__ __forceinline__ void deposit_element(const DepArgs& D, double L, double qx, double qy, double qz,
+                                                double dx, double dy, double dz) {
+  const double yx = wrap_coord(qx + D.tau * dx, L), yy = wrap_coord(qy + D.tau * dy, L),
+               yz = wrap_coord(qz + D.tau * dz, L);
   const double ux = yx / D.H, uy = yy / D.H, uz = yz / D.H;
   const int64_t ne = D.ne;
   if (D.scheme == 1) {
@@ -308,6 +307,176 @@ __global__ __launch_bounds__(kLocBlock) void k_deposit(LocArgs A, DepArgs D) {
   }
 }
 
+// Mesh queries, one wavefront per 4 x 4 x 4 brick of nodes (a lane per
+// node): the lanes walk the same blocks together.  Around the box of blocks
+// that holds the brick the wave visits shells of blocks; each lane tests a
+// block with its own tilted bound, and when some lane needs it the wave
+// stages the block's cells that could serve any of the needing lanes (a
+// tilted bound over the box of their queries, against the largest of their
+// best values) into LDS, kStage sites at a time, and every lane evaluates
+// all staged sites.  A lane stops needing blocks at shell r under the same
+// test as the per-thread walk (every block at Chebyshev distance >= r from
+// its own block is out of reach); the walk ends when all lanes have
+// stopped.  The minimum is the same as the per-thread walk's (the same
+// candidate values, and a minimum does not depend on the order); only ties
+// may pick another site.  DEP: then deposit the element (Zel'dovich step).
+constexpr int kStage = 256;
+
+template <bool DEP>
+__global__ __launch_bounds__(64) void k_mesh_coop(LocArgs A, DepArgs D) {
+  __shared__ double4 site[kStage];
+  __shared__ int32_t sidx[kStage];
+  __shared__ int32_t cst[64], cpre[64];
+  const int lane = threadIdx.x;
+  const int64_t wg = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+  if ((wg >> 3) >= A.per_xcd) return;
+  const int64_t brick = (wg & 7) * A.per_xcd + (wg >> 3);
+  const int64_t nb = A.nb;
+  if (brick >= nb * nb * nb) return;
+  const int64_t a = 4 * (brick / (nb * nb)) + (lane >> 4);
+  const int64_t b = 4 * ((brick / nb) % nb) + ((lane >> 2) & 3);
+  const int64_t c = 4 * (brick % nb) + (lane & 3);
+  const bool valid = a < A.ng && b < A.ng && c < A.ng;
+  const double L = A.L, h = A.h, bh = BLOCK_SIDE * h;
+  const double q0x = (double(a) + A.mesh_off) * A.mesh_h, q0y = (double(b) + A.mesh_off) * A.mesh_h,
+               q0z = (double(c) + A.mesh_off) * A.mesh_h;
+  const double qx = wrap_coord(q0x, L), qy = wrap_coord(q0y, L), qz = wrap_coord(q0z, L);
+  const int Gn = A.Gn, Gb = A.Gb;
+  const double slack = 1e-12 * L * L;
+  const int bx0 = cell_coord(qx, h, Gn) >> 2, by0 = cell_coord(qy, h, Gn) >> 2, bz0 = cell_coord(qz, h, Gn) >> 2;
+  double mb = fmin(fmin(qx - bx0 * bh, (bx0 + 1) * bh - qx),
+                   fmin(fmin(qy - by0 * bh, (by0 + 1) * bh - qy), fmin(qz - bz0 * bh, (bz0 + 1) * bh - qz)));
+  mb = fmax(mb - 1e-9 * h, 0.0);
+  const double* suf = A.bsuf + block_key(bx0, by0, bz0, Gb) * (SHELL_MAX + 1);
+  const double gmax = A.scal[0];
+  // the box of blocks of the brick's nodes
+  const double big = 1e300;
+  const int Bx0 = int(-wave_max_d(valid ? -double(bx0) : -big)), Bx1 = int(wave_max_d(valid ? double(bx0) : -big));
+  const int By0 = int(-wave_max_d(valid ? -double(by0) : -big)), By1 = int(wave_max_d(valid ? double(by0) : -big));
+  const int Bz0 = int(-wave_max_d(valid ? -double(bz0) : -big)), Bz1 = int(wave_max_d(valid ? double(bz0) : -big));
+
+  double best = INFINITY, bdx = 0, bdy = 0, bdz = 0;
+  int32_t bk = -1;
+  bool done = !valid;
+  for (int r = 0; r <= Gb + 2; ++r) {
+    if (r > 0 && !done) {
+      bool stop = true;
+      for (int s2 = r; s2 <= SHELL_MAX && stop; ++s2) {
+        const double t = (s2 - 1) * bh + mb;
+        stop = 0.5 * t * t - suf[s2] - slack >= best;
+      }
+      if (stop) {
+        const double t = (max(r, SHELL_MAX + 1) - 1) * bh + mb;
+        stop = 0.5 * t * t - gmax - slack >= best;
+      }
+      done = stop;
+    }
+    if (ballot(!done) == 0) break;
+    const int x0 = Bx0 - r, x1 = Bx1 + r, y0 = By0 - r, y1 = By1 + r, z0 = Bz0 - r, z1 = Bz1 + r;
+    for (int ubx = x0; ubx <= x1; ++ubx) {
+      const bool xe = r == 0 || ubx == x0 || ubx == x1;
+      for (int uby = y0; uby <= y1; ++uby) {
+        const bool ye = xe || uby == y0 || uby == y1;
+        const int zstep = ye ? 1 : z1 - z0;
+        for (int ubz = z0; ubz <= z1; ubz += zstep) {
+          const int sx = period_floor(ubx, Gb), sy = period_floor(uby, Gb), sz = period_floor(ubz, Gb);
+          const int64_t bkey = block_key(ubx - sx * Gb, uby - sy * Gb, ubz - sz * Gb, Gb);
+          const double gx = A.bg[3 * bkey], gy = A.bg[3 * bkey + 1], gz = A.bg[3 * bkey + 2];
+          const double lx = ubx * bh, ly = uby * bh, lz = ubz * bh;
+          const double cx = lx + 0.5 * bh, cy = ly + 0.5 * bh, cz = lz + 0.5 * bh;
+          const double g2 = 0.5 * (gx * gx + gy * gy + gz * gz);
+          bool need = false;
+          if (!done) {
+            const double px = qx + gx, py = qy + gy, pz = qz + gz;
+            const double base = g2 + (gx * (qx - cx) + gy * (qy - cy) + gz * (qz - cz)) + slack;
+            const double dbx = fmax(fmax(lx - px, px - lx - bh), 0.0);
+            const double dby = fmax(fmax(ly - py, py - ly - bh), 0.0);
+            const double dbz = fmax(fmax(lz - pz, pz - lz - bh), 0.0);
+            need = 0.5 * (dbx * dbx + dby * dby + dbz * dbz) - base - A.btmax[bkey] < best;
+          }
+          if (ballot(need) == 0) continue;
+          // the box of the needing lanes' queries and their largest best
+          const double qlx = -wave_max_d(need ? -qx : -big), qhx = wave_max_d(need ? qx : -big);
+          const double qly = -wave_max_d(need ? -qy : -big), qhy = wave_max_d(need ? qy : -big);
+          const double qlz = -wave_max_d(need ? -qz : -big), qhz = wave_max_d(need ? qz : -big);
+          const double bmax = wave_max_d(need ? best : -big);
+          // cell `lane` of the block
+          const int ux = 4 * ubx + (lane >> 4), uy = 4 * uby + ((lane >> 2) & 3), uz = 4 * ubz + (lane & 3);
+          const int64_t key = bkey * 64 + lane;
+          const int32_t s0 = A.start[key], cnt = A.start[key + 1] - s0;
+          bool has = cnt > 0;
+          if (has) {
+            const double clx = ux * h, cly = uy * h, clz = uz * h;
+            const double gpx = fmax(fmax(clx - (qhx + gx), (qlx + gx) - clx - h), 0.0);
+            const double gpy = fmax(fmax(cly - (qhy + gy), (qly + gy) - cly - h), 0.0);
+            const double gpz = fmax(fmax(clz - (qhz + gz), (qlz + gz) - clz - h), 0.0);
+            const double gq = fmax(gx * (qlx - cx), gx * (qhx - cx)) + fmax(gy * (qly - cy), gy * (qhy - cy)) +
+                              fmax(gz * (qlz - cz), gz * (qhz - cz));
+            has = 0.5 * (gpx * gpx + gpy * gpy + gpz * gpz) - g2 - gq - A.ctmax[key] - slack < bmax;
+          }
+          const uint64_t am = ballot(has);
+          if (am == 0) continue;
+          const int ncl = __popcll(am);
+          const int cn = has ? cnt : 0;
+          const int incl = wave_incl_scan_i(cn);
+          const int total = readlane_i(incl, 63);
+          if (has) {
+            const int idx = lanes_below(am);
+            cst[idx] = s0;
+            cpre[idx] = incl - cn;
+          }
+          __syncthreads();
+          const double Lx = sx * L, Ly = sy * L, Lz = sz * L;
+          for (int base0 = 0; base0 < total; base0 += kStage) {
+            const int m = min(kStage, total - base0);
+            for (int t = lane; t < m; t += 64) {
+              const int tt = base0 + t;
+              int lo = 0, hi = ncl - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (cpre[mid] <= tt) lo = mid; else hi = mid - 1;
+              }
+              const int32_t k = cst[lo] + (tt - cpre[lo]);
+              const double4 P = A.pts[k];
+              site[t] = make_double4(P.x + Lx, P.y + Ly, P.z + Lz, P.w);
+              sidx[t] = k;
+            }
+            __syncthreads();
+            if (need) {
+              for (int t = 0; t < m; ++t) {
+                const double4 P = site[t];
+                const double dx = P.x - qx, dy = P.y - qy, dz = P.z - qz;
+                const double v = power_dist(dx, dy, dz, P.w);
+                if (v < best) {
+                  best = v;
+                  bk = sidx[t];
+                  bdx = dx;
+                  bdy = dy;
+                  bdz = dz;
+                }
+              }
+            }
+            __syncthreads();
+          }
+        }
+      }
+    }
+  }
+  if (!valid) return;
+  if (DEP) {
+    deposit_element(D, L, qx, qy, qz, bdx, bdy, bdz);
+  } else {
+    const int64_t out = (a * A.ng + b) * A.ng + c;
+    if (A.phi) A.phi[out] = best;
+    if (A.idx) A.idx[out] = bk >= 0 ? A.perm[bk] : -1;
+    if (A.disp) {
+      A.disp[3 * out] = bdx;
+      A.disp[3 * out + 1] = bdy;
+      A.disp[3 * out + 2] = bdz;
+    }
+  }
+}
+
 __global__ void k_units_to_density(const unsigned long long* __restrict__ acc, double scale,
                                    double* __restrict__ rho, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -343,6 +512,18 @@ void set_mesh(LocArgs& a, int64_t ng, double offset) {
   a.mesh_off = offset;
 }
 
+// Grid of one 64-lane workgroup per 4^3-node brick of the mesh, dealt to the
+// XCDs in contiguous ranges (2-D above 65536 workgroups).
+dim3 brick_grid(LocArgs& a) {
+  const int64_t bricks = a.nb * a.nb * a.nb;
+  a.per_xcd = ceil_div(bricks, 8);
+  const int64_t total = 8 * a.per_xcd;
+  const int64_t gx = total < 65536 ? total : 65536;
+  const int64_t gy = ceil_div(total, gx);
+  if (gy > 65535) MAK_FAIL(MAK_EINVAL, "mesh too large for one launch");
+  return dim3(unsigned(gx), unsigned(gy));
+}
+
 // Grid of `threads` items in workgroups of kLocBlock, dealt to the XCDs in
 // contiguous ranges (2-D above 65536 workgroups).
 dim3 xcd_grid(LocArgs& a, int64_t threads) {
@@ -376,12 +557,15 @@ void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, do
   }
   if (a.Q == 0) return;
   if (queries) MAK_HIP(hipMemsetAsync(a.status, 0, sizeof(int32_t), st));
-  const dim3 grid = xcd_grid(a, threads);
+  const dim3 grid = queries ? xcd_grid(a, threads) : brick_grid(a);
   ProfScope scope("locate", st, double(a.Q), double(a.Q) * (phi ? 8 : 0) + double(a.Q) * (idx ? 4 : 0) +
                                                  double(a.Q) * (disp ? 24 : 0) +
                                                  double(a.Q) * (queries ? 24 : 0) +
                                                  double(ps.N) * sizeof(double4));
-  hipLaunchKernelGGL(k_locate, grid, dim3(kLocBlock), 0, st, a);
+  if (queries)
+    hipLaunchKernelGGL(k_locate, grid, dim3(kLocBlock), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_mesh_coop<false>, grid, dim3(64), 0, st, a, DepArgs{});
   MAK_HIP(hipGetLastError());
   scope.stop();
   if (queries) {
@@ -396,7 +580,7 @@ void za_deposit(const PointSet& ps, double tau, int64_t n_lag, double lag_offset
                 double* density, DevBuf& acc, hipStream_t st) {
   LocArgs a = loc_args(ps);
   set_mesh(a, n_lag, lag_offset);
-  const dim3 grid = xcd_grid(a, a.nb * a.nb * a.nb * 64);
+  const dim3 grid = brick_grid(a);
   const int64_t n_e = ne * ne * ne;
   DepArgs d{};
   d.tau = tau;
@@ -414,7 +598,7 @@ void za_deposit(const PointSet& ps, double tau, int64_t n_lag, double lag_offset
   MAK_HIP(hipMemsetAsync(d.acc, 0, size_t(n_e) * sizeof(unsigned long long), st));
   {
     ProfScope scope("deposit", st, double(a.Q), double(ps.N) * sizeof(double4) + double(n_e) * 16);
-    hipLaunchKernelGGL(k_deposit, grid, dim3(kLocBlock), 0, st, a, d);
+    hipLaunchKernelGGL(k_mesh_coop<true>, grid, dim3(64), 0, st, a, d);
     MAK_HIP(hipGetLastError());
   }
   // element mass (L / n_lag)^3 over U units, per Eulerian cell volume H^3
