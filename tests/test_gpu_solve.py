@@ -170,3 +170,41 @@ def test_masses_rejected(ctx):
         assert e.value.name == "MAK_EINVAL"
     # the context is still usable
     gsolve(ctx, x, 1.0, 1e-6)
+
+
+# ------------------------------------------------------------- edge cases
+def test_single_and_two_sites(ctx):
+    """N = 1: the one cell is the whole box (no Newton step); N = 2 on a line
+    with unequal target masses: the closed-form layered solution."""
+    import torch
+    x1 = np.array([[0.3, 0.6, 0.9]])
+    psi, C, D, info = gsolve(ctx, x1, 1.0, 1e-12)
+    assert info["newton_iters"] == 0 and np.allclose(psi, 0.0)
+    from tests.closed_forms import layered_ot_psi
+    X = np.array([0.2, 0.55])
+    w = np.array([0.3, 0.7])
+    psi_l, _ = layered_ot_psi(X, 1.0, widths=w)
+    x2 = workloads.layered(X, 1, 1)
+    p2, C2, D2, info2 = ctx.solve(torch.from_numpy(x2), 1.0, 1e-12, masses=torch.from_numpy(w))
+    p2 = p2.cpu().numpy()
+    assert np.allclose(p2, psi_l - psi_l.mean(), atol=1e-12)
+
+
+def test_box_size_and_masses(ctx):
+    """L = 2.5, Zel'dovich 10^3: uniform masses and masses from a random weight
+    vector, both certified by the oracle's volumes at the returned weights."""
+    import torch
+    L, n = 2.5, 10
+    x = workloads.zeldovich(n, L=L, rms=0.5, smooth=1.0, seed=17)
+    psi, C, D, info = gsolve(ctx, x, L, 1e-9)
+    r = oracle.cells(x, psi, L)
+    m = L ** 3 / len(x)
+    assert np.max(np.abs(r["V"] - m)) / m <= 1e-9 * 1.001
+    rng = np.random.default_rng(17)
+    psi0 = rng.uniform(-1, 1, len(x)) * 0.03 * (L / n) ** 2
+    ms = oracle.cells(x, psi0, L)["V"]
+    p2, _, _, _ = ctx.solve(torch.from_numpy(x), L, 1e-9, masses=torch.from_numpy(ms))
+    p2 = p2.cpu().numpy()
+    r2 = oracle.cells(x, p2, L)
+    assert np.max(np.abs(r2["V"] - ms) / ms) <= 1e-9 * 1.001
+    assert np.allclose(p2, psi0 - psi0.mean(), atol=1e-8 * (L / n) ** 2)
