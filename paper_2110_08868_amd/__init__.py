@@ -1,5 +1,11 @@
 """MI355X semi-discrete optimal transport (MAK reconstruction hot path).
 
+Context: Laguerre cell passes (volumes, centroids, the Hessian and faces), the
+damped-Newton solve (uniform or per-site target masses), the Legendre
+transform of the weights on query points or a mesh, the Zel'dovich deposit
+of the cells' mass on an Eulerian mesh, and the power spectrum of a mesh
+field.  Server: many solves of different sizes on one device.
+
 Thin ctypes binding of libmak.so (include/mak.h): argument marshalling only.
 PyTorch provides the device memory and the stream; every step of the cell
 pass and of the Newton solve runs in the HIP kernels of the library.  There is
