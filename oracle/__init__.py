@@ -19,7 +19,9 @@ Contents
                          phi(q), the index of the Laguerre cell holding q,
                          and the transport displacement (brute force).
   za_deposit(...)        Zel'dovich advection of the cells' mass elements
-                         and their deposit on an Eulerian mesh.
+                         and their deposit on an Eulerian mesh;
+                         za_deposit_exact: the moved cells clipped against
+                         the voxels (the limit of many elements).
   power_spectrum(f, L)   shell-averaged power spectrum of a periodic mesh
                          field (FFT estimator, optional window and contrast).
   exact                  exact-rational mini oracle (Python fractions).
@@ -27,7 +29,7 @@ Contents
 from .cells import cells, cell_faces_dict, load_library
 from .legendre import legendre
 from .power import power_spectrum
-from .deposit import za_deposit
+from .deposit import za_deposit, za_deposit_exact
 from .newton import (
     hessian_dense,
     hessian_coo,
@@ -45,6 +47,7 @@ __all__ = [
     "legendre",
     "power_spectrum",
     "za_deposit",
+    "za_deposit_exact",
     "hessian_dense",
     "hessian_coo",
     "kantorovich",

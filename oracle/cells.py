@@ -30,6 +30,9 @@ def load_library():
     lib.oracle_fetch.argtypes = [P] * 12
     lib.oracle_free.restype = None
     lib.oracle_free.argtypes = [P]
+    lib.oracle_deposit_exact.restype = None
+    lib.oracle_deposit_exact.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int64, P, ctypes.c_int]
     _LIB = lib
     return lib
 

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .cells import _ptr, load_library
 from .legendre import legendre
 
 
@@ -53,3 +54,21 @@ def za_deposit(x, psi, L: float, tau: float, n_lag: int, ng: int, scheme: str = 
                     j = np.mod(i0 + np.array([dx, dy, dz]), ng)
                     np.add.at(rho, (j[:, 0] * ng + j[:, 1]) * ng + j[:, 2], m * w)
     return rho.reshape(ng, ng, ng) / H ** 3
+
+
+def za_deposit_exact(x, psi, L: float, tau: float, ng: int, threads: int = 0):
+    """Density (ng, ng, ng) of the moved cells themselves: each cell V_i
+    shrunk by 1 - tau towards x_i carries its mass |V_i| at density
+    1 / (1 - tau)^3; the mass in the voxel [a H - H/2, a H + H/2)^3 of node a
+    is the volume of the shrunk polytope inside it (the C++ cell oracle's
+    polytope, clipped against the six voxel planes).  tau < 1.  This is the
+    limit of za_deposit with scheme 'ngp' as n_lag grows."""
+    assert 0.0 <= tau < 1.0
+    x = np.mod(np.ascontiguousarray(x, dtype=np.float64), L)
+    x[x >= L] = 0.0
+    x = np.ascontiguousarray(x)
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    rho = np.zeros(ng ** 3)
+    load_library().oracle_deposit_exact(_ptr(x), _ptr(psi), x.shape[0], float(L), float(tau), int(ng),
+                                        _ptr(rho), int(threads))
+    return rho.reshape(ng, ng, ng)

@@ -35,7 +35,11 @@
  *      R + sqrt(R^2 + 2 max(0, psi_max - psi_i)) <= K L.  If that fails the
  *      cell is recomputed with K + 1.
  *
- * Build: g++ -O2 -std=c++17 -ffp-contract=off -shared -fPIC (see build.py).
+ * Also: the exact deposit of the cells moved by the Zel'dovich step onto an
+ * Eulerian mesh (each cell shrunk towards its site, clipped against the
+ * voxels it overlaps; oracle_deposit_exact).
+ *
+ * Build: g++ -O2 -std=c++17 -ffp-contract=off -shared -fPIC (oracle/build.py).
  */
 #include <algorithm>
 #include <atomic>
@@ -339,6 +343,52 @@ void compute_cell(const double* x, const double* psi, int64_t n, double L, doubl
   }
 }
 
+// Exact deposit of one moved cell (Zel'dovich step of the cell at growth
+// amplitude tau: the cell shrunk by 1 - tau towards its site, carrying the
+// cell's mass at density 1 / (1 - tau)^3) onto the voxels of the Eulerian
+// nodes a H (voxel [a H - H/2, a H + H/2) per axis): the shrunk polytope is
+// clipped against the six planes of every voxel its box overlaps.
+void deposit_cell(const CellOut& c, V3 xi, double L, double tau, int64_t ng, double* rho) {
+  if (c.faces.empty()) return;
+  const double sc = 1.0 - tau;
+  std::vector<Face> f0 = c.faces;
+  V3 lo{INFINITY, INFINITY, INFINITY}, hi{-INFINITY, -INFINITY, -INFINITY};
+  for (Face& f : f0) {
+    for (V3& v : f.poly) {
+      v = v * sc;
+      lo = V3{std::min(lo.x, v.x), std::min(lo.y, v.y), std::min(lo.z, v.z)};
+      hi = V3{std::max(hi.x, v.x), std::max(hi.y, v.y), std::max(hi.z, v.z)};
+    }
+    f.b *= sc;
+  }
+  const double H = L / double(ng);
+  const double w = 1.0 / (sc * sc * sc * H * H * H);
+  auto first = [H](double u) { return int64_t(std::floor((u + 0.5 * H) / H)); };
+  const int64_t a0 = first(xi.x + lo.x), a1 = first(xi.x + hi.x);
+  const int64_t b0 = first(xi.y + lo.y), b1 = first(xi.y + hi.y);
+  const int64_t c0 = first(xi.z + lo.z), c1 = first(xi.z + hi.z);
+  const int32_t s0[3] = {0, 0, 0};
+  auto wrap = [ng](int64_t k) { return ((k % ng) + ng) % ng; };
+  for (int64_t a = a0; a <= a1; ++a)
+    for (int64_t b = b0; b <= b1; ++b)
+      for (int64_t cc = c0; cc <= c1; ++cc) {
+        std::vector<Face> f = f0;
+        const V3 vl{a * H - 0.5 * H - xi.x, b * H - 0.5 * H - xi.y, cc * H - 0.5 * H - xi.z};
+        const V3 vh = vl + V3{H, H, H};
+        clip(f, V3{1, 0, 0}, vh.x, -1, s0);
+        if (!f.empty()) clip(f, V3{-1, 0, 0}, -vl.x, -1, s0);
+        if (!f.empty()) clip(f, V3{0, 1, 0}, vh.y, -1, s0);
+        if (!f.empty()) clip(f, V3{0, -1, 0}, -vl.y, -1, s0);
+        if (!f.empty()) clip(f, V3{0, 0, 1}, vh.z, -1, s0);
+        if (!f.empty()) clip(f, V3{0, 0, -1}, -vl.z, -1, s0);
+        if (f.empty()) continue;
+        CellOut t;
+        t.faces = std::move(f);
+        integrate(t);
+        rho[(wrap(a) * ng + wrap(b)) * ng + wrap(cc)] += t.V * w;
+      }
+}
+
 }  // namespace
 
 struct OracleResult {
@@ -407,5 +457,35 @@ void oracle_fetch(const OracleResult* r, double* V, double* M, double* S, double
 }
 
 void oracle_free(OracleResult* r) { delete r; }
+
+// Exact Eulerian deposit of all cells moved to growth amplitude tau < 1:
+// rho (ng^3, row-major) = mass per voxel / voxel volume.
+void oracle_deposit_exact(const double* x, const double* psi, int64_t n, double L, double tau, int64_t ng,
+                          double* rho, int nthreads) {
+  double psi_max = -INFINITY;
+  for (int64_t k = 0; k < n; ++k) psi_max = std::max(psi_max, psi[k]);
+  if (nthreads <= 0) nthreads = int(std::max(1u, std::thread::hardware_concurrency()));
+  const size_t nv = size_t(ng * ng * ng);
+  std::vector<std::vector<double>> acc(size_t(nthreads), std::vector<double>(nv, 0.0));
+  std::atomic<int64_t> next{0};
+  auto work = [&](int t) {
+    for (;;) {
+      const int64_t i = next.fetch_add(1);
+      if (i >= n) break;
+      CellOut c;
+      compute_cell(x, psi, n, L, psi_max, i, c);
+      deposit_cell(c, V3{x[3 * i], x[3 * i + 1], x[3 * i + 2]}, L, tau, ng, acc[size_t(t)].data());
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nthreads; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto& th : pool) th.join();
+  for (size_t v = 0; v < nv; ++v) {
+    double sum = 0.0;
+    for (int t = 0; t < nthreads; ++t) sum += acc[size_t(t)][v];
+    rho[v] = sum;
+  }
+}
 
 }  // extern "C"

@@ -630,3 +630,44 @@ def test_p11_deposit_layered_separable():
         assert np.allclose(r, ref, rtol=1e-13, atol=1e-13)
         errs.append(np.abs(r - exact).max())
     assert errs[1] < 0.7 * errs[0] and errs[1] < 0.5
+
+
+def test_p11_exact_deposit_pins():
+    """The exact deposit of the moved cells: density 1 at tau = 0 (the cells
+    tile the box), mass L^3 at any tau, the closed form of the layered slabs
+    (a product of three 1-D slab averages), and the element deposit (NGP)
+    approaching it at first order in the Lagrangian spacing."""
+    x, psi = _random_case(n=3, seed=83, wscale=0.03)
+    L = 1.0
+    assert np.allclose(oracle.za_deposit_exact(x, psi, L, 0.0, 5), 1.0, rtol=1e-12)
+    r = oracle.za_deposit_exact(x, psi, L, 0.6, 7)
+    assert r.sum() * (L / 7) ** 3 == pytest.approx(L ** 3, rel=1e-12)
+    # layered slabs: exact closed form
+    L, nl, ny, X, psi_l, b = _layer_setup()
+    xl = workloads.layered(X, ny, ny, L)
+    ng, tau = 8, 0.4
+    H = L / ng
+    lo = np.concatenate([[b[-1] - L], b[:-1]])
+    s = L / ny
+
+    def slab_avg(intervals):
+        out = np.zeros(ng)
+        for e in range(ng):
+            a0, a1 = e * H - H / 2, e * H + H / 2
+            for (u0, u1) in intervals:
+                for k in (-2, -1, 0, 1, 2):
+                    out[e] += max(0.0, min(a1, u1 + k * L) - max(a0, u0 + k * L))
+        return out / ((1 - tau) * H)
+
+    ex = slab_avg([(X[a] + (1 - tau) * (lo[a] - X[a]), X[a] + (1 - tau) * (b[a] - X[a])) for a in range(nl)])
+    ey = slab_avg([((k + 0.5) * s - (1 - tau) * s / 2, (k + 0.5) * s + (1 - tau) * s / 2) for k in range(ny)])
+    exact = ex[:, None, None] * ey[None, :, None] * ey[None, None, :]
+    r = oracle.za_deposit_exact(xl, np.repeat(psi_l, ny * ny), L, tau, ng)
+    assert np.allclose(r, exact, rtol=1e-11, atol=1e-12)
+    # elements -> cells
+    x = workloads.zeldovich(4, rms=0.5, smooth=1.0, seed=81)
+    psi = np.random.default_rng(81).uniform(-1, 1, 64) * 0.03 / 16
+    ex = oracle.za_deposit_exact(x, psi, 1.0, 0.5, 6)
+    e12 = np.abs(oracle.za_deposit(x, psi, 1.0, 0.5, 12, 6, scheme="ngp") - ex).mean()
+    e24 = np.abs(oracle.za_deposit(x, psi, 1.0, 0.5, 24, 6, scheme="ngp") - ex).mean()
+    assert e24 < 0.65 * e12
