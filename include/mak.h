@@ -238,6 +238,27 @@ mak_status mak_za_deposit(mak_ctx* ctx, const double* points, const double* psi,
                           double tau, int64_t n_lag, double lag_offset, int64_t ng, int32_t scheme,
                           double* density, void* stream);
 
+/* The deposit of the moved cells themselves (the limit of mak_za_deposit as
+ * n_lag grows): at growth amplitude tau the cell V_i becomes
+ * S_i = x_i + (1 - tau)(V_i - x_i), which carries the mass |V_i| at density
+ * 1 / (1 - tau)^3; the mass in the voxel [a H - H/2, a H + H/2)^3 of node a
+ * (H = L / ng) is the volume of S_i inside it over (1 - tau)^3, found by
+ * clipping polytopes in float64 (a cell pass with faces, then each cell
+ * clipped against the voxels it reaches).
+ *   points, psi  as for mak_legendre (psi NULL: all zero)
+ *   tau          in [0, 1)
+ *   ng           1..1024
+ *   density      DEVICE (ng, ng, ng) float64 out, row-major: mass / H^3 (mean 1)
+ * Masses are summed in 64-bit fixed point (unit L^3 2^-60, each cell-voxel
+ * part rounded to the nearest unit), so the result is the same bits on every
+ * run.  MAK_EDEGENERATE for coincident sites; MAK_EOVERFLOW if a cell has more
+ * than 122 faces, a clipped polytope more than 64 faces or a face more than
+ * 16 vertices, or a cut meets three points of one face in the plane (a
+ * degenerate configuration).  Holds the cell pass (about 600 bytes a site)
+ * and ng^3 x 8 bytes of scratch in the context. */
+mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
+                                double L, double tau, int64_t ng, double* density, void* stream);
+
 /* ---- power spectrum of a mesh field ----
  * The estimator behind the fractional spectra of Sec. BAO reconstruction,
  * for a field f on the periodic ng^3 mesh of side L (spacing H = L / ng):
@@ -270,7 +291,7 @@ mak_status mak_power_spectrum(mak_ctx* ctx, const double* field, int64_t ng, dou
  * separate runs). */
 typedef struct {
   char name[32];       /* "clip", "clip_large", "spmv", "pcg_update", "pcg_solve",
-                          "csr_assembly", "grid_build", "locate", "deposit", "fft", "shell_bin" */
+                          "csr_assembly", "grid_build", "locate", "deposit", "cells_deposit", "fft", "shell_bin" */
   int64_t launches;
   double total_ms;     /* summed event durations */
   double units;        /* work items processed (cells, rows) */

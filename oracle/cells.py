@@ -32,7 +32,7 @@ def load_library():
     lib.oracle_free.argtypes = [P]
     lib.oracle_deposit_exact.restype = None
     lib.oracle_deposit_exact.argtypes = [P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
-                                         ctypes.c_int64, P, ctypes.c_int]
+                                         ctypes.c_int64, P, ctypes.c_int64, P, ctypes.c_int]
     _LIB = lib
     return lib
 

@@ -56,19 +56,23 @@ def za_deposit(x, psi, L: float, tau: float, n_lag: int, ng: int, scheme: str = 
     return rho.reshape(ng, ng, ng) / H ** 3
 
 
-def za_deposit_exact(x, psi, L: float, tau: float, ng: int, threads: int = 0):
+def za_deposit_exact(x, psi, L: float, tau: float, ng: int, threads: int = 0, idx=None):
     """Density (ng, ng, ng) of the moved cells themselves: each cell V_i
     shrunk by 1 - tau towards x_i carries its mass |V_i| at density
     1 / (1 - tau)^3; the mass in the voxel [a H - H/2, a H + H/2)^3 of node a
     is the volume of the shrunk polytope inside it (the C++ cell oracle's
     polytope, clipped against the six voxel planes).  tau < 1.  This is the
-    limit of za_deposit with scheme 'ngp' as n_lag grows."""
+    limit of za_deposit with scheme 'ngp' as n_lag grows.  idx: deposit only
+    these cells (all by default)."""
     assert 0.0 <= tau < 1.0
     x = np.mod(np.ascontiguousarray(x, dtype=np.float64), L)
     x[x >= L] = 0.0
     x = np.ascontiguousarray(x)
     psi = np.ascontiguousarray(psi, dtype=np.float64)
     rho = np.zeros(ng ** 3)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
     load_library().oracle_deposit_exact(_ptr(x), _ptr(psi), x.shape[0], float(L), float(tau), int(ng),
+                                        None if idx is None else _ptr(idx), 0 if idx is None else len(idx),
                                         _ptr(rho), int(threads))
     return rho.reshape(ng, ng, ng)

@@ -458,10 +458,12 @@ void oracle_fetch(const OracleResult* r, double* V, double* M, double* S, double
 
 void oracle_free(OracleResult* r) { delete r; }
 
-// Exact Eulerian deposit of all cells moved to growth amplitude tau < 1:
-// rho (ng^3, row-major) = mass per voxel / voxel volume.
+// Exact Eulerian deposit of the cells moved to growth amplitude tau < 1:
+// rho (ng^3, row-major) = mass per voxel / voxel volume, over every cell, or
+// over the cells idx[0..nidx) when idx is not NULL.
 void oracle_deposit_exact(const double* x, const double* psi, int64_t n, double L, double tau, int64_t ng,
-                          double* rho, int nthreads) {
+                          const int64_t* idx, int64_t nidx, double* rho, int nthreads) {
+  const int64_t ncell = idx ? nidx : n;
   double psi_max = -INFINITY;
   for (int64_t k = 0; k < n; ++k) psi_max = std::max(psi_max, psi[k]);
   if (nthreads <= 0) nthreads = int(std::max(1u, std::thread::hardware_concurrency()));
@@ -470,8 +472,9 @@ void oracle_deposit_exact(const double* x, const double* psi, int64_t n, double 
   std::atomic<int64_t> next{0};
   auto work = [&](int t) {
     for (;;) {
-      const int64_t i = next.fetch_add(1);
-      if (i >= n) break;
+      const int64_t k = next.fetch_add(1);
+      if (k >= ncell) break;
+      const int64_t i = idx ? idx[k] : k;
       CellOut c;
       compute_cell(x, psi, n, L, psi_max, i, c);
       deposit_cell(c, V3{x[3 * i], x[3 * i + 1], x[3 * i + 2]}, L, tau, ng, acc[size_t(t)].data());

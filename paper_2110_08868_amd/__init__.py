@@ -3,8 +3,9 @@
 Context: Laguerre cell passes (volumes, centroids, the Hessian and faces), the
 damped-Newton solve (uniform or per-site target masses), the Legendre
 transform of the weights on query points or a mesh, the Zel'dovich deposit
-of the cells' mass on an Eulerian mesh, and the power spectrum of a mesh
-field.  Server: many solves of different sizes on one device.
+of the cells' mass on an Eulerian mesh (by Lagrangian elements, or exactly,
+by clipping the moved cells against the voxels), and the power spectrum of
+a mesh field.  Server: many solves of different sizes on one device.
 
 Thin ctypes binding of libmak.so (include/mak.h): argument marshalling only.
 PyTorch provides the device memory and the stream; every step of the cell
@@ -28,7 +29,8 @@ EXPORTED_SYMBOLS = [
     "mak_default_options", "mak_create", "mak_destroy", "mak_last_error",
     "mak_laguerre_cells", "mak_hessian_copy", "mak_faces_copy", "mak_solve",
     "mak_solve_masses", "mak_solve_from", "mak_solve_memory_estimate", "mak_legendre",
-    "mak_legendre_mesh", "mak_power_spectrum", "mak_za_deposit", "mak_profile_enable", "mak_profile_read",
+    "mak_legendre_mesh", "mak_power_spectrum", "mak_za_deposit", "mak_za_deposit_cells",
+    "mak_profile_enable", "mak_profile_read",
     "mak_profile_counters", "mak_server_create", "mak_server_submit", "mak_server_poll",
     "mak_server_wait", "mak_server_release", "mak_server_stats", "mak_server_last_error",
     "mak_server_destroy",
@@ -135,6 +137,8 @@ def load_library():
     lib.mak_solve.restype = ctypes.c_int
     lib.mak_za_deposit.argtypes = [P, P, P, I64, D, D, I64, D, I64, ctypes.c_int32, P, P]
     lib.mak_za_deposit.restype = ctypes.c_int
+    lib.mak_za_deposit_cells.argtypes = [P, P, P, I64, D, D, I64, P, P]
+    lib.mak_za_deposit_cells.restype = ctypes.c_int
     lib.mak_power_spectrum.argtypes = [P, P, I64, D, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        P, P, P, P]
     lib.mak_power_spectrum.restype = ctypes.c_int
@@ -360,6 +364,20 @@ class Context:
         st = self.lib.mak_za_deposit(self._h, x.data_ptr(), None if w is None else w.data_ptr(),
                                      x.shape[0], float(L), float(tau), int(n_lag), float(lag_offset),
                                      int(ng), sch, rho.data_ptr(), self._stream())
+        self._check(st)
+        return rho
+
+    def za_deposit_cells(self, points, psi, L: float, tau: float, ng: int):
+        """Density (ng, ng, ng) of the cells themselves moved to growth
+        amplitude tau < 1: each cell shrunk by 1 - tau towards its site and
+        clipped against the voxels (the limit of za_deposit as n_lag grows)."""
+        torch = _torch()
+        x = self._dev(points, (3,))
+        w = None if psi is None else self._dev(psi)
+        rho = torch.empty((int(ng),) * 3, dtype=torch.float64, device=self.device)
+        st = self.lib.mak_za_deposit_cells(self._h, x.data_ptr(), None if w is None else w.data_ptr(),
+                                           x.shape[0], float(L), float(tau), int(ng), rho.data_ptr(),
+                                           self._stream())
         self._check(st)
         return rho
 

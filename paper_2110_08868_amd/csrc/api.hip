@@ -124,6 +124,7 @@ struct mak_ctx {
   // Legendre transform / point location
   PointSet lps;
   DevBuf lstatus, dep_acc;
+  CellPass dcp;  // cell pass of the exact deposit
   // power spectrum
   PowerWork pk;
   Profiler prof;
@@ -341,6 +342,27 @@ mak_status mak_za_deposit(mak_ctx* ctx, const double* points, const double* psi,
     hipStream_t st = static_cast<hipStream_t>(stream);
     build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
     za_deposit(ctx->lps, tau, n_lag, lag_offset, ng, scheme, density, ctx->dep_acc, st);
+  });
+}
+
+mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
+                                double L, double tau, int64_t ng, double* density, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    check_args(N, L);
+    if (!points || !density) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    if (!(tau >= 0.0 && tau < 1.0)) MAK_FAIL(MAK_EINVAL, "tau must be in [0, 1)");
+    if (ng < 1 || ng > 1024) MAK_FAIL(MAK_EINVAL, "ng must be in [1, 1024]");
+    set_device(ctx);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
+    PassOpts po;
+    po.precision = MAK_FP64;
+    ClipStats cs = run_cells(ctx->lps, ctx->dcp, po, st);
+    (void)cs;
+    FlagStats fs = flag_stats(ctx->lps, ctx->dcp, ctx->tmp, st);
+    if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
+    za_deposit_cells(ctx->lps, ctx->dcp, tau, ng, density, ctx->dep_acc, ctx->lstatus, st);
   });
 }
 

@@ -251,6 +251,16 @@ void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, do
 void za_deposit(const PointSet& ps, double tau, int64_t n_lag, double lag_offset, int64_t ne, int scheme,
                 double* density, DevBuf& acc, hipStream_t st);
 
+// --- cells_deposit.hip
+// Exact deposit of the cells moved to growth amplitude tau in [0, 1): each
+// cell of the pass `cp` (float64, with faces, at the weights in ps) shrunk by
+// 1 - tau towards its site, clipped against the voxels of the ng^3 mesh
+// (nodes (a, b, c) L / ng); density (ng^3, mean 1) = mass / voxel volume.
+// acc: scratch of ng^3 uint64; status: 4 bytes.  Throws MAK_EOVERFLOW when a
+// polytope exceeds the kernel's capacity.
+void za_deposit_cells(const PointSet& ps, const CellPass& cp, double tau, int64_t ng, double* density,
+                      DevBuf& acc, DevBuf& status, hipStream_t st);
+
 // --- power.hip
 // Shell-averaged power spectrum of a field on the periodic ng^3 mesh; the
 // FFT plan (for the last ng) and the buffers are kept between calls.

@@ -1,0 +1,129 @@
+"""GPU exact deposit of the moved cells (mak_za_deposit_cells) against the
+oracle's exact deposit (the oracle's cell polytopes shrunk towards their
+sites and clipped against the voxels).
+
+Both sides compute the same volumes in float64 by different clipping orders
+(the GPU clips each voxel box by the cell's planes, the oracle clips the
+cell's polytope by the voxel planes), so they agree to rounding: relative
+1e-13 of a cell's volume per voxel part.  The GPU adds each part in fixed
+point (unit L^3 2^-60, rounding at most half a unit) and drops faces of area
+below 1e-12 of the squared site spacing (a volume change of that relative
+order), hence the absolute density tolerance 1e-10 (densities are O(1)-O(100))."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2110_08868_amd as mak
+    c = mak.Context(0)
+    yield c
+    c.close()
+
+
+def gcells(ctx, x, psi, L, tau, ng):
+    import torch
+    r = ctx.za_deposit_cells(torch.from_numpy(np.ascontiguousarray(x)),
+                             None if psi is None else torch.from_numpy(np.ascontiguousarray(psi)), L, tau, ng)
+    return r.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,tau,ng,L,seed", [
+    (3, 0.5, 6, 1.0, 81), (4, 0.0, 5, 1.0, 5), (4, 0.8, 7, 2.0, 9), (5, 0.35, 8, 1.0, 11),
+    (4, 0.95, 3, 1.0, 13), (6, 0.6, 11, 3.0, 15), (4, 0.5, 1, 1.0, 17)])
+def test_vs_oracle(ctx, n, tau, ng, L, seed):
+    x = np.mod(workloads.zeldovich(n, rms=0.5, smooth=1.0, seed=seed) * L, L)
+    psi = np.random.default_rng(seed).uniform(-1, 1, len(x)) * 0.03 * (L / n) ** 2
+    print(f"  n={n}^3 tau={tau} ng={ng} L={L} seed={seed}", flush=True)
+    r = gcells(ctx, x, psi, L, tau, ng)
+    o = oracle.za_deposit_exact(x, psi, L, tau, ng)
+    err = np.abs(r - o).max()
+    print(f"    max |drho| = {err:.2e}", flush=True)
+    assert err <= TOL
+    assert r.sum() / ng ** 3 == pytest.approx(1.0, rel=1e-12)
+
+
+def test_single_site_and_clustered(ctx):
+    """One site (the cell is the whole box, moved it is the box shrunk by
+    1 - tau), and a clustered set with near-empty cells."""
+    x = np.array([[0.3, 0.6, 0.1]])
+    r = gcells(ctx, x, None, 1.0, 0.3, 4)
+    o = oracle.za_deposit_exact(x, np.zeros(1), 1.0, 0.3, 4)
+    assert np.abs(r - o).max() <= TOL
+    L = 2.0
+    x = workloads.clustered(8, L=L, seed=85)
+    psi = np.random.default_rng(85).uniform(-1, 1, len(x)) * 0.02 * (L / 8) ** 2
+    print(f"  clustered 8^3 L={L}", flush=True)
+    r = gcells(ctx, x, psi, L, 0.7, 9)
+    o = oracle.za_deposit_exact(x, psi, L, 0.7, 9)
+    assert np.abs(r - o).max() <= TOL
+    x = workloads.clustered(12, seed=86)
+    psi = np.random.default_rng(86).uniform(-1, 1, len(x)) * 0.05 / 12 ** 2
+    print("  clustered 12^3 L=1", flush=True)
+    r = gcells(ctx, x, psi, 1.0, 0.5, 16)
+    o = oracle.za_deposit_exact(x, psi, 1.0, 0.5, 16)
+    assert np.abs(r - o).max() <= TOL
+
+
+def test_element_deposit_converges_to_it(ctx):
+    """The element deposit (NGP) approaches the exact one as n_lag grows."""
+    import torch
+    x = workloads.zeldovich(4, rms=0.5, smooth=1.0, seed=87)
+    psi = np.random.default_rng(87).uniform(-1, 1, 64) * 0.03 / 16
+    ex = gcells(ctx, x, psi, 1.0, 0.5, 6)
+    errs = []
+    for n_lag in (16, 32, 64, 128):
+        r = ctx.za_deposit(torch.from_numpy(x), torch.from_numpy(psi), 1.0, 0.5, n_lag, 6, "ngp").cpu().numpy()
+        errs.append(float(np.abs(r - ex).mean()))
+    print(f"  mean |rho_elements - rho_cells| for n_lag 16..128: {errs}", flush=True)
+    for k in range(3):
+        assert errs[k + 1] < 0.7 * errs[k]
+
+
+def test_full_size_at_solution(ctx):
+    """Clustered 128^3 (2.1 M sites) at its solved weights on a 128^3 mesh.
+    At tau = 0 the cells tile the torus, so every voxel is exactly covered:
+    density 1 in every voxel (a piece of a cell lost or counted twice
+    anywhere would show).  At tau = 0.5 the mass is conserved and a second
+    run gives the same bits."""
+    import time
+    import torch
+    import paper_2110_08868_amd as mak
+    n = 128
+    x = workloads.clustered(n, rms=3.0, smooth=1.0, frac=0.2, n_clumps=2000, a=0.5, seed=3)
+    sctx = mak.Context(0, "mixed", cg_rtol=1e-3)
+    xd = torch.from_numpy(x).cuda()
+    psi_d, _, _, _ = sctx.solve(xd, 1.0, 1e-6)
+    sctx.close()
+    t0 = time.time()
+    r0 = ctx.za_deposit_cells(xd, psi_d, 1.0, 0.0, n).cpu().numpy()
+    print(f"  tau 0: {time.time() - t0:.2f} s, max |rho - 1| = {np.abs(r0 - 1).max():.2e}", flush=True)
+    assert np.abs(r0 - 1.0).max() <= TOL
+    r = ctx.za_deposit_cells(xd, psi_d, 1.0, 0.5, n).cpu().numpy()
+    r2 = ctx.za_deposit_cells(xd, psi_d, 1.0, 0.5, n).cpu().numpy()
+    print(f"  tau 0.5: rho range {r.min():.3f}..{r.max():.1f}", flush=True)
+    assert np.array_equal(r, r2)
+    assert r.sum() / n ** 3 == pytest.approx(1.0, rel=1e-12)
+
+
+def test_errors(ctx):
+    import torch
+    import paper_2110_08868_amd as mak
+    x = torch.from_numpy(workloads.zeldovich(4, rms=0.3, smooth=1.0, seed=89))
+    for tau, ng in ((1.0, 8), (-0.1, 8), (0.5, 0), (0.5, 1025), (float("nan"), 8)):
+        with pytest.raises(mak.MakError) as e:
+            ctx.za_deposit_cells(x, None, 1.0, tau, ng)
+        assert e.value.name == "MAK_EINVAL"
+    xc = x.clone()
+    xc[5] = xc[9]
+    with pytest.raises(mak.MakError) as e:
+        ctx.za_deposit_cells(xc, None, 1.0, 0.5, 8)
+    assert e.value.name == "MAK_EDEGENERATE"
+    ctx.za_deposit_cells(x, None, 1.0, 0.5, 8)
