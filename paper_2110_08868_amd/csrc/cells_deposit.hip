@@ -10,20 +10,20 @@
 // float64 cell pass: u . d <= b with d = x_j + sL - x_i and
 // b = |d|^2/2 + psi_i - psi_j (u seed-local), scaled to u . d <= (1 - tau) b,
 // plus the box of the site's own images, |u_a| <= (1 - tau) L / 2.  A
-// polytope is held in LDS as face polygons, one face per lane (vertices
-// double-buffered, vertex-major so that the lanes' accesses do not collide).
-// Clipping by a plane: every lane cuts its polygon Sutherland-Hodgman style
-// (the crossing point of an edge is evaluated from its inside end and the
-// side tests use explicit FMAs, so the two faces sharing an edge produce the
-// same bits), the surviving polygons are compacted, the crossing points are
-// gathered and duplicates dropped, and the new face is their polygon ordered
-// by angle about their centroid.  The moved cell is clipped out of its box
-// first, to find the voxels it can reach; then each of those voxels (as a
-// box) is clipped by the same planes, and the volume of what remains (fans
-// from the first vertex of each face, apex at the site) goes to the voxel.
-// Masses are summed in 64-bit fixed point (unit L^3 2^-60), so every run
-// gives the same bits; the rounding is at most half a unit per cell and
-// voxel.
+// polytope is held in LDS as face polygons, one face per lane, the vertices
+// of all faces packed in one pool per polytope.  Clipping by a plane: every
+// lane cuts its polygon Sutherland-Hodgman style (the crossing point of an
+// edge is evaluated from its inside end and the side tests use explicit
+// FMAs, so the two faces sharing an edge produce the same bits), the
+// surviving polygons are compacted, the crossing points are gathered and
+// duplicates dropped, and the new face is their polygon ordered by angle
+// about their centroid.  S_i is clipped out of its box once; then it is cut
+// into the slabs of voxel columns along x, each slab into the columns along
+// y, and a column's voxels are the differences of the volumes below the
+// successive z boundaries (fans from the first vertex of each face, apex at
+// the site).  Masses are summed in 64-bit fixed point (unit L^3 2^-60), so
+// every run gives the same bits; the rounding is at most half a unit per
+// cell and voxel.
 #include <cmath>
 
 #include "../../include/mak.h"
@@ -33,8 +33,9 @@
 namespace mak {
 namespace {
 
-constexpr int kMaxF = 64;        // face slots of a polytope (one per lane)
-constexpr int kMaxV = 16;        // vertices of a face polygon
+constexpr int kMaxF = 64;        // faces of a polytope (one per lane)
+constexpr int kPool = 512;       // vertices of all faces of a polytope
+constexpr int kBuf = 4;          // polytopes held: the moved cell, a temporary, a slab, a column
 constexpr int kMaxPlanes = 128;  // planes of a cell (faces + 6 box planes)
 
 struct DepCellArgs {
@@ -55,10 +56,11 @@ struct DepCellArgs {
 };
 
 struct PolyLDS {
-  double vx[2][kMaxV][kMaxF], vy[2][kMaxV][kMaxF], vz[2][kMaxV][kMaxF];
+  double vx[kBuf][kPool], vy[kBuf][kPool], vz[kBuf][kPool];
   double px[kMaxPlanes], py[kMaxPlanes], pz[kMaxPlanes], pb[kMaxPlanes];
   double cx[2 * kMaxF], cy[2 * kMaxF], cz[2 * kMaxF];  // crossing points, then their angles
-  int32_t nvs[kMaxF];                                  // vertex counts of the face slots
+  int32_t off[kBuf][kMaxF], nvs[kBuf][kMaxF];          // each face's vertices in the pool
+  int32_t nfc[kBuf];                                   // faces of each polytope
 };
 
 __device__ __forceinline__ double side(double x, double y, double z, double nx, double ny, double nz,
@@ -127,54 +129,60 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
   }
   __syncthreads();
 
-  int buf = 0;       // vertex buffer holding the current polygons
-  int nfc = 0;       // face slots in use (wave-uniform)
-  int nv = 0;        // vertex count of this lane's face slot
   bool bad = false;  // capacity exceeded or degenerate cut (wave-uniform after each clip)
 
-  auto init_box = [&](double lx, double ly, double lz, double hx, double hy, double hz) {
-    buf = 0;
-    nfc = 6;
-    nv = lane < 6 ? 4 : 0;
+  // the box [l, h] (seed-local) as six faces into polytope d
+  auto init_box = [&](int d, double lx, double ly, double lz, double hx, double hy, double hz) {
     if (lane < 6) {
       const uint32_t code = box_face_code(lane);
       for (int k = 0; k < 4; ++k) {
         const uint32_t c = (code >> (4 * k)) & 7u;
-        S.vx[0][k][lane] = (c & 4u) ? hx : lx;
-        S.vy[0][k][lane] = (c & 2u) ? hy : ly;
-        S.vz[0][k][lane] = (c & 1u) ? hz : lz;
+        S.vx[d][4 * lane + k] = (c & 4u) ? hx : lx;
+        S.vy[d][4 * lane + k] = (c & 2u) ? hy : ly;
+        S.vz[d][4 * lane + k] = (c & 1u) ? hz : lz;
       }
+      S.off[d][lane] = 4 * lane;
+      S.nvs[d][lane] = 4;
     }
+    if (lane == 0) S.nfc[d] = 6;
     __syncthreads();
   };
 
-  // Clip the polytope by u . n <= b; false when nothing of volume is left.
-  auto clip = [&](double nx, double ny, double nz, double b) -> bool {
-    const double* X = &S.vx[buf][0][lane];
-    const double* Y = &S.vy[buf][0][lane];
-    const double* Z = &S.vz[buf][0][lane];
+  // Polytope src clipped by u . n <= b.  Returns src when nothing of it is
+  // outside (unchanged), else d holding the clipped polytope, or -1 when
+  // nothing of volume is left.  src != d.
+  auto clip = [&](int src, int d, double nx, double ny, double nz, double b) -> int {
+    const int nfc = S.nfc[src];
+    const int nv = lane < nfc ? S.nvs[src][lane] : 0;
+    const int o = lane < nfc ? S.off[src][lane] : 0;
+    const double* X = &S.vx[src][o];
+    const double* Y = &S.vy[src][o];
+    const double* Z = &S.vz[src][o];
     // pass 1: how many vertices each face keeps
     int m = 0;
     bool out = false, on_all = nv > 0;
-    if (lane < nfc && nv > 0) {
+    if (nv > 0) {
       const double s0 = side(X[0], Y[0], Z[0], nx, ny, nz, b);
       double sp = s0;
       for (int k = 0; k < nv; ++k) {
         const int k2 = k + 1 < nv ? k + 1 : 0;
-        const double sq = k2 ? side(X[k2 * kMaxF], Y[k2 * kMaxF], Z[k2 * kMaxF], nx, ny, nz, b) : s0;
+        const double sq = k2 ? side(X[k2], Y[k2], Z[k2], nx, ny, nz, b) : s0;
         m += int(sp <= 0.0) + int((sp < 0.0 && sq > 0.0) || (sp > 0.0 && sq < 0.0));
         out = out || sp > 0.0;
         on_all = on_all && sp == 0.0;
         sp = sq;
       }
     }
-    if (ballot(out) == 0) return true;
+    if (ballot(out) == 0) return src;
     // a face lying in the plane is dropped: the new face replaces it
-    if (m > kMaxV) bad = true;
-    const bool live = m >= 3 && m <= kMaxV && !on_all;
+    const bool live = m >= 3 && !on_all;
     const int dest = wave_incl_scan_i(live ? 1 : 0) - (live ? 1 : 0);
     const int nlive = __popcll(ballot(live));
-    const int ob = buf ^ 1;
+    const int wincl = wave_incl_scan_i(live ? m : 0);
+    const int total = readlane_i(wincl, 63);
+    const int wo = wincl - (live ? m : 0);
+    const bool fits = total <= kPool;
+    if (!fits) bad = true;
     // pass 2: the clipped polygons, compacted, and the crossing points
     int ncap = 0, w = 0;
     double c0x = 0, c0y = 0, c0z = 0, c1x = 0, c1y = 0, c1z = 0;
@@ -193,18 +201,18 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
       ++ncap;
     };
     auto push = [&](double x, double y, double z) {
-      if (live) {
-        S.vx[ob][w][dest] = x;
-        S.vy[ob][w][dest] = y;
-        S.vz[ob][w][dest] = z;
+      if (live && fits) {
+        S.vx[d][wo + w] = x;
+        S.vy[d][wo + w] = y;
+        S.vz[d][wo + w] = z;
       }
       ++w;
     };
-    if (lane < nfc && nv > 0 && !on_all) {
+    if (nv > 0 && !on_all) {
       for (int k = 0; k < nv; ++k) {
         const int k2 = k + 1 < nv ? k + 1 : 0;
-        const double Px = X[k * kMaxF], Py = Y[k * kMaxF], Pz = Z[k * kMaxF];
-        const double Qx = X[k2 * kMaxF], Qy = Y[k2 * kMaxF], Qz = Z[k2 * kMaxF];
+        const double Px = X[k], Py = Y[k], Pz = Z[k];
+        const double Qx = X[k2], Qy = Y[k2], Qz = Z[k2];
         const double sP = side(Px, Py, Pz, nx, ny, nz, b), sQ = side(Qx, Qy, Qz, nx, ny, nz, b);
         if (sP <= 0.0) {
           push(Px, Py, Pz);
@@ -224,7 +232,10 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
       }
     }
     if (ncap > 2) bad = true;
-    if (live) S.nvs[dest] = m;
+    if (live) {
+      S.off[d][dest] = wo;
+      S.nvs[d][dest] = m;
+    }
     // gather the crossing points (at most two per face)
     const int nc = ncap > 2 ? 2 : ncap;
     const int incl = wave_incl_scan_i(nc);
@@ -257,8 +268,9 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
     }
     const int cnt = wave_sum_i(int(keep[0]) + int(keep[1]));
     int nfc_new = nlive;
-    if (cnt > kMaxV || (cnt >= 3 && nlive >= kMaxF)) bad = true;
-    if (cnt >= 3 && cnt <= kMaxV && nlive < kMaxF) {
+    const bool cap_fits = nlive < kMaxF && total + cnt <= kPool;
+    if (cnt >= 3 && !cap_fits) bad = true;
+    if (cnt >= 3 && cap_fits) {
       // centroid and an in-plane basis (e1 normal to n, e2 = n x e1)
       const double gx = wave_sum_d((keep[0] ? kx[0] : 0.0) + (keep[1] ? kx[1] : 0.0)) / cnt;
       const double gy = wave_sum_d((keep[0] ? ky[0] : 0.0) + (keep[1] ? ky[1] : 0.0)) / cnt;
@@ -292,92 +304,141 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
             const double au = S.cx[u];
             rank += (au < ang[h] || (au == ang[h] && u < t)) ? 1 : 0;
           }
-          S.vx[ob][rank][nlive] = kx[h];
-          S.vy[ob][rank][nlive] = ky[h];
-          S.vz[ob][rank][nlive] = kz[h];
+          S.vx[d][total + rank] = kx[h];
+          S.vy[d][total + rank] = ky[h];
+          S.vz[d][total + rank] = kz[h];
         }
       }
-      if (lane == 0) S.nvs[nlive] = cnt;
+      if (lane == 0) {
+        S.off[d][nlive] = total;
+        S.nvs[d][nlive] = cnt;
+      }
       nfc_new = nlive + 1;
     }
-    buf = ob;
     bad = ballot(bad) != 0;
     // a solid has at least four faces; fewer means nothing of volume is left
-    nfc = nfc_new >= 4 ? nfc_new : 0;
+    if (nfc_new < 4) nfc_new = 0;
+    if (lane == 0) S.nfc[d] = nfc_new;
     __syncthreads();
-    nv = lane < nfc ? S.nvs[lane] : 0;
-    return nfc > 0;
+    return nfc_new > 0 ? d : -1;
+  };
+
+  // polytope src copied into d (same pool layout)
+  auto copy = [&](int src, int d) {
+    const int nfc = S.nfc[src];
+    if (lane < nfc) {
+      const int nv = S.nvs[src][lane], o = S.off[src][lane];
+      for (int k = 0; k < nv; ++k) {
+        S.vx[d][o + k] = S.vx[src][o + k];
+        S.vy[d][o + k] = S.vy[src][o + k];
+        S.vz[d][o + k] = S.vz[src][o + k];
+      }
+      S.off[d][lane] = o;
+      S.nvs[d][lane] = nv;
+    }
+    if (lane == 0) S.nfc[d] = nfc;
+    __syncthreads();
   };
 
   // polytope volume: fans from each face's first vertex, apex at the site
-  auto volume = [&]() -> double {
+  auto volume = [&](int src) -> double {
+    const int nfc = S.nfc[src];
     double v = 0.0;
-    if (lane < nfc && nv >= 3) {
-      const double ax = S.vx[buf][0][lane], ay = S.vy[buf][0][lane], az = S.vz[buf][0][lane];
-      for (int k = 1; k + 1 < nv; ++k) {
-        const double bx = S.vx[buf][k][lane], by = S.vy[buf][k][lane], bz = S.vz[buf][k][lane];
-        const double qx = S.vx[buf][k + 1][lane], qy = S.vy[buf][k + 1][lane], qz = S.vz[buf][k + 1][lane];
-        v += ax * (by * qz - bz * qy) + ay * (bz * qx - bx * qz) + az * (bx * qy - by * qx);
-      }
+    if (lane < nfc) {
+      const int nv = S.nvs[src][lane], o = S.off[src][lane];
+      const double* X = &S.vx[src][o];
+      const double* Y = &S.vy[src][o];
+      const double* Z = &S.vz[src][o];
+      for (int k = 1; k + 1 < nv; ++k)
+        v += X[0] * (Y[k] * Z[k + 1] - Z[k] * Y[k + 1]) + Y[0] * (Z[k] * X[k + 1] - X[k] * Z[k + 1]) +
+             Z[0] * (X[k] * Y[k + 1] - Y[k] * X[k + 1]);
     }
     return wave_sum_d(v) / 6.0;
   };
 
-  auto clip_all = [&]() -> bool {
-    for (int k = 0; k < npl; ++k) {
-      const bool left = clip(S.px[k], S.py[k], S.pz[k], S.pb[k]);
-      if (bad || !left) return false;
+  // voxel index range of polytope src along axis ax (0 x, 1 y, 2 z), within
+  // the moved cell's box
+  const double hb = 0.5 * sc * L;
+  auto vrange = [&](int src, int ax, int64_t& v0, int64_t& v1) {
+    const int nfc = S.nfc[src];
+    double lo = INFINITY, hi = -INFINITY;
+    if (lane < nfc) {
+      const int nv = S.nvs[src][lane], o = S.off[src][lane];
+      const double* C = ax == 0 ? &S.vx[src][o] : (ax == 1 ? &S.vy[src][o] : &S.vz[src][o]);
+      for (int k = 0; k < nv; ++k) {
+        lo = fmin(lo, C[k]);
+        hi = fmax(hi, C[k]);
+      }
     }
-    return true;
+    const double org = ax == 0 ? me.x : (ax == 1 ? me.y : me.z);
+    const double l = fmax(-wave_max_d(-lo), -hb), h = fmin(wave_max_d(hi), hb);
+    v0 = int64_t(floor((org + l) / H + 0.5));
+    v1 = l <= h ? int64_t(floor((org + h) / H + 0.5)) : v0 - 1;
   };
 
-  // the moved cell, for the voxels it can reach
-  const double hb = 0.5 * sc * L;
-  init_box(-hb, -hb, -hb, hb, hb, hb);
-  if (!clip_all()) {
-    if (bad && lane == 0) atomicOr(A.status, 1u);
-    return;
-  }
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (lane < nfc)
-    for (int k = 0; k < nv; ++k) {
-      lo[0] = fmin(lo[0], S.vx[buf][k][lane]);
-      lo[1] = fmin(lo[1], S.vy[buf][k][lane]);
-      lo[2] = fmin(lo[2], S.vz[buf][k][lane]);
-      hi[0] = fmax(hi[0], S.vx[buf][k][lane]);
-      hi[1] = fmax(hi[1], S.vy[buf][k][lane]);
-      hi[2] = fmax(hi[2], S.vz[buf][k][lane]);
+  // the moved cell, built by clipping its box (ping-pong between 0 and 1)
+  int cur = 0, tmp = 1;
+  init_box(cur, -hb, -hb, -hb, hb, hb, hb);
+  for (int k = 0; k < npl; ++k) {
+    const int r = clip(cur, tmp, S.px[k], S.py[k], S.pz[k], S.pb[k]);
+    if (bad || r < 0) {
+      if (bad && lane == 0) atomicOr(A.status, 1u);
+      return;
     }
-  // the moved cell lies in its box: clamping to it bounds the voxel loops
-  // (at most ng + 2 voxels an axis)
-  const double org[3] = {me.x, me.y, me.z};
-  int64_t v0[3], v1[3];
-  for (int a = 0; a < 3; ++a) {
-    const double l = fmax(-wave_max_d(-lo[a]), -hb), h = fmin(wave_max_d(hi[a]), hb);
-    v0[a] = int64_t(floor((org[a] + l) / H + 0.5));
-    v1[a] = l <= h ? int64_t(floor((org[a] + h) / H + 0.5)) : v0[a] - 1;
+    if (r == tmp) {
+      tmp = cur;
+      cur = r;
+    }
   }
-  __syncthreads();
+  if (cur != 0) copy(cur, 0);
+  // polytopes: 0 the moved cell, 1 a temporary, 2 an x slab, 3 a y column of it
   const double inv3 = 1.0 / (sc * sc * sc);
-  for (int64_t a = v0[0]; a <= v1[0]; ++a)
-    for (int64_t b = v0[1]; b <= v1[1]; ++b)
-      for (int64_t c = v0[2]; c <= v1[2]; ++c) {
-        const double lx = a * H - 0.5 * H - me.x, ly = b * H - 0.5 * H - me.y, lz = c * H - 0.5 * H - me.z;
-        init_box(lx, ly, lz, lx + H, ly + H, lz + H);
-        const bool left = clip_all();
-        if (bad) {
-          if (lane == 0) atomicOr(A.status, 1u);
-          return;
-        }
-        if (!left) continue;
-        const double vol = volume();
-        __syncthreads();  // the next box overwrites the polygons
-        if (lane == 0 && vol > 0.0) {
-          const unsigned long long u = (unsigned long long)llrint(vol * inv3 / A.unit);
-          const int64_t wa = ((a % ng) + ng) % ng, wb = ((b % ng) + ng) % ng, wc = ((c % ng) + ng) % ng;
+  int64_t a0, a1;
+  vrange(0, 0, a0, a1);
+  for (int64_t a = a0; a <= a1; ++a) {
+    const double xl = (double(a) - 0.5) * H - me.x, xh = (double(a) + 0.5) * H - me.x;
+    int xs = clip(0, 1, -1.0, 0.0, 0.0, -xl);
+    if (xs >= 0) xs = clip(xs, 2, 1.0, 0.0, 0.0, xh);
+    if (bad) break;
+    if (xs < 0) continue;
+    if (xs == 1) {
+      copy(1, 2);
+      xs = 2;
+    }
+    int64_t b0, b1;
+    vrange(xs, 1, b0, b1);
+    for (int64_t bb = b0; bb <= b1; ++bb) {
+      const double yl = (double(bb) - 0.5) * H - me.y, yh = (double(bb) + 0.5) * H - me.y;
+      int ys = clip(xs, 1, 0.0, -1.0, 0.0, -yl);
+      if (ys >= 0) ys = clip(ys, 3, 0.0, 1.0, 0.0, yh);
+      if (bad) break;
+      if (ys < 0) continue;
+      if (ys == 1) {
+        copy(1, 3);
+        ys = 3;
+      }
+      int64_t c0, c1;
+      vrange(ys, 2, c0, c1);
+      // the column's voxels: differences of the volumes below the z boundaries
+      double below = 0.0;
+      for (int64_t c = c0; c <= c1; ++c) {
+        const double zh = (double(c) + 0.5) * H - me.z;
+        const int zs = clip(ys, 1, 0.0, 0.0, 1.0, zh);
+        if (bad) break;
+        const double vz = zs < 0 ? 0.0 : volume(zs);
+        const double part = vz - below;
+        below = vz;
+        if (lane == 0 && part > 0.0) {
+          const unsigned long long u = (unsigned long long)llrint(part * inv3 / A.unit);
+          const int64_t wa = ((a % ng) + ng) % ng, wb = ((bb % ng) + ng) % ng, wc = ((c % ng) + ng) % ng;
           if (u) atomicAdd(&A.acc[(wa * ng + wb) * ng + wc], u);
         }
       }
+      if (bad) break;
+    }
+    if (bad) break;
+  }
+  if (bad && lane == 0) atomicOr(A.status, 1u);
 }
 
 __global__ void k_units_to_rho(const unsigned long long* __restrict__ acc, double scale,
