@@ -225,7 +225,8 @@ def deposit_and_power(mak, x_dev, psi, L, ng, tau, reps, workload):
     """Zel'dovich deposit of the solved cells at growth amplitude tau (ng^3
     mass elements, cloud in cell onto an ng^3 mesh), then the power spectrum
     of its contrast (CIC window removed).  HIP-event times of the deposit
-    kernel, the FFT and the shell binning over `reps` calls each."""
+    kernel, the FFT and the shell binning over `reps` calls each, and of one
+    exact deposit of the moved cells."""
     import torch
     ctx = mak.Context(0)
     rho = ctx.za_deposit(x_dev, psi, L, tau, ng, ng, "cic")
@@ -241,11 +242,25 @@ def deposit_and_power(mak, x_dev, psi, L, ng, tau, reps, workload):
         k, P, m = ctx.power_spectrum(rho, L, window=2, contrast=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    # the exact deposit of the moved cells (a float64 cell pass with faces,
+    # then each cell clipped against the voxels it reaches): one warm call
+    ctx.za_deposit_cells(x_dev, psi, L, tau, ng)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    rho_x = ctx.za_deposit_cells(x_dev, psi, L, tau, ng)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.close()
     dep = prof["deposit"]
+    cdep = prof["cells_deposit"]
     rho_c = rho.cpu()
+    N = x_dev.shape[0]
+    cells_kernel_ms = cdep["total_ms"] / cdep["launches"]
     return {
+        "deposit_cells": {"tau": tau, "cells": N, "mesh": ng, "ms_per_call": (t4 - t3) * 1e3,
+                          "kernel_ms": cells_kernel_ms, "cells_per_s_kernel": N / (cells_kernel_ms * 1e-3),
+                          "mass_rel_err": float(rho_x.sum().item() / ng ** 3 - 1.0)},
         "deposit": {"tau": tau, "elements": ng ** 3, "mesh": ng, "scheme": "cic",
                     "ms_per_call": (t1 - t0) / reps * 1e3,
                     "elements_per_s_kernel": ng ** 3 / (dep["total_ms"] / dep["launches"] * 1e-3),
