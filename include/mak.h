@@ -251,10 +251,11 @@ mak_status mak_za_deposit(mak_ctx* ctx, const double* points, const double* psi,
  *   density      DEVICE (ng, ng, ng) float64 out, row-major: mass / H^3 (mean 1)
  * Masses are summed in 64-bit fixed point (unit L^3 2^-60, each cell-voxel
  * part rounded to the nearest unit), so the result is the same bits on every
- * run.  MAK_EDEGENERATE for coincident sites; MAK_EOVERFLOW if a cell has more
- * than 122 faces, a clipped polytope more than 64 faces or a face more than
- * 16 vertices, or a cut meets three points of one face in the plane (a
- * degenerate configuration).  Holds the cell pass (about 600 bytes a site)
+ * run.  Vertices within 1e-14 L of a cutting plane count as on it (lattice
+ * inputs put cell faces on voxel boundaries).  MAK_EDEGENERATE for
+ * coincident sites; MAK_EOVERFLOW if a cell has more than 122 faces, a
+ * clipped polytope more than 64 faces or 512 face corners in all, or a cut
+ * meets more than four points of one face in the plane.  Holds the cell pass (about 600 bytes a site)
  * and ng^3 x 8 bytes of scratch in the context. */
 mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
                                 double L, double tau, int64_t ng, double* density, void* stream);

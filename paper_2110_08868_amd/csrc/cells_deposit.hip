@@ -14,10 +14,11 @@
 // of all faces packed in one pool per polytope.  Clipping by a plane: every
 // lane cuts its polygon Sutherland-Hodgman style (the crossing point of an
 // edge is evaluated from its inside end and the side tests use explicit
-// FMAs, so the two faces sharing an edge produce the same bits), the
-// surviving polygons are compacted, the crossing points are gathered and
-// duplicates dropped, and the new face is their polygon ordered by angle
-// about their centroid.  S_i is clipped out of its box once; then it is cut
+// FMAs, so the two faces sharing an edge produce the same bits; a vertex
+// within 1e-14 L of the plane counts as on it, so lattice inputs whose faces
+// fall on voxel boundaries cut cleanly), the surviving polygons are
+// compacted, the crossing points are gathered and duplicates dropped, and
+// the new face is their polygon ordered by angle about their centroid.  S_i is clipped out of its box once; then it is cut
 // into the slabs of voxel columns along x, each slab into the columns along
 // y, and a column's voxels are the differences of the volumes below the
 // successive z boundaries (fans from the first vertex of each face, apex at
@@ -37,6 +38,10 @@ constexpr int kMaxF = 64;        // faces of a polytope (one per lane)
 constexpr int kPool = 512;       // vertices of all faces of a polytope
 constexpr int kBuf = 4;          // polytopes held: the moved cell, a temporary, a slab, a column
 constexpr int kMaxPlanes = 128;  // planes of a cell (faces + 6 box planes)
+constexpr int kCap = 4;          // points of one face on a cutting plane
+// side values within kSnap L |n| of zero count as on the plane (rounding of
+// vertices that lie on it, e.g. lattice sites against voxel boundaries)
+constexpr double kSnap = 1e-14;
 
 struct DepCellArgs {
   const double4* pts;
@@ -58,7 +63,7 @@ struct DepCellArgs {
 struct PolyLDS {
   double vx[kBuf][kPool], vy[kBuf][kPool], vz[kBuf][kPool];
   double px[kMaxPlanes], py[kMaxPlanes], pz[kMaxPlanes], pb[kMaxPlanes];
-  double cx[2 * kMaxF], cy[2 * kMaxF], cz[2 * kMaxF];  // crossing points, then their angles
+  double cx[kCap * kMaxF], cy[kCap * kMaxF], cz[kCap * kMaxF];  // crossing points, then their angles
   int32_t off[kBuf][kMaxF], nvs[kBuf][kMaxF];          // each face's vertices in the pool
   int32_t nfc[kBuf];                                   // faces of each polytope
 };
@@ -158,15 +163,20 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
     const double* X = &S.vx[src][o];
     const double* Y = &S.vy[src][o];
     const double* Z = &S.vz[src][o];
+    const double tol = kSnap * A.L * sqrt(nx * nx + ny * ny + nz * nz);
+    auto sd = [&](double x, double y, double z) {
+      const double v = side(x, y, z, nx, ny, nz, b);
+      return fabs(v) <= tol ? 0.0 : v;
+    };
     // pass 1: how many vertices each face keeps
     int m = 0;
     bool out = false, on_all = nv > 0;
     if (nv > 0) {
-      const double s0 = side(X[0], Y[0], Z[0], nx, ny, nz, b);
+      const double s0 = sd(X[0], Y[0], Z[0]);
       double sp = s0;
       for (int k = 0; k < nv; ++k) {
         const int k2 = k + 1 < nv ? k + 1 : 0;
-        const double sq = k2 ? side(X[k2], Y[k2], Z[k2], nx, ny, nz, b) : s0;
+        const double sq = k2 ? sd(X[k2], Y[k2], Z[k2]) : s0;
         m += int(sp <= 0.0) + int((sp < 0.0 && sq > 0.0) || (sp > 0.0 && sq < 0.0));
         out = out || sp > 0.0;
         on_all = on_all && sp == 0.0;
@@ -185,19 +195,18 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
     if (!fits) bad = true;
     // pass 2: the clipped polygons, compacted, and the crossing points
     int ncap = 0, w = 0;
-    double c0x = 0, c0y = 0, c0z = 0, c1x = 0, c1y = 0, c1z = 0;
+    double qx[kCap] = {0, 0, 0, 0}, qy[kCap] = {0, 0, 0, 0}, qz[kCap] = {0, 0, 0, 0};
     auto add_cap = [&](double x, double y, double z) {
-      if (ncap > 0 && x == c0x && y == c0y && z == c0z) return;
-      if (ncap > 1 && x == c1x && y == c1y && z == c1z) return;
-      if (ncap == 0) {
-        c0x = x;
-        c0y = y;
-        c0z = z;
-      } else if (ncap == 1) {
-        c1x = x;
-        c1y = y;
-        c1z = z;
-      }
+#pragma unroll
+      for (int c = 0; c < kCap; ++c)
+        if (c < ncap && x == qx[c] && y == qy[c] && z == qz[c]) return;
+#pragma unroll
+      for (int c = 0; c < kCap; ++c)
+        if (c == ncap) {
+          qx[c] = x;
+          qy[c] = y;
+          qz[c] = z;
+        }
       ++ncap;
     };
     auto push = [&](double x, double y, double z) {
@@ -213,7 +222,7 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
         const int k2 = k + 1 < nv ? k + 1 : 0;
         const double Px = X[k], Py = Y[k], Pz = Z[k];
         const double Qx = X[k2], Qy = Y[k2], Qz = Z[k2];
-        const double sP = side(Px, Py, Pz, nx, ny, nz, b), sQ = side(Qx, Qy, Qz, nx, ny, nz, b);
+        const double sP = sd(Px, Py, Pz), sQ = sd(Qx, Qy, Qz);
         if (sP <= 0.0) {
           push(Px, Py, Pz);
           if (sP == 0.0) add_cap(Px, Py, Pz);
@@ -231,30 +240,30 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
         }
       }
     }
-    if (ncap > 2) bad = true;
+    // (a convex face meets a plane in a segment: two points, more only when
+    // vertices of the face lie on the plane between them)
+    if (ncap > kCap) bad = true;
     if (live) {
       S.off[d][dest] = wo;
       S.nvs[d][dest] = m;
     }
-    // gather the crossing points (at most two per face)
-    const int nc = ncap > 2 ? 2 : ncap;
+    // gather the crossing points
+    const int nc = ncap > kCap ? kCap : ncap;
     const int incl = wave_incl_scan_i(nc);
     const int tot = readlane_i(incl, 63);
-    if (nc > 0) {
-      S.cx[incl - nc] = c0x;
-      S.cy[incl - nc] = c0y;
-      S.cz[incl - nc] = c0z;
-      if (nc > 1) {
-        S.cx[incl - 1] = c1x;
-        S.cy[incl - 1] = c1y;
-        S.cz[incl - 1] = c1z;
+#pragma unroll
+    for (int c = 0; c < kCap; ++c)
+      if (c < nc) {
+        S.cx[incl - nc + c] = qx[c];
+        S.cy[incl - nc + c] = qy[c];
+        S.cz[incl - nc + c] = qz[c];
       }
-    }
     __syncthreads();
-    // the first occurrence of each point (two entries per lane)
-    bool keep[2] = {false, false};
-    double kx[2] = {0, 0}, ky[2] = {0, 0}, kz[2] = {0, 0};
-    for (int h = 0; h < 2; ++h) {
+    // the first occurrence of each point (kCap entries per lane)
+    bool keep[kCap] = {false, false, false, false};
+    double kx[kCap] = {0, 0, 0, 0}, ky[kCap] = {0, 0, 0, 0}, kz[kCap] = {0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < kCap; ++h) {
       const int t = lane + 64 * h;
       if (t < tot) {
         kx[h] = S.cx[t];
@@ -266,15 +275,25 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
         keep[h] = first;
       }
     }
-    const int cnt = wave_sum_i(int(keep[0]) + int(keep[1]));
+    int nkeep = 0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int h = 0; h < kCap; ++h)
+      if (keep[h]) {
+        ++nkeep;
+        sx += kx[h];
+        sy += ky[h];
+        sz += kz[h];
+      }
+    const int cnt = wave_sum_i(nkeep);
     int nfc_new = nlive;
     const bool cap_fits = nlive < kMaxF && total + cnt <= kPool;
     if (cnt >= 3 && !cap_fits) bad = true;
     if (cnt >= 3 && cap_fits) {
       // centroid and an in-plane basis (e1 normal to n, e2 = n x e1)
-      const double gx = wave_sum_d((keep[0] ? kx[0] : 0.0) + (keep[1] ? kx[1] : 0.0)) / cnt;
-      const double gy = wave_sum_d((keep[0] ? ky[0] : 0.0) + (keep[1] ? ky[1] : 0.0)) / cnt;
-      const double gz = wave_sum_d((keep[0] ? kz[0] : 0.0) + (keep[1] ? kz[1] : 0.0)) / cnt;
+      const double gx = wave_sum_d(sx) / cnt;
+      const double gy = wave_sum_d(sy) / cnt;
+      const double gz = wave_sum_d(sz) / cnt;
       const double inn = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
       const double hx = nx * inn, hy = ny * inn, hz = nz * inn;
       // e1 = t x n with t the x axis, or the y axis when n is close to x
@@ -285,18 +304,21 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
       e1y *= ie1;
       e1z *= ie1;
       const double e2x = hy * e1z - hz * e1y, e2y = hz * e1x - hx * e1z, e2z = hx * e1y - hy * e1x;
-      double ang[2] = {0.0, 0.0};
-      for (int h = 0; h < 2; ++h) {
+      double ang[kCap] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int h = 0; h < kCap; ++h) {
         const double rx = kx[h] - gx, ry = ky[h] - gy, rz = kz[h] - gz;
         ang[h] = atan2(rx * e2x + ry * e2y + rz * e2z, rx * e1x + ry * e1y + rz * e1z);
       }
       __syncthreads();  // the crossing points are read; their slots now take the angles
-      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int h = 0; h < kCap; ++h) {
         const int t = lane + 64 * h;
         S.cx[t] = (t < tot && keep[h]) ? ang[h] : INFINITY;
       }
       __syncthreads();
-      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int h = 0; h < kCap; ++h) {
         const int t = lane + 64 * h;
         if (t < tot && keep[h]) {
           int rank = 0;

@@ -50,6 +50,23 @@ def test_vs_oracle(ctx, n, tau, ng, L, seed):
     assert r.sum() / ng ** 3 == pytest.approx(1.0, rel=1e-12)
 
 
+@pytest.mark.parametrize("n,off,ng,tau,L", [
+    (5, 0.0, 5, 0.0, 1.0), (5, 0.0, 10, 0.3, 1.0), (6, 0.0, 12, 0.5, 0.7), (4, 0.0, 8, 0.5, 1.0),
+    (3, 0.0, 3, 0.0, 1.0), (5, 0.0, 5, 0.6, 2.0), (4, 0.5, 4, 0.0, 1.0)])
+def test_lattice(ctx, n, off, ng, tau, L):
+    """Sites on a lattice with zero weights: the cells are cubes whose faces
+    (moved or not) fall on voxel boundaries and on each other's vertices,
+    the degenerate cuts of the method."""
+    x = workloads.mesh_points(n, L, off)
+    print(f"  lattice {n}^3 offset {off} ng={ng} tau={tau} L={L}", flush=True)
+    r = gcells(ctx, x, None, L, tau, ng)
+    o = oracle.za_deposit_exact(x, np.zeros(len(x)), L, tau, ng)
+    err = np.abs(r - o).max()
+    print(f"    max |drho| = {err:.2e}", flush=True)
+    assert err <= TOL
+    assert r.sum() / ng ** 3 == pytest.approx(1.0, rel=1e-12)
+
+
 def test_single_site_and_clustered(ctx):
     """One site (the cell is the whole box, moved it is the box shrunk by
     1 - tau), and a clustered set with near-empty cells."""
