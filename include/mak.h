@@ -254,7 +254,7 @@ mak_status mak_za_deposit(mak_ctx* ctx, const double* points, const double* psi,
  * run.  Vertices within 1e-14 L of a cutting plane count as on it (lattice
  * inputs put cell faces on voxel boundaries).  MAK_EDEGENERATE for
  * coincident sites; MAK_EOVERFLOW if a cell has more than 122 faces, a
- * clipped polytope more than 64 faces or 512 face corners in all, or a cut
+ * clipped polytope more than 64 faces or 400 face corners in all, or a cut
  * meets more than four points of one face in the plane.  Holds the cell pass (about 600 bytes a site)
  * and ng^3 x 8 bytes of scratch in the context. */
 mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double* psi, int64_t N,

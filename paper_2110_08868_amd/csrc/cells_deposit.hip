@@ -35,7 +35,7 @@ namespace mak {
 namespace {
 
 constexpr int kMaxF = 64;        // faces of a polytope (one per lane)
-constexpr int kPool = 512;       // vertices of all faces of a polytope
+constexpr int kPool = 400;       // face corners of a polytope (Euler: at most 6 F - 12 = 372 for F = 64 faces)
 constexpr int kBuf = 4;          // polytopes held: the moved cell, a temporary, a slab, a column
 constexpr int kMaxPlanes = 128;  // planes of a cell (faces + 6 box planes)
 constexpr int kCap = 4;          // points of one face on a cutting plane
@@ -71,6 +71,16 @@ struct PolyLDS {
 __device__ __forceinline__ double side(double x, double y, double z, double nx, double ny, double nz,
                                        double b) {
   return fma(x, nx, fma(y, ny, z * nz)) - b;
+}
+
+// A strictly increasing function of the angle of (x, y) in [0, 2 pi), with
+// values in [0, 4): the position along the unit diamond |x| + |y| = 1 (one
+// division instead of an arctangent; only the order is used).
+__device__ __forceinline__ double pseudo_angle(double x, double y) {
+  const double s = fabs(x) + fabs(y);
+  if (!(s > 0.0)) return 0.0;
+  const double t = y / s;  // sin-like coordinate in [-1, 1]
+  return x >= 0.0 ? (y >= 0.0 ? t : 4.0 + t) : 2.0 - t;
 }
 
 // Corners of the six faces of a box, counter-clockwise seen from outside:
@@ -308,7 +318,7 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
 #pragma unroll
       for (int h = 0; h < kCap; ++h) {
         const double rx = kx[h] - gx, ry = ky[h] - gy, rz = kz[h] - gz;
-        ang[h] = atan2(rx * e2x + ry * e2y + rz * e2z, rx * e1x + ry * e1y + rz * e1z);
+        ang[h] = pseudo_angle(rx * e1x + ry * e1y + rz * e1z, rx * e2x + ry * e2y + rz * e2z);
       }
       __syncthreads();  // the crossing points are read; their slots now take the angles
 #pragma unroll
