@@ -255,7 +255,9 @@ mak_status mak_za_deposit(mak_ctx* ctx, const double* points, const double* psi,
  * inputs put cell faces on voxel boundaries).  MAK_EDEGENERATE for
  * coincident sites; MAK_EOVERFLOW if a cell has more than 122 faces, a
  * clipped polytope more than 64 faces or 400 face corners in all, or a cut
- * meets more than four points of one face in the plane.  Holds the cell pass (about 600 bytes a site)
+ * meets more than four points of one face in the plane.  One wavefront
+ * clips all the voxels of a cell, so MAK_EINVAL when the largest moved cell
+ * spans more than 2^22 voxel volumes ((1 - tau)^3 max V_i / H^3).  Holds the cell pass (about 600 bytes a site)
  * and ng^3 x 8 bytes of scratch in the context. */
 mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
                                 double L, double tau, int64_t ng, double* density, void* stream);

@@ -163,6 +163,8 @@ mak_status guarded(mak_ctx* ctx, F&& f) {
   }
 }
 
+constexpr int64_t kMaxVoxelsPerCell = int64_t(1) << 22;
+
 void check_args(int64_t N, double L) {
   if (N < 1) MAK_FAIL(MAK_EINVAL, "N must be >= 1");
   if (N >= (int64_t(1) << 31)) MAK_FAIL(MAK_EINVAL, "N must be < 2^31");
@@ -362,6 +364,12 @@ mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double
     (void)cs;
     FlagStats fs = flag_stats(ctx->lps, ctx->dcp, ctx->tmp, st);
     if (fs.coincident > 0) MAK_FAIL(MAK_EDEGENERATE, "coincident sites");
+    // one wavefront clips all the voxels of a cell: bound that work (a moved
+    // cell of volume (1 - tau)^3 V spans at least that many voxel volumes)
+    const double vmax = dev_reduce_max(ctx->dcp.vol.as<double>(), N, ctx->tmp, st);
+    const double H = L / double(ng), sc = 1.0 - tau;
+    if (vmax * sc * sc * sc / (H * H * H) > double(kMaxVoxelsPerCell))
+      MAK_FAIL(MAK_EINVAL, "a moved cell spans more than 2^22 voxels: use a coarser mesh (or mak_za_deposit)");
     za_deposit_cells(ctx->lps, ctx->dcp, tau, ng, density, ctx->dep_acc, ctx->lstatus, st);
   });
 }

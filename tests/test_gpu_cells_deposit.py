@@ -138,6 +138,10 @@ def test_errors(ctx):
         with pytest.raises(mak.MakError) as e:
             ctx.za_deposit_cells(x, None, 1.0, tau, ng)
         assert e.value.name == "MAK_EINVAL"
+    # one site: its cell is the whole box, 256^3 voxels at tau = 0 (over 2^22)
+    with pytest.raises(mak.MakError) as e:
+        ctx.za_deposit_cells(torch.tensor([[0.3, 0.6, 0.1]], dtype=torch.float64), None, 1.0, 0.0, 256)
+    assert e.value.name == "MAK_EINVAL"
     xc = x.clone()
     xc[5] = xc[9]
     with pytest.raises(mak.MakError) as e:
