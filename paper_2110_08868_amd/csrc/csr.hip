@@ -204,6 +204,43 @@ __global__ __launch_bounds__(256) void k_lap_fill_rows(const FaceRec* faces, con
   diag[p] = d;
 }
 
+// SELL-64 copy of the Laplacian rows (one wavefront per slice of 64 rows).
+__global__ __launch_bounds__(256) void k_sell_len(const int64_t* __restrict__ rowcnt, int32_t* __restrict__ slen,
+                                                  int64_t* __restrict__ slen64, int64_t n, int64_t nsl) {
+  const int64_t s = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (s >= nsl) return;  // the same slice for the whole wavefront
+  const int64_t r = s * 64 + lane;
+  int c = r < n ? int(rowcnt[r]) : 0;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) c = max(c, __shfl_xor(c, o));
+  if (lane == 0) {
+    slen[s] = c;
+    slen64[s] = int64_t(c) * 64;
+  }
+}
+
+template <typename W>
+__global__ __launch_bounds__(256) void k_sell_fill(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   const W* __restrict__ w, const int64_t* __restrict__ soff,
+                                                   const int32_t* __restrict__ slen, int32_t* __restrict__ scol,
+                                                   W* __restrict__ sw, int64_t n, int64_t nsl) {
+  const int64_t s = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (s >= nsl) return;
+  const int64_t r = s * 64 + lane;
+  const int64_t base = soff[s] + lane;
+  const int len = slen[s];
+  const int64_t o = r < n ? rp[r] : 0;
+  const int cnt = r < n ? int(rp[r + 1] - o) : 0;
+  const int32_t own = r < n ? int32_t(r) : 0;
+  for (int k = 0; k < len; ++k) {
+    const bool in = k < cnt;
+    scol[base + int64_t(k) * 64] = in ? col[o + k] : own;
+    sw[base + int64_t(k) * 64] = in ? w[o + k] : W(0);
+  }
+}
+
 // Face lists in original order; the area is the stored weight times |d|,
 // with d formed as the clip kernel forms it (equal to within rounding).
 __global__ void k_face_copy(const FaceRec* faces, const FaceRec* ovf, const int64_t* fbase,
@@ -293,6 +330,33 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
                        fst.ovf.as<FaceRec>(), fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(),
                        J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.w.as<double>(),
                        J.diag.as<double>(), n);
+  MAK_HIP(hipGetLastError());
+  // the SELL-64 copy for the SpMV
+  const int64_t nsl = ceil_div(n, 64);
+  J.nsl = nsl;
+  J.slen.ensure(size_t(nsl) * sizeof(int32_t));
+  J.slen64.ensure(size_t(nsl) * sizeof(int64_t));
+  J.soff.ensure(size_t(nsl) * sizeof(int64_t));
+  const unsigned nbsl = unsigned(ceil_div(nsl, 4));
+  hipLaunchKernelGGL(k_sell_len, dim3(nbsl), dim3(256), 0, st, J.rowcnt.as<int64_t>(), J.slen.as<int32_t>(),
+                     J.slen64.as<int64_t>(), n, nsl);
+  MAK_HIP(hipGetLastError());
+  exclusive_scan_i64(J.slen64.as<int64_t>(), J.soff.as<int64_t>(), nsl, cp.scan_tmp, st);
+  int64_t last[2] = {0, 0};
+  MAK_HIP(hipMemcpyAsync(&last[0], J.soff.as<int64_t>() + (nsl - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipMemcpyAsync(&last[1], J.slen64.as<int64_t>() + (nsl - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  J.sell_n = last[0] + last[1];
+  J.scol.ensure(size_t(J.sell_n) * sizeof(int32_t));
+  J.sw.ensure(size_t(J.sell_n) * (f32 ? sizeof(float) : sizeof(double)));
+  if (f32)
+    hipLaunchKernelGGL(k_sell_fill<float>, dim3(nbsl), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
+                       J.col.as<int32_t>(), J.w.as<float>(), J.soff.as<int64_t>(), J.slen.as<int32_t>(),
+                       J.scol.as<int32_t>(), J.sw.as<float>(), n, nsl);
+  else
+    hipLaunchKernelGGL(k_sell_fill<double>, dim3(nbsl), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
+                       J.col.as<int32_t>(), J.w.as<double>(), J.soff.as<int64_t>(), J.slen.as<int32_t>(),
+                       J.scol.as<int32_t>(), J.sw.as<double>(), n, nsl);
   MAK_HIP(hipGetLastError());
 }
 

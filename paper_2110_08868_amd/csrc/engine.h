@@ -142,6 +142,16 @@ struct Lap {
   DevBuf w;        // float or double [nnz]
   DevBuf diag;     // double [n]
   DevBuf rowcnt;   // int64 [n]
+  // The same off-diagonal weights in SELL-64 form for the SpMV: slice s holds
+  // rows 64 s .. 64 s + 63 column-major (entry k of row 64 s + l at
+  // soff[s] + 64 k + l), padded to the slice's longest row with the row's own
+  // column and weight 0.
+  int64_t nsl = 0, sell_n = 0;
+  DevBuf soff;     // int64 [nsl]
+  DevBuf slen;     // int32 [nsl]
+  DevBuf slen64;   // int64 [nsl] (scan input)
+  DevBuf scol;     // int32 [sell_n]
+  DevBuf sw;       // float or double [sell_n]
 };
 
 // --- grid.hip
