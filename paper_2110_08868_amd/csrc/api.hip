@@ -46,15 +46,15 @@ size_t solve_bytes_per_site(int64_t N) {
   //     slot row
   //   J: row_ptr 8, row counts 8, diagonal 8, 16 neighbours per row x 12
   //     (col + float64 weight; 8 with the mixed path's float weights), and
-  //     its SELL-64 copy for the SpMV: 24 slots per row (42 % padding on
-  //     clustered inputs) x 12, slice tables ~0.3
+  //     on the mixed path its SELL-64 copy for the SpMV: 24 slots per row
+  //     (42 % padding on clustered inputs) x 8, slice tables ~0.3
   //   CG r, u, p, w, s, 1/diag 48;  Newton psi, trial psi, g, step, masses 40
   // The grid build's staging (40 bytes per site) is released before the
   // first pass for sets above 2^24 sites and fits in the pass buffers' share
   // below that.
   const size_t fslot = size_t(face_slots(N));
   const size_t faces = fslot * sizeof(FaceRec) + 8 + 2 * sizeof(FaceRec);
-  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 24 * 12 + 1 + 48 + 40;
+  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 24 * 8 + 1 + 48 + 40;
 }
 
 namespace {

@@ -331,7 +331,11 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
                        J.row_ptr.as<int64_t>(), J.col.as<int32_t>(), J.w.as<double>(),
                        J.diag.as<double>(), n);
   MAK_HIP(hipGetLastError());
-  // the SELL-64 copy for the SpMV
+  // the SELL-64 copy for the SpMV of the mixed path (float weights)
+  if (!f32) {
+    J.nsl = J.sell_n = 0;
+    return;
+  }
   const int64_t nsl = ceil_div(n, 64);
   J.nsl = nsl;
   J.slen.ensure(size_t(nsl) * sizeof(int32_t));
@@ -348,15 +352,10 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
   MAK_HIP(hipStreamSynchronize(st));
   J.sell_n = last[0] + last[1];
   J.scol.ensure(size_t(J.sell_n) * sizeof(int32_t));
-  J.sw.ensure(size_t(J.sell_n) * (f32 ? sizeof(float) : sizeof(double)));
-  if (f32)
-    hipLaunchKernelGGL(k_sell_fill<float>, dim3(nbsl), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
-                       J.col.as<int32_t>(), J.w.as<float>(), J.soff.as<int64_t>(), J.slen.as<int32_t>(),
-                       J.scol.as<int32_t>(), J.sw.as<float>(), n, nsl);
-  else
-    hipLaunchKernelGGL(k_sell_fill<double>, dim3(nbsl), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
-                       J.col.as<int32_t>(), J.w.as<double>(), J.soff.as<int64_t>(), J.slen.as<int32_t>(),
-                       J.scol.as<int32_t>(), J.sw.as<double>(), n, nsl);
+  J.sw.ensure(size_t(J.sell_n) * sizeof(float));
+  hipLaunchKernelGGL(k_sell_fill<float>, dim3(nbsl), dim3(256), 0, st, J.row_ptr.as<int64_t>(),
+                     J.col.as<int32_t>(), J.w.as<float>(), J.soff.as<int64_t>(), J.slen.as<int32_t>(),
+                     J.scol.as<int32_t>(), J.sw.as<float>(), n, nsl);
   MAK_HIP(hipGetLastError());
 }
 

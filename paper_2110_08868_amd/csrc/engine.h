@@ -142,7 +142,8 @@ struct Lap {
   DevBuf w;        // float or double [nnz]
   DevBuf diag;     // double [n]
   DevBuf rowcnt;   // int64 [n]
-  // The same off-diagonal weights in SELL-64 form for the SpMV: slice s holds
+  // Mixed path: the same off-diagonal weights in SELL-64 form for the SpMV
+  // (float; not built for FP64 weights): slice s holds
   // rows 64 s .. 64 s + 63 column-major (entry k of row 64 s + l at
   // soff[s] + 64 k + l), padded to the slice's longest row with the row's own
   // column and weight 0.
@@ -151,7 +152,7 @@ struct Lap {
   DevBuf slen;     // int32 [nsl]
   DevBuf slen64;   // int64 [nsl] (scan input)
   DevBuf scol;     // int32 [sell_n]
-  DevBuf sw;       // float or double [sell_n]
+  DevBuf sw;       // float [sell_n]
 };
 
 // --- grid.hip

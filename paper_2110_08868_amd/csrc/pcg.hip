@@ -36,8 +36,69 @@ unsigned vec_blocks(int64_t n) {
   return unsigned(b < MAXB ? (b < 1 ? 1 : b) : MAXB);
 }
 
-// q = J p for the Laplacian form (q_i = d_i p_i - sum_j w_ij p_j) from the
-// SELL-64 copy, and per-block partials of p . q.  One lane per row: the
+// CSR SpMV (the FP64 path, whose 12-byte slots make the SELL padding cost
+// more than it saves): LPR lanes per row, each lane issuing UNR independent
+// loads of col / val before the gathers of p (rows hold ~16 nonzeros: one
+// unrolled step covers most rows, and the loads of a lane are all in flight
+// at once).
+constexpr int LPR = 4, UNR = 6;
+
+// A multiple of 8: workgroup b runs on XCD b mod 8 (round-robin dispatch),
+// and each XCD takes one contiguous eighth of the rows, so the gathers of p
+// by its rows (spatial neighbours in the grid-sorted order) stay in its own
+// L2 instead of all eight.
+unsigned spmv_blocks(int64_t n) {
+  int64_t b = ceil_div(n, TPB / LPR);
+  b = b < SPMV_MAXB ? b : SPMV_MAXB;
+  return unsigned(ceil_div(b < 1 ? 1 : b, 8) * 8);
+}
+
+// q = J p for the Laplacian form (q_i = d_i p_i - sum_j w_ij p_j),
+// grid-stride over row groups, and per-block partial of p . q
+template <typename W>
+__global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const W* __restrict__ w,
+                                                  const double* __restrict__ diag,
+                                                  const double* __restrict__ p, double* __restrict__ q,
+                                                  double* __restrict__ part, int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  const int sub = threadIdx.x & (LPR - 1);
+  const int xcd = int(blockIdx.x & 7u);
+  const int64_t r0 = n * xcd / 8, r1 = n * (xcd + 1) / 8;
+  const int64_t step = int64_t(gridDim.x >> 3) * (TPB / LPR);
+  double acc = 0.0;
+  for (int64_t row = r0 + int64_t(blockIdx.x >> 3) * (TPB / LPR) + (threadIdx.x / LPR); row < r1;
+       row += step) {
+    const int64_t b = rp[row], e = rp[row + 1];
+    double s = 0.0;
+    for (int64_t k = b + sub; k < e; k += UNR * LPR) {
+      int32_t c[UNR];
+      double v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int64_t kk = k + u * LPR;
+        c[u] = kk < e ? col[kk] : -1;
+        v[u] = kk < e ? double(w[kk]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) s += c[u] >= 0 ? v[u] * p[c[u]] : 0.0;
+    }
+#pragma unroll
+    for (int o = LPR / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+    if (sub == 0) {
+      const double pr = p[row];
+      const double qi = diag[row] * pr - s;
+      q[row] = qi;
+      acc += qi * pr;
+    }
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// The same product from the SELL-64 copy (the mixed path's float weights),
+// and per-block partials of p . q.  One lane per row: the
 // loads of a slice's k-th entries are coalesced across the wavefront and
 // independent of one another (no row-pointer chain); on the clustered 128^3
 // Hessian this is 21 % faster than CSR with 4 lanes per row, despite 42 %
@@ -266,7 +327,7 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
   w.q.ensure(size_t(n) * sizeof(double));
   w.s.ensure(size_t(n) * sizeof(double));
   w.dinv.ensure(size_t(n) * sizeof(double));
-  const unsigned nbs = sell_blocks(n);
+  const unsigned nbs = J.f32 ? sell_blocks(n) : spmv_blocks(n);
   w.part.ensure(size_t(2 * MAXB + 16) * sizeof(double));
   w.part2.ensure(size_t(nbs + 16) * sizeof(double));
   w.scal.ensure(16 * sizeof(double));
@@ -294,9 +355,8 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
                          J.slen.as<int32_t>(), J.scol.as<int32_t>(), J.sw.as<float>(), J.diag.as<double>(), v,
                          qv, part2, n);
     else
-      hipLaunchKernelGGL(k_spmv_sell<double>, dim3(nbs), dim3(TPB), 0, st, J.soff.as<int64_t>(),
-                         J.slen.as<int32_t>(), J.scol.as<int32_t>(), J.sw.as<double>(), J.diag.as<double>(), v,
-                         qv, part2, n);
+      hipLaunchKernelGGL(k_spmv_dot<double>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
+                         J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), v, qv, part2, n);
   };
   hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.diag.as<double>(), dinv, n);
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, b, part, n);
