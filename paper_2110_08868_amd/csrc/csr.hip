@@ -340,17 +340,16 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
   J.nsl = nsl;
   J.slen.ensure(size_t(nsl) * sizeof(int32_t));
   J.slen64.ensure(size_t(nsl) * sizeof(int64_t));
-  J.soff.ensure(size_t(nsl) * sizeof(int64_t));
+  J.soff.ensure(size_t(nsl + 1) * sizeof(int64_t));  // the scan writes the total at [nsl]
   const unsigned nbsl = unsigned(ceil_div(nsl, 4));
   hipLaunchKernelGGL(k_sell_len, dim3(nbsl), dim3(256), 0, st, J.rowcnt.as<int64_t>(), J.slen.as<int32_t>(),
                      J.slen64.as<int64_t>(), n, nsl);
   MAK_HIP(hipGetLastError());
   exclusive_scan_i64(J.slen64.as<int64_t>(), J.soff.as<int64_t>(), nsl, cp.scan_tmp, st);
-  int64_t last[2] = {0, 0};
-  MAK_HIP(hipMemcpyAsync(&last[0], J.soff.as<int64_t>() + (nsl - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  MAK_HIP(hipMemcpyAsync(&last[1], J.slen64.as<int64_t>() + (nsl - 1), sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  int64_t total = 0;
+  MAK_HIP(hipMemcpyAsync(&total, J.soff.as<int64_t>() + nsl, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));
-  J.sell_n = last[0] + last[1];
+  J.sell_n = total;
   J.scol.ensure(size_t(J.sell_n) * sizeof(int32_t));
   J.sw.ensure(size_t(J.sell_n) * sizeof(float));
   hipLaunchKernelGGL(k_sell_fill<float>, dim3(nbsl), dim3(256), 0, st, J.row_ptr.as<int64_t>(),

@@ -148,7 +148,7 @@ struct Lap {
   // soff[s] + 64 k + l), padded to the slice's longest row with the row's own
   // column and weight 0.
   int64_t nsl = 0, sell_n = 0;
-  DevBuf soff;     // int64 [nsl]
+  DevBuf soff;     // int64 [nsl + 1] (exclusive scan of 64 x slen, total last)
   DevBuf slen;     // int32 [nsl]
   DevBuf slen64;   // int64 [nsl] (scan input)
   DevBuf scol;     // int32 [sell_n]
@@ -293,6 +293,7 @@ double dev_reduce_max(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 double dev_reduce_min(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 double dev_reduce_sum(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 void dev_max_to(const double* x, int64_t n, double* out, DevBuf& tmp, hipStream_t st);
+// Exclusive scans: out holds n + 1 entries (out[n] = the total).
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
 
