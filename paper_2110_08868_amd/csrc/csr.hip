@@ -94,8 +94,9 @@ __global__ void k_fill(const FaceRec* faces, const FaceRec* ovf, const int64_t* 
 // does not occur earlier in the list, the rank of a column is the number of
 // distinct columns below it, and a column's weight is the sum of its faces'
 // weights in list order.  A row kept in the overflow region (more faces than
-// slots) is done the same way from memory.  (The weights stay in memory and
-// are read back from the cache for each column's faces.)
+// slots) is done the same way from memory.  (All loads of a row are issued
+// before the arithmetic: a load inside the per-column branch cost a memory
+// round trip per face.)
 constexpr int kRegFaces = 32;
 
 __device__ int32_t lap_row_mem(const FaceRec* f, int32_t nf, int32_t* col, float* wf, double* wd,
@@ -175,8 +176,12 @@ __global__ __launch_bounds__(256) void k_lap_fill_rows(const FaceRec* faces, con
     return;
   }
   int32_t jj[kRegFaces];
+  double ww[kRegFaces];
 #pragma unroll
-  for (int k = 0; k < kRegFaces; ++k) jj[k] = k < nf ? f[k].j : -1 - k;
+  for (int k = 0; k < kRegFaces; ++k) {
+    jj[k] = k < nf ? f[k].j : -1 - k;
+    ww[k] = k < nf ? f[k].w : 0.0;
+  }
   uint32_t firsts = 0;
 #pragma unroll
   for (int k = 0; k < kRegFaces; ++k) {
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(256) void k_lap_fill_rows(const FaceRec* faces, con
     double s = 0.0;
 #pragma unroll
     for (int m = 0; m < kRegFaces; ++m) {
-      if (jj[m] == jj[k]) s += f[m].w;  // the weights are read back (cached) only for the column's faces
+      s += jj[m] == jj[k] ? ww[m] : 0.0;  // in list order, as the unsorted sum
       rank += (((firsts >> m) & 1u) && jj[m] < jj[k]) ? 1 : 0;
     }
     const W ws = W(s);
