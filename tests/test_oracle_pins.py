@@ -671,3 +671,20 @@ def test_p11_exact_deposit_pins():
     e12 = np.abs(oracle.za_deposit(x, psi, 1.0, 0.5, 12, 6, scheme="ngp") - ex).mean()
     e24 = np.abs(oracle.za_deposit(x, psi, 1.0, 0.5, 24, 6, scheme="ngp") - ex).mean()
     assert e24 < 0.65 * e12
+
+
+def test_p11_exact_deposit_cell_subsets():
+    """The exact deposit restricted to cell subsets: the deposits of a
+    partition of the cells add up to the full deposit, and each part holds
+    exactly its cells' volumes (each cell's mass lands on the mesh whole)."""
+    x, psi = _random_case(n=3, seed=87, wscale=0.03)
+    L, ng, tau = 1.0, 6, 0.45
+    full = oracle.za_deposit_exact(x, psi, L, tau, ng)
+    idx = np.random.default_rng(87).permutation(len(x))
+    parts = [idx[:7], idx[7:19], idx[19:]]
+    got = sum(oracle.za_deposit_exact(x, psi, L, tau, ng, idx=p) for p in parts)
+    assert np.allclose(got, full, rtol=1e-12, atol=1e-13)
+    vols = oracle.cells(x, psi, L)["V"]
+    for p in parts:
+        r = oracle.za_deposit_exact(x, psi, L, tau, ng, idx=p)
+        assert r.sum() * (L / ng) ** 3 == pytest.approx(vols[p].sum(), rel=1e-12)
