@@ -302,8 +302,9 @@ typedef struct {
   double bytes;        /* compulsory HBM bytes of the algorithm */
 } mak_kernel_profile;
 
-/* flags: bit 0 = time kernels, bit 1 = count clip work.  Clears the
- * accumulated profile. */
+/* flags: bit 0 = time kernels, bit 1 = count clip work, bit 2 = time only
+ * the cell-pass kernels (the events around the others cost ~2 % of a solve).
+ * Clears the accumulated profile. */
 mak_status mak_profile_enable(mak_ctx* ctx, int32_t flags);
 /* Writes up to max_entries entries (HOST array, may be NULL) and returns the
  * number of entries available, or -1 on error.  Waits for pending events. */

@@ -290,9 +290,12 @@ class Context:
                                             fa.data_ptr(), self._stream()))
         return {"face_ptr": fp, "face_j": fj[:nf], "face_shift": fs[:nf], "face_area": fa[:nf]}
 
-    def profile_enable(self, timing: bool = True, counting: bool = False):
-        """Start (and clear) the kernel profile: event timing and/or counted work."""
-        self._check(self.lib.mak_profile_enable(self._h, (1 if timing else 0) | (2 if counting else 0)))
+    def profile_enable(self, timing: bool = True, counting: bool = False, cells_only: bool = False):
+        """Start (and clear) the kernel profile: event timing (of every main
+        kernel, or with cells_only of the cell-pass kernels alone) and/or
+        counted work."""
+        self._check(self.lib.mak_profile_enable(
+            self._h, (1 if timing else 0) | (2 if counting else 0) | (4 if cells_only else 0)))
 
     def profile_read(self) -> dict:
         """{kernel name: {launches, total_ms, units, flops, bytes}} since profile_enable."""

@@ -619,6 +619,7 @@ mak_status mak_profile_enable(mak_ctx* ctx, int32_t flags) {
     ctx->prof.clear();
     ctx->prof.timing = (flags & 1) != 0;
     ctx->prof.counting = (flags & 2) != 0;
+    ctx->prof.cells_only = (flags & 4) != 0;
   });
 }
 

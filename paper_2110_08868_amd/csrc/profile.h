@@ -21,6 +21,7 @@ struct ProfAcc {
 struct Profiler {
   bool timing = false;
   bool counting = false;
+  bool cells_only = false;  // time only the cell-pass kernels (names starting "clip")
   struct Pending {
     std::string name;
     hipEvent_t a, b;
@@ -86,7 +87,7 @@ struct ProfScope {
   bool open = false;
   ProfScope(const char* n, hipStream_t s, double u = 0, double by = 0)
       : p(g_prof), name(n), st(s), units(u), bytes(by) {
-    if (p && p->timing) {
+    if (p && p->timing && (!p->cells_only || name.compare(0, 4, "clip") == 0)) {
       a = p->take();
       MAK_HIP(hipEventRecord(a, st));
       open = true;
