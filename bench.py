@@ -443,8 +443,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "domain decomposition is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the domain "
+              "decomposition over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
