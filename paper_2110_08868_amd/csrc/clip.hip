@@ -867,7 +867,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     int rb = 0, gbase = 0, gcount = 1;
     uint64_t bmask = 0;
     int ubx = 0, uby = 0, ubz = 0;
+    int walk_iter = 0;
     while (!dead) {
+      // a trial another cell has already rejected: stop the walk (the pass is
+      // discarded); checked every 16 lists, a long walk of a far cell would
+      // otherwise hold the launch open
+      if (A.doom && (++walk_iter & 15) == 0 &&
+          __hip_atomic_load(A.doom, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        dead = true;
+        break;
+      }
       bool act = false;
       int32_t st = 0, cnt = 0, shp = 0;
       if (phase == 1 || phase == 2) {
