@@ -208,3 +208,30 @@ def test_box_size_and_masses(ctx):
     r2 = oracle.cells(x, p2, L)
     assert np.max(np.abs(r2["V"] - ms) / ms) <= 1e-9 * 1.001
     assert np.allclose(p2, psi0 - psi0.mean(), atol=1e-8 * (L / n) ** 2)
+
+
+# ------------------------------------------------------------ mixed precision
+@pytest.fixture(scope="module")
+def mctx():
+    import paper_2110_08868_amd as mak
+    c = mak.Context(0, "mixed", cg_rtol=1e-6)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("N,seed", [(1000, 21), (4033, 23), (64, 24)])
+def test_mixed_solve_vs_oracle(mctx, N, seed):
+    """The mixed path (FP32 clipping, float Laplacian weights held in slices
+    of 64 rows for the SpMV) on site counts that fill the last slice or not:
+    certified by the oracle's cells at the returned weights, and (N = 1000,
+    64) at the oracle's own solution."""
+    x = np.random.default_rng(seed).uniform(0.0, 1.0, (N, 3))
+    psi, C, D, info = gsolve(mctx, x, 1.0, 1e-7)
+    certificate(x, psi, 1.0, 1e-7)
+    if N <= 1000:
+        s = oracle.solve(x, 1.0, tol=1e-10)
+        dpsi = psi - s["psi"]
+        dpsi -= dpsi.mean()
+        D2 = N ** (-2.0 / 3.0)
+        print(f"  psi rms diff {np.sqrt(np.mean(dpsi ** 2)) / D2:.2e} D^2", flush=True)
+        assert np.sqrt(np.mean(dpsi ** 2)) <= 1e-5 * D2
