@@ -17,7 +17,8 @@
 // FMAs, so the two faces sharing an edge produce the same bits; a vertex
 // within 1e-14 L of the plane counts as on it, so lattice inputs whose faces
 // fall on voxel boundaries cut cleanly), the surviving polygons are
-// compacted, the crossing points are gathered and duplicates dropped, and
+// compacted, the crossing points are gathered (each face's exit point alone
+// when no vertex lies on the plane, else all of them, duplicates dropped), and
 // the new face is their polygon ordered by angle about their centroid.  S_i is clipped out of its box once; then it is cut
 // into the slabs of voxel columns along x, each slab into the columns along
 // y, and a column's voxels are the differences of the volumes below the
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
     };
     // pass 1: how many vertices each face keeps
     int m = 0;
-    bool out = false, on_all = nv > 0;
+    bool out = false, on_all = nv > 0, zero = false;
     if (nv > 0) {
       const double s0 = sd(X[0], Y[0], Z[0]);
       double sp = s0;
@@ -190,10 +191,16 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
         m += int(sp <= 0.0) + int((sp < 0.0 && sq > 0.0) || (sp > 0.0 && sq < 0.0));
         out = out || sp > 0.0;
         on_all = on_all && sp == 0.0;
+        zero = zero || sp == 0.0;
         sp = sq;
       }
     }
     if (ballot(out) == 0) return src;
+    // No vertex on the plane: every crossing point is the exit (inside to
+    // outside, in traversal order) of exactly one face and the entry of the
+    // face across its edge, so the exits alone list the new face's corners
+    // once each and need no deduplication.
+    const bool generic = ballot(zero) == 0;
     // a face lying in the plane is dropped: the new face replaces it
     const bool live = m >= 3 && !on_all;
     const int dest = wave_incl_scan_i(live ? 1 : 0) - (live ? 1 : 0);
@@ -246,7 +253,7 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
           const double t = sQ / (sQ - sP);
           const double Xx = fma(Px - Qx, t, Qx), Xy = fma(Py - Qy, t, Qy), Xz = fma(Pz - Qz, t, Qz);
           push(Xx, Xy, Xz);
-          add_cap(Xx, Xy, Xz);
+          if (!generic) add_cap(Xx, Xy, Xz);
         }
       }
     }
@@ -280,8 +287,9 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
         ky[h] = S.cy[t];
         kz[h] = S.cz[t];
         bool first = true;
-        for (int u = 0; u < t; ++u)
-          first = first && !(S.cx[u] == kx[h] && S.cy[u] == ky[h] && S.cz[u] == kz[h]);
+        if (!generic)
+          for (int u = 0; u < t; ++u)
+            first = first && !(S.cx[u] == kx[h] && S.cy[u] == ky[h] && S.cz[u] == kz[h]);
         keep[h] = first;
       }
     }
