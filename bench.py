@@ -140,8 +140,10 @@ def timed_solves(mak, x_dev, L, tol, precision, steps, warmup, cg_rtol, verbose=
     # the per-kernel breakdown of a solve
     ctx.profile_enable(timing=True, counting=False)
     ctx.solve(x_dev, L, tol)
-    prof["_breakdown"] = {k: round(v["total_ms"], 3) for k, v in ctx.profile_read().items()
+    bprof = ctx.profile_read()
+    prof["_breakdown"] = {k: round(v["total_ms"], 3) for k, v in bprof.items()
                           if not k.startswith("_") and isinstance(v, dict) and "total_ms" in v}
+    prof["_spmv"] = bprof.get("spmv")
     cprof = {}
     if counting:
         # counting solve (outside the timed region): work per clip launch
@@ -489,6 +491,8 @@ def main():
                   "abandoned_trials": infos[-1]["abandoned_trials"],
                   "cg_iters": infos[-1]["cg_iters_total"], "final_err": infos[-1]["final_err"]},
         "kernel_ms_one_solve": prof.get("_breakdown"),
+        # the second kernel of the solve (CG), against the HBM roofline
+        "spmv_roofline": hbm_roofline("spmv", prof["_spmv"], args.workload) if prof.get("_spmv") else None,
         "device_mem_used_gb": prof.get("_device_mem_used_gb"),
         "work_counters_per_solve": cprof.get("_counters"),
         "roofline": rl,
