@@ -299,6 +299,26 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp,
 
 struct PcgWork {
   DevBuf r, z, p, q, s, dinv, part, part2, scal;
+  // host side of the convergence checks: two pinned flags and their events
+  double* hflag = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  PcgWork() = default;
+  PcgWork(const PcgWork&) = delete;
+  PcgWork& operator=(const PcgWork&) = delete;
+  ~PcgWork() {
+    if (hflag) (void)hipHostFree(hflag);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void ensure_host() {
+    if (!hflag && hipHostMalloc(reinterpret_cast<void**>(&hflag), 2 * sizeof(double), 0) != hipSuccess) {
+      hflag = nullptr;
+      (void)hipGetLastError();
+      MAK_FAIL(MAK_ENOMEM, "pinned host allocation failed");
+    }
+    for (hipEvent_t& e : ev)
+      if (!e) MAK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
 };
 // Solve J x = b - mean(b) with Jacobi-preconditioned CG to
 // ||r|| <= rtol ||b - mean(b)||; x is overwritten (mean zero on return).  It

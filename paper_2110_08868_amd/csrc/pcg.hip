@@ -17,7 +17,7 @@ constexpr int MAXB = 1024;       // blocks of the grid-stride vector kernels
 constexpr int SPMV_MAXB = 8192;  // blocks of the SpMV (grid-stride over rows)
 
 // scalar slots (device doubles)
-enum { S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6 };
+enum { S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6, S_DONE = 7, S_ITER = 8 };
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum_d(v);
@@ -61,8 +61,10 @@ __global__ __launch_bounds__(TPB) void k_spmv_dot(const int64_t* __restrict__ rp
                                                   const W* __restrict__ w,
                                                   const double* __restrict__ diag,
                                                   const double* __restrict__ p, double* __restrict__ q,
-                                                  double* __restrict__ part, int64_t n) {
+                                                  double* __restrict__ part, const double* __restrict__ done,
+                                                  int64_t n) {
   __shared__ double sh[TPB / WAVE];
+  if (done[0] != 0.0) return;  // CG converged: iterations queued after it do nothing
   const int sub = threadIdx.x & (LPR - 1);
   const int xcd = int(blockIdx.x & 7u);
   const int64_t r0 = n * xcd / 8, r1 = n * (xcd + 1) / 8;
@@ -111,8 +113,10 @@ __global__ __launch_bounds__(TPB) void k_spmv_sell(const int64_t* __restrict__ s
                                                    const int32_t* __restrict__ col, const W* __restrict__ w,
                                                    const double* __restrict__ diag,
                                                    const double* __restrict__ p, double* __restrict__ q,
-                                                   double* __restrict__ part, int64_t n) {
+                                                   double* __restrict__ part, const double* __restrict__ done,
+                                                   int64_t n) {
   __shared__ double sh[TPB / WAVE];
+  if (done[0] != 0.0) return;  // CG converged: iterations queued after it do nothing
   const int64_t nsl = (n + 63) / 64;
   const int lane = threadIdx.x & 63;
   const int xcd = int(blockIdx.x & 7u);
@@ -180,6 +184,7 @@ __global__ __launch_bounds__(TPB) void k_cg_update(double* __restrict__ x, doubl
                                                    const double* __restrict__ scal, double* __restrict__ part,
                                                    int64_t n) {
   __shared__ double sh[TPB / WAVE];
+  if (scal[S_DONE] != 0.0) return;  // CG converged
   const double alpha = scal[S_ALPHA], beta = scal[S_BETA];
   double aru = 0.0, arr = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * TPB + threadIdx.x; i < n; i += int64_t(gridDim.x) * TPB) {
@@ -206,11 +211,15 @@ __global__ __launch_bounds__(TPB) void k_cg_update(double* __restrict__ x, doubl
 // gamma' = r.u, rr = r.r (from the update's partials), delta = w.u (from the
 // SpMV's); beta = gamma' / gamma, alpha = gamma' / (delta - beta gamma' /
 // alpha) (first: beta = 0, alpha = gamma' / delta).  Fixed tree, one block.
+// After an iteration (first == 0) it counts it and raises S_DONE once
+// rr <= stop: the kernels of the iterations already queued then return at
+// once, so the host need not wait for each residual.
 constexpr int SCAL_TPB = 1024;
 __global__ __launch_bounds__(SCAL_TPB) void k_cg_scalars(const double* __restrict__ pu, int nu,
                                                          const double* __restrict__ ps, int nsp,
-                                                         double* __restrict__ scal, int first) {
+                                                         double* __restrict__ scal, int first, double stop) {
   __shared__ double sh[3][SCAL_TPB / WAVE];
+  if (scal[S_DONE] != 0.0) return;
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = threadIdx.x; i < nu; i += SCAL_TPB) {
     a += pu[2 * i];
@@ -243,6 +252,10 @@ __global__ __launch_bounds__(SCAL_TPB) void k_cg_scalars(const double* __restric
     scal[S_BETA] = beta;
     scal[S_GAMMA] = gn;
     scal[S_RR] = b;
+    if (!first) {
+      scal[S_ITER] += 1.0;
+      if (b <= stop) scal[S_DONE] = 1.0;
+    }
   }
 }
 
@@ -342,6 +355,7 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
   double* scal = w.scal.as<double>();
   const unsigned nb = vec_blocks(n);
   const unsigned nbe = unsigned(ceil_div(n, 256));
+  MAK_HIP(hipMemsetAsync(scal + S_DONE, 0, 2 * sizeof(double), st));  // S_DONE, S_ITER
 
   // q = J v with the partials of q . v in part2
   auto spmv = [&](const double* v, double* qv) {
@@ -353,10 +367,11 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
     if (J.f32)
       hipLaunchKernelGGL(k_spmv_sell<float>, dim3(nbs), dim3(TPB), 0, st, J.soff.as<int64_t>(),
                          J.slen.as<int32_t>(), J.scol.as<int32_t>(), J.sw.as<float>(), J.diag.as<double>(), v,
-                         qv, part2, n);
+                         qv, part2, scal + S_DONE, n);
     else
       hipLaunchKernelGGL(k_spmv_dot<double>, dim3(nbs), dim3(TPB), 0, st, J.row_ptr.as<int64_t>(),
-                         J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), v, qv, part2, n);
+                         J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), v, qv, part2,
+                         scal + S_DONE, n);
   };
   hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.diag.as<double>(), dinv, n);
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, b, part, n);
@@ -378,7 +393,8 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
     hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(TPB), 0, st, b, scal, nullptr, x, r, u, p, sv, dinv, part,
                        n);
   spmv(u, wv);
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 1);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 1,
+                     -1.0);
   MAK_HIP(hipGetLastError());
   MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));
@@ -386,25 +402,39 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
   if (!(bb > 0.0)) return 0;
   const double stop = rtol * rtol * bb;
   if (hb[S_RR] <= stop) return 0;
-  int it = 0;
-  for (; it < max_iter; ++it) {
+  // The loop queues iterations ahead of the device; every 8 iterations it
+  // copies the convergence flag to pinned host memory behind an event and
+  // looks at the copy queued 8 iterations earlier (waiting for it only when
+  // the device is that far behind), so the queue never drains.
+  w.ensure_host();
+  int slot = 0, pending = -1;
+  bool done = false;
+  for (int it = 0; it < max_iter && !done; ++it) {
     {
       ProfScope ps("pcg_update", st, double(n), 96.0 * double(n));
       ps.flops = 14.0 * double(n);
       hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(TPB), 0, st, x, r, u, p, sv, wv, dinv, scal, part, n);
     }
     spmv(u, wv);
-    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 0);
-    if ((it & 7) == 7 || it + 1 == max_iter) {
-      double rr = 0;
-      MAK_HIP(hipMemcpyAsync(&rr, scal + S_RR, sizeof(double), hipMemcpyDeviceToHost, st));
-      MAK_HIP(hipStreamSynchronize(st));
-      if (rr <= stop) {
-        ++it;
-        break;
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 0,
+                       stop);
+    if ((it & 7) == 7) {
+      if (pending >= 0) {
+        MAK_HIP(hipEventSynchronize(w.ev[pending]));
+        done = w.hflag[pending] != 0.0;
+      }
+      if (!done) {
+        MAK_HIP(hipMemcpyAsync(&w.hflag[slot], scal + S_DONE, sizeof(double), hipMemcpyDeviceToHost, st));
+        MAK_HIP(hipEventRecord(w.ev[slot], st));
+        pending = slot;
+        slot ^= 1;
       }
     }
   }
+  double tail[2] = {0.0, 0.0};
+  MAK_HIP(hipMemcpyAsync(tail, scal + S_DONE, sizeof(tail), hipMemcpyDeviceToHost, st));
+  MAK_HIP(hipStreamSynchronize(st));
+  const int it = int(tail[1]);
   MAK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, x, part, n);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_TMP), 0);
