@@ -235,3 +235,57 @@ def test_mixed_solve_vs_oracle(mctx, N, seed):
         D2 = N ** (-2.0 / 3.0)
         print(f"  psi rms diff {np.sqrt(np.mean(dpsi ** 2)) / D2:.2e} D^2", flush=True)
         assert np.sqrt(np.mean(dpsi ** 2)) <= 1e-5 * D2
+
+
+def test_full_size_clustered_128():
+    """The timed workload itself: the clustered 128^3 input (2.1 M sites, 2000
+    clumps), solved by the mixed path to 1e-6 with the CG tolerance 1e-3, as
+    timed.  Certified on 48 sampled cells by the oracle's own cells at the
+    returned weights; at those weights the float64 pass matches the oracle
+    on the sample to the float64 bar and the mixed pass to 1e-6; the solve's
+    centroids and displacements are those of the oracle's cells; every
+    Hessian row sums to zero."""
+    import torch
+    import paper_2110_08868_amd as mak
+    from tests.parity import compare_cells, gpu_faces, spacing
+    n = 128
+    N = n ** 3
+    x = workloads.clustered(n, rms=3.0, smooth=1.0, frac=0.2, n_clumps=2000, a=0.5, seed=3)
+    xd = torch.from_numpy(x).cuda()
+    sctx = mak.Context(0, "mixed", cg_rtol=1e-3)
+    try:
+        psi_d, C_d, D_d, info = sctx.solve(xd, 1.0, 1e-6)
+    finally:
+        sctx.close()
+    print(f"  solve 128^3 clustered: {info}", flush=True)
+    assert info["final_err"] <= 1e-6
+    psi = psi_d.cpu().numpy()
+    C = C_d.cpu().numpy()
+    Dp = D_d.cpu().numpy()
+    idx = np.sort(np.random.default_rng(11).choice(N, 48, replace=False))
+    res = oracle.cells(x, psi, 1.0, idx=idx, threads=16)
+    m = 1.0 / N
+    err = float(np.max(np.abs(res["V"] - m)) / m)
+    print(f"  oracle volume error at the GPU weights (48 cells): {err:.2e}", flush=True)
+    assert err <= 1e-6
+    sp = spacing(N, 1.0)
+    co = np.mod(x[idx] + res["M"] / res["V"][:, None], 1.0)
+    for name, got in (("centroids", C[idx]), ("displacements", x[idx] - Dp[idx])):
+        dc = got - co
+        dc -= np.round(dc)
+        print(f"  solve {name} vs oracle: {np.abs(dc).max() / sp:.2e} spacings", flush=True)
+        assert np.abs(dc).max() <= 1e-6 * sp
+    for prec, bar in (("fp64", 1e-10), ("mixed", 1e-6)):
+        c = mak.Context(0, prec)
+        try:
+            V, Cc, cinfo = c.laguerre_cells(xd, psi_d, 1.0)
+            F = gpu_faces(c)
+            rp, col, val = (t.cpu().numpy() for t in c.hessian())
+        finally:
+            c.close()
+        rep = compare_cells(x, psi, 1.0, V.cpu().numpy(), Cc.cpu().numpy(), F, res=res,
+                            vol_rel=bar, cen_rel=bar, area_rel=bar)
+        print(f"  {prec} pass at the solution vs oracle (48 cells): {rep}", flush=True)
+        rs = np.add.reduceat(val, rp[:-1])
+        assert np.abs(rs).max() <= 1e-12 * np.abs(val).max()
+        assert abs(V.sum().item() - 1.0) <= 1e-11
