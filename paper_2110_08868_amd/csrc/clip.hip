@@ -171,6 +171,16 @@ __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
   return key;
 }
 
+// Smallest key of the wave: DPP reductions within each row of 16 lanes,
+// then the four row results.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, uint32_t(dpp_i<kDppXor1>(int(v))));
+  v = min(v, uint32_t(dpp_i<kDppXor2>(int(v))));
+  v = min(v, uint32_t(dpp_i<kDppHalfMirror>(int(v))));
+  v = min(v, uint32_t(dpp_i<kDppMirror>(int(v))));
+  return min(min(readlane_u(v, 0), readlane_u(v, 16)), min(readlane_u(v, 32), readlane_u(v, 48)));
+}
+
 // Offset of the t-th block of the Chebyshev shell of radius r (r >= 1).
 __host__ __device__ constexpr void shell_offset_calc(int r, int t, int& ox, int& oy, int& oz) {
   if (r == 0) {
@@ -782,7 +792,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         ns = __popcll(ballot(may));
         if (ns == 0) continue;
       }
-      key = wave_sort_u32(key);
+      if (ns <= 2) {
+        // one or two candidates (the common case): their order from wave
+        // minima, without the 21 exchange stages of the sort (the keys are
+        // distinct, the lane being their low bits)
+        const uint32_t k0 = wave_min_u32(key);
+        const uint32_t k1 = ns == 2 ? wave_min_u32(key == k0 ? 0xffffffffu : key) : 0xffffffffu;
+        key = lane == 0 ? k0 : (lane == 1 ? k1 : 0xffffffffu);
+      } else {
+        key = wave_sort_u32(key);
+      }
       uint64_t tc0 = 0;
       if (STATS) tc0 = clock_stamp();
       // park the batch in LDS (frees its registers during the serial loop)
