@@ -104,6 +104,17 @@ typedef struct {
   int32_t reserved;
 } mak_cells_info;
 
+/* The Hessian of a cell pass in CSR form, as returned by mak_laguerre_cells:
+ * library-owned DEVICE arrays, valid until the next mak_laguerre_cells or
+ * mak_destroy on the same context; the caller must not write or free them. */
+typedef struct {
+  int64_t n_rows;          /* N */
+  int64_t nnz;             /* nonzeros, diagonal included */
+  const int64_t* row_ptr;  /* DEVICE [n_rows + 1] */
+  const int32_t* col;      /* DEVICE [nnz], sorted within each row */
+  const double* val;       /* DEVICE [nnz] */
+} mak_csr;
+
 typedef struct mak_ctx mak_ctx;
 
 /* Create a context on HIP device `device` with options `opt` (NULL = the
@@ -123,14 +134,19 @@ const char* mak_last_error(const mak_ctx* ctx);
  *   volumes    DEVICE (N,) float64 out: |V_i| (0 for an empty cell)
  *   centroids  DEVICE (N, 3) float64 out: centroid of V_i wrapped into
  *              [0, L)^3 (x_i for an empty cell)
+ *   hessian    HOST, may be NULL: filled with the Hessian of this pass in
+ *              CSR form (library-owned, see mak_csr; original site order)
  *   info       HOST, may be NULL: counters of this pass
- * The pass also builds the Hessian J = dV/dpsi (= minus the Hessian of K):
+ * The pass builds the Hessian J = dV/dpsi (= minus the Hessian of K, the
+ * derivative of the cell volumes, the gradient of Eq. SDK, in the weights):
  * J_ij = -sum over the faces between cell i and images of site j of
- * area / |x_i - x_j^image|, J_ii = -sum_j J_ij; fetch it with
- * mak_hessian_copy.  Faces of a cell with its own images do not enter J. */
+ * area / |x_i - x_j^image|, J_ii = -sum_j J_ij.  Faces of a cell with its own
+ * images do not enter J.  mak_hessian_copy copies it into caller memory.
+ * Returns after enqueueing plus one device-to-host read of the nonzero count
+ * (the outputs are then complete in stream order). */
 mak_status mak_laguerre_cells(mak_ctx* ctx, const double* points, const double* psi,
                               int64_t N, double L, double* volumes, double* centroids,
-                              mak_cells_info* info, void* stream);
+                              mak_csr* hessian, mak_cells_info* info, void* stream);
 
 /* Copy the Hessian of the last mak_laguerre_cells call on `ctx` as CSR with
  * sorted columns (diagonal included):
@@ -319,11 +335,16 @@ mak_status mak_profile_counters(mak_ctx* ctx, double* out);
 
 /* ---- serving: many reconstruction requests on one device ----
  * A server owns `max_slots` worker slots, each with its own context (device
- * workspace kept resident between requests) and HIP stream.  Requests are
- * admitted first-in first-out when a slot is free and their memory estimate
- * (mak_solve_memory_estimate) fits in what `mem_budget_bytes` has left;
- * requests submitted while others run start as soon as slots and memory
- * free up (continuous batching).  The cell passes of all requests that need
+ * workspace kept resident between requests) and HIP stream.  The budget is
+ * charged with what the slots hold: a slot's workspace, sized for the
+ * largest request it has served since it was last emptied (by the memory
+ * estimate, mak_solve_memory_estimate), stays charged while the slot is
+ * idle.  Requests are admitted first-in first-out when a slot is free and
+ * the total held after the head request (that slot's workspace resized for
+ * it: kept when the request needs at least half of it, replaced otherwise)
+ * fits in `mem_budget_bytes`; when no idle slot can take the head request,
+ * idle slots give their workspace back.  Requests submitted while others run
+ * start as soon as slots and memory free up (continuous batching).  The cell passes of all requests that need
  * one at the same time are packed into shared clip launches (up to 8 point
  * sets per launch) by the server's pass batcher; the Newton / PCG work of
  * each request runs on its slot's stream and overlaps on the device.
@@ -339,6 +360,8 @@ typedef struct {
   int64_t batched_passes;               /* cell passes run in them */
   int32_t max_batch;                    /* most passes in one of them */
   int32_t reserved;
+  int64_t releases;                     /* idle slot workspaces given back to
+                                           admit the head request */
 } mak_server_info;
 
 /* opt: solver options of every request (NULL = defaults); mem_budget_bytes
@@ -368,6 +391,14 @@ void mak_server_destroy(mak_server* s);
 
 /* Device memory a solve of N sites needs at most (bytes), for admission. */
 size_t mak_solve_memory_estimate(int64_t N, int32_t precision);
+
+/* Device memory the library holds (HOST out pointers, either may be NULL):
+ * *live = bytes allocated now by all contexts and servers of the process,
+ * *peak = the most held at once since the last reset (updated at every
+ * allocation).  reset_peak nonzero: afterwards the peak restarts from the
+ * bytes held now.  Measured, not estimated: the sum of the library's own
+ * device allocations (torch's or the caller's tensors are not included). */
+void mak_device_bytes(size_t* live, size_t* peak, int32_t reset_peak);
 
 #ifdef __cplusplus
 }

@@ -21,7 +21,9 @@ Contents
   za_deposit(...)        Zel'dovich advection of the cells' mass elements
                          and their deposit on an Eulerian mesh;
                          za_deposit_exact: the moved cells clipped against
-                         the voxels (the limit of many elements).
+                         the voxels (the limit of many elements);
+                         mesh_assign: NGP / cloud-in-cell assignment of
+                         point masses to the mesh.
   power_spectrum(f, L)   shell-averaged power spectrum of a periodic mesh
                          field (FFT estimator, optional window and contrast).
   exact                  exact-rational mini oracle (Python fractions).
@@ -29,7 +31,7 @@ Contents
 from .cells import cells, cell_faces_dict, load_library
 from .legendre import legendre
 from .power import power_spectrum
-from .deposit import za_deposit, za_deposit_exact
+from .deposit import za_deposit, za_deposit_exact, mesh_assign
 from .newton import (
     hessian_dense,
     hessian_coo,
@@ -48,6 +50,7 @@ __all__ = [
     "power_spectrum",
     "za_deposit",
     "za_deposit_exact",
+    "mesh_assign",
     "hessian_dense",
     "hessian_coo",
     "kantorovich",

@@ -35,9 +35,17 @@ def za_deposit(x, psi, L: float, tau: float, n_lag: int, ng: int, scheme: str = 
     _, _, disp = legendre(x, psi, L, q)
     y = np.mod(q + tau * disp, L)
     y[y >= L] = 0.0
+    return mesh_assign(y, (L / n_lag) ** 3, L, ng, scheme)
+
+
+def mesh_assign(y, m: float, L: float, ng: int, scheme: str = "cic"):
+    """Density (ng, ng, ng) of point masses m at positions y (Q, 3) in
+    [0, L)^3 on the periodic mesh of nodes a L / ng: nearest grid point, or
+    cloud in cell (the node below the point on each axis takes 1 - f of the
+    mass, the node above f, f the point's fractional node coordinate; the
+    three axis weights multiply).  Mass per node over the node volume."""
     H = L / ng
-    u = y / H
-    m = (L / n_lag) ** 3
+    u = np.asarray(y, dtype=np.float64) / H
     rho = np.zeros(ng ** 3)
     if scheme == "ngp":
         i = np.mod(np.floor(u + 0.5).astype(np.int64), ng)

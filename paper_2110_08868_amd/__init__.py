@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "mak_profile_enable", "mak_profile_read",
     "mak_profile_counters", "mak_server_create", "mak_server_submit", "mak_server_poll",
     "mak_server_wait", "mak_server_release", "mak_server_stats", "mak_server_last_error",
-    "mak_server_destroy",
+    "mak_server_destroy", "mak_device_bytes",
 ]
 
 STATUS = {0: "MAK_OK", 1: "MAK_EINVAL", 2: "MAK_ENOMEM", 3: "MAK_EDEGENERATE",
@@ -100,7 +100,13 @@ class _ServerStats(ctypes.Structure):
         ("peak_used_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
         ("pass_batches", ctypes.c_int64), ("batched_passes", ctypes.c_int64),
         ("max_batch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("releases", ctypes.c_int64),
     ]
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
 def _as_dict(s) -> dict:
@@ -127,7 +133,7 @@ def load_library():
     lib.mak_destroy.restype = None
     lib.mak_last_error.argtypes = [P]
     lib.mak_last_error.restype = ctypes.c_char_p
-    lib.mak_laguerre_cells.argtypes = [P, P, P, I64, D, P, P, P, P]
+    lib.mak_laguerre_cells.argtypes = [P, P, P, I64, D, P, P, P, P, P]
     lib.mak_laguerre_cells.restype = ctypes.c_int
     lib.mak_hessian_copy.argtypes = [P, P, P, P, P]
     lib.mak_hessian_copy.restype = ctypes.c_int
@@ -152,6 +158,8 @@ def load_library():
     lib.mak_solve_from.restype = ctypes.c_int
     lib.mak_solve_memory_estimate.argtypes = [I64, I32]
     lib.mak_solve_memory_estimate.restype = ctypes.c_size_t
+    lib.mak_device_bytes.argtypes = [P, P, I32]
+    lib.mak_device_bytes.restype = None
     lib.mak_profile_enable.argtypes = [P, I32]
     lib.mak_profile_enable.restype = ctypes.c_int
     lib.mak_profile_read.argtypes = [P, P, I32]
@@ -187,6 +195,14 @@ def default_options() -> dict:
 
 def memory_estimate(n: int, precision: str = "fp64") -> int:
     return int(load_library().mak_solve_memory_estimate(int(n), PRECISION[precision]))
+
+
+def device_bytes(reset_peak: bool = False):
+    """(live, peak): device bytes the library holds now and the most it held
+    at once since the last reset (its own allocations, all contexts)."""
+    live, peak = ctypes.c_size_t(), ctypes.c_size_t()
+    load_library().mak_device_bytes(ctypes.byref(live), ctypes.byref(peak), 1 if reset_peak else 0)
+    return int(live.value), int(peak.value)
 
 
 def _torch():
@@ -260,11 +276,19 @@ class Context:
         V = torch.empty(n, dtype=torch.float64, device=self.device)
         C = torch.empty((n, 3), dtype=torch.float64, device=self.device)
         info = _CellsInfo()
+        csr = _Csr()
         self._check(self.lib.mak_laguerre_cells(self._h, x.data_ptr(), w.data_ptr(), n, float(L),
-                                                V.data_ptr(), C.data_ptr(), ctypes.byref(info),
-                                                self._stream()))
+                                                V.data_ptr(), C.data_ptr(), ctypes.byref(csr),
+                                                ctypes.byref(info), self._stream()))
         self._last_n, self._last_nnz, self._last_faces = n, info.nnz, info.faces
+        self._last_csr = {name: getattr(csr, name) for name, _ in csr._fields_}
         return V, C, _as_dict(info)
+
+    def hessian_view(self) -> dict:
+        """The library-owned CSR that the last mak_laguerre_cells returned:
+        n_rows, nnz and the DEVICE addresses row_ptr, col, val (valid until
+        the next cell pass on this context)."""
+        return dict(self._last_csr)
 
     def hessian(self):
         """CSR (row_ptr int64, col int32, val float64) of J = dV/dpsi of the

@@ -238,8 +238,8 @@ const char* mak_last_error(const mak_ctx* ctx) {
 }
 
 mak_status mak_laguerre_cells(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
-                              double L, double* volumes, double* centroids, mak_cells_info* info,
-                              void* stream) {
+                              double L, double* volumes, double* centroids, mak_csr* hessian,
+                              mak_cells_info* info, void* stream) {
   if (!ctx) return MAK_EINVAL;
   return guarded(ctx, [&] {
     check_args(N, L);
@@ -259,6 +259,13 @@ mak_status mak_laguerre_cells(mak_ctx* ctx, const double* points, const double* 
     scatter_cells_outputs(ctx->ps, ctx->cp.vol.as<double>(), ctx->cp.mom.as<double>(), volumes,
                           centroids, st);
     ctx->cells_valid = true;
+    if (hessian) {
+      hessian->n_rows = ctx->J.n;
+      hessian->nnz = ctx->J.nnz;
+      hessian->row_ptr = ctx->J.row_ptr.as<const int64_t>();
+      hessian->col = ctx->J.col.as<const int32_t>();
+      hessian->val = ctx->J.val.as<const double>();
+    }
     if (info) {
       std::memset(info, 0, sizeof(*info));
       info->empty_cells = fs.empty;
@@ -656,6 +663,16 @@ size_t mak_solve_memory_estimate(int64_t N, int32_t precision) {
   (void)precision;
   if (N < 1) return 0;
   return size_t(N) * solve_bytes_per_site(N) + (size_t(64) << 20);
+}
+
+void mak_device_bytes(size_t* live, size_t* peak, int32_t reset_peak) {
+  const int64_t l = mak::g_dev_bytes.live.load();
+  if (live) *live = size_t(l > 0 ? l : 0);
+  if (peak) {
+    const int64_t p = mak::g_dev_bytes.peak.load();
+    *peak = size_t(p > 0 ? p : 0);
+  }
+  if (reset_peak) mak::g_dev_bytes.peak.store(mak::g_dev_bytes.live.load());
 }
 
 }  // extern "C"

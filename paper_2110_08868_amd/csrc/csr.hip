@@ -291,7 +291,7 @@ void build_csr(const PointSet& ps, CellPass& cp, Csr& J, bool original_space, hi
                      perm, J.rowcnt.as<int64_t>(), original_space ? J.rowcnt.as<int64_t>() + n : nullptr,
                      n, 1);
   MAK_HIP(hipGetLastError());
-  exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr.as<int64_t>(), n, cp.scan_tmp, st);
+  exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr, n, cp.scan_tmp, st);
   int64_t nnz = 0;
   MAK_HIP(hipMemcpyAsync(&nnz, J.row_ptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));
@@ -318,7 +318,7 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
   hipLaunchKernelGGL(k_lap_count, dim3(nb), dim3(256), 0, st, fst.faces.as<FaceRec>(), fst.ovf.as<FaceRec>(),
                      fst.fbase.as<int64_t>(), fst.fslot, cp.nface.as<int32_t>(), J.rowcnt.as<int64_t>(), n);
   MAK_HIP(hipGetLastError());
-  exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr.as<int64_t>(), n, cp.scan_tmp, st);
+  exclusive_scan_i64(J.rowcnt.as<int64_t>(), J.row_ptr, n, cp.scan_tmp, st);
   int64_t nnz = 0;
   MAK_HIP(hipMemcpyAsync(&nnz, J.row_ptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));
@@ -350,7 +350,7 @@ void build_lap(const PointSet& ps, CellPass& cp, Lap& J, bool f32, hipStream_t s
   hipLaunchKernelGGL(k_sell_len, dim3(nbsl), dim3(256), 0, st, J.rowcnt.as<int64_t>(), J.slen.as<int32_t>(),
                      J.slen64.as<int64_t>(), n, nsl);
   MAK_HIP(hipGetLastError());
-  exclusive_scan_i64(J.slen64.as<int64_t>(), J.soff.as<int64_t>(), nsl, cp.scan_tmp, st);
+  exclusive_scan_i64(J.slen64.as<int64_t>(), J.soff, nsl, cp.scan_tmp, st);
   int64_t total = 0;
   MAK_HIP(hipMemcpyAsync(&total, J.soff.as<int64_t>() + nsl, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));
@@ -367,7 +367,7 @@ int64_t count_faces(const PointSet& ps, CellPass& cp, Csr& J, DevBuf& face_ptr, 
   // build_csr(original_space) left the per-row face counts after the row counts
   const int64_t n = ps.N;
   face_ptr.ensure(size_t(n + 1) * sizeof(int64_t));
-  exclusive_scan_i64(J.rowcnt.as<int64_t>() + n, face_ptr.as<int64_t>(), n, cp.scan_tmp, st);
+  exclusive_scan_i64(J.rowcnt.as<int64_t>() + n, face_ptr, n, cp.scan_tmp, st);
   int64_t nf = 0;
   MAK_HIP(hipMemcpyAsync(&nf, face_ptr.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));

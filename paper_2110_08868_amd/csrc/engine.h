@@ -2,6 +2,7 @@
 // pass kernels (grid build, clip, CSR assembly, PCG).
 #pragma once
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -10,6 +11,21 @@
 struct mak_ctx;
 
 namespace mak {
+
+// Device bytes held by all DevBufs of the process (every context and
+// server), and the most held at once since the last reset, updated at every
+// allocation: what the library really holds, beside the estimates the server
+// admits requests by.
+struct DevBytes {
+  std::atomic<int64_t> live{0}, peak{0};
+  void add(int64_t b) {
+    const int64_t now = live.fetch_add(b) + b;
+    int64_t p = peak.load();
+    while (now > p && !peak.compare_exchange_weak(p, now)) {
+    }
+  }
+};
+inline DevBytes g_dev_bytes;
 
 // A growable device buffer owned by the engine.
 struct DevBuf {
@@ -20,7 +36,10 @@ struct DevBuf {
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      g_dev_bytes.add(-int64_t(cap));
+    }
     p = nullptr;
     cap = 0;
   }
@@ -34,6 +53,7 @@ struct DevBuf {
       MAK_FAIL(MAK_ENOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
     }
     cap = want;
+    g_dev_bytes.add(int64_t(want));
   }
   template <class T>
   T* as() const {
@@ -293,9 +313,10 @@ double dev_reduce_max(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 double dev_reduce_min(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 double dev_reduce_sum(const double* x, int64_t n, DevBuf& tmp, hipStream_t st);
 void dev_max_to(const double* x, int64_t n, double* out, DevBuf& tmp, hipStream_t st);
-// Exclusive scans: out holds n + 1 entries (out[n] = the total).
-void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
-void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st);
+// Exclusive scans into out[0..n] (out[n] = the total); throws when `out` holds
+// fewer than n + 1 entries.
+void exclusive_scan_i64(const int64_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st);
+void exclusive_scan_i32(const int32_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st);
 
 struct PcgWork {
   DevBuf r, z, p, q, s, dinv, part, part2, scal;

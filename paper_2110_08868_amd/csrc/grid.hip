@@ -257,7 +257,7 @@ void build_pointset(PointSet& ps, const double* points, const double* psi, int64
   hipLaunchKernelGGL(k_stage, dim3(nb), dim3(256), 0, st, points, psi, N, L, ps.g.h, ps.g.Gn,
                      ps.g.Gb, xw, ps.key.as<int32_t>(), ps.rank.as<int32_t>(),
                      ps.count.as<int32_t>(), status);
-  exclusive_scan_i32(ps.count.as<int32_t>(), ps.cell_start.as<int32_t>(), G, ps.tmp, st);
+  exclusive_scan_i32(ps.count.as<int32_t>(), ps.cell_start, G, ps.tmp, st);
   hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(256), 0, st, ps.key.as<int32_t>(),
                      ps.rank.as<int32_t>(), ps.cell_start.as<int32_t>(), ps.perm.as<int32_t>(), N);
   hipLaunchKernelGGL(k_cell_sort, dim3(unsigned(ceil_div(G, 256))), dim3(256), 0, st,

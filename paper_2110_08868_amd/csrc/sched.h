@@ -1,13 +1,17 @@
 // Host-side scheduling of the server, free of device code so that it can be
 // exercised on the CPU with a fake executor.
 //
-// RequestScheduler: a FIFO queue feeding `slots` worker threads.  The head
-// request is admitted when a worker is free and its memory estimate fits in
-// what the budget has left (no overtaking: a large head request is not
-// starved by smaller ones behind it); a request submitted while others run
-// starts as soon as a worker and memory free up.  Each worker owns one
-// executor for its whole life (the device workspace of a slot stays
-// resident between requests).
+// RequestScheduler: a FIFO queue feeding `slots` worker threads.  Each
+// worker owns one executor for its whole life, and an executor keeps its
+// device workspace between requests, so the budget is charged with what the
+// executors hold, not only with what is running: a slot's holding is charged
+// from the request that sizes it until the executor releases it.  The head
+// request is admitted on a free worker when the total held after it (that
+// worker's holding replaced by what it will hold once sized for the request)
+// fits in the budget; an idle worker whose holding keeps the head request
+// out releases its workspace.  No overtaking: a large head request is not
+// starved by smaller ones behind it.  A request submitted while others run
+// starts as soon as a worker and memory free up.
 //
 // Batcher: solves post jobs (cell passes) and block; one thread takes every
 // job posted so far at once (optionally after a short window in which more
@@ -37,7 +41,8 @@ struct Stats {
   int64_t submitted = 0, completed = 0, queued = 0;
   int32_t active = 0, peak_active = 0;
   int64_t admitted_while_busy = 0;
-  size_t used = 0, peak_used = 0, budget = 0;
+  int64_t releases = 0;  // idle workspaces released to admit the head request
+  size_t used = 0, peak_used = 0, budget = 0;  // bytes held by the executors
 };
 
 template <class P>
@@ -52,14 +57,21 @@ struct Ticket {
   int32_t slot = -1;
 };
 
-// Exec: constructed once per worker; `int run(P&, std::string& err, int64_t
-// est)` runs one request and returns 0 or an error code.
+// Exec: constructed once per worker.
+//   int run(P&, std::string& err, int64_t est)  runs one request, returns 0 or
+//                                               an error code;
+//   static size_t hold_after(size_t est, size_t held)
+//                                               bytes an executor holding
+//                                               `held` holds once it has run
+//                                               a request of estimate est;
+//   void release()                              frees what it holds (idle).
 template <class P, class Exec>
 class RequestScheduler {
  public:
   using MakeExec = std::function<std::unique_ptr<Exec>(int32_t slot)>;
 
-  RequestScheduler(size_t budget, int32_t slots, MakeExec make) : make_(std::move(make)) {
+  RequestScheduler(size_t budget, int32_t slots, MakeExec make)
+      : make_(std::move(make)), held_(size_t(slots), 0), idle_(size_t(slots), false) {
     budget_ = budget ? budget : ~size_t(0);
     for (int32_t k = 0; k < slots; ++k) workers_.emplace_back([this, k] { worker(k); });
   }
@@ -121,6 +133,7 @@ class RequestScheduler {
     s.active = active_;
     s.peak_active = peak_active_;
     s.admitted_while_busy = overlapped_;
+    s.releases = releases_;
     s.used = used_;
     s.peak_used = peak_used_;
     s.budget = budget_;
@@ -138,20 +151,61 @@ class RequestScheduler {
   }
 
  private:
+  // Whether the idle worker `k` can take the head request without releasing
+  // anything, and what it would hold then.
+  bool fits(int32_t k, size_t* after) const {
+    const size_t a = Exec::hold_after(queue_.front()->est, held_[size_t(k)]);
+    if (after) *after = a;
+    return used_ - held_[size_t(k)] + a <= budget_;
+  }
+  bool some_idle_fits() const {
+    for (size_t k = 0; k < idle_.size(); ++k)
+      if (idle_[k] && fits(int32_t(k), nullptr)) return true;
+    return false;
+  }
+
   void worker(int32_t slot) {
     std::unique_ptr<Exec> ex = make_(slot);
+    const size_t k = size_t(slot);
     for (;;) {
       std::shared_ptr<Ticket<P>> t;
       {
         std::unique_lock<std::mutex> lk(mu_);
-        cv_work_.wait(lk, [&] {
-          return (!queue_.empty() && used_ + queue_.front()->est <= budget_) ||
-                 (stopping_ && queue_.empty());
-        });
-        if (queue_.empty()) break;  // stopping with nothing left
+        idle_[k] = true;
+        size_t after = 0;
+        for (;;) {
+          if (queue_.empty()) {
+            if (stopping_) break;
+            cv_work_.wait(lk);
+            continue;
+          }
+          if (fits(slot, &after)) break;
+          if (held_[k] > 0 && ex && !some_idle_fits()) {
+            // no idle worker can take the head request as things are, and
+            // what this one holds keeps it out: give the workspace back
+            const size_t h = held_[k];
+            idle_[k] = false;  // not a candidate while it releases
+            lk.unlock();
+            ex->release();
+            lk.lock();
+            idle_[k] = true;
+            used_ -= h;
+            held_[k] = 0;
+            ++releases_;
+            cv_work_.notify_all();
+            continue;
+          }
+          cv_work_.wait(lk);
+        }
+        if (queue_.empty()) {  // stopping with nothing left
+          idle_[k] = false;
+          break;
+        }
         t = queue_.front();
         queue_.pop_front();
-        used_ += t->est;
+        idle_[k] = false;
+        used_ = used_ - held_[k] + after;
+        held_[k] = after;
         if (used_ > peak_used_) peak_used_ = used_;
         if (active_ > 0) ++overlapped_;
         ++active_;
@@ -168,13 +222,16 @@ class RequestScheduler {
         t->err = ex ? err : "executor could not be created";
         t->t_end = now_s();
         t->done = true;
-        used_ -= t->est;
         --active_;
         ++completed_;
       }
       cv_done_.notify_all();
       cv_work_.notify_all();
     }
+    ex.reset();  // the executor's workspace goes with it
+    std::lock_guard<std::mutex> lk(mu_);
+    used_ -= held_[k];
+    held_[k] = 0;
   }
 
   MakeExec make_;
@@ -182,9 +239,11 @@ class RequestScheduler {
   std::condition_variable cv_work_, cv_done_;
   std::deque<std::shared_ptr<Ticket<P>>> queue_;
   std::map<int64_t, std::shared_ptr<Ticket<P>>> tickets_;
+  std::vector<size_t> held_;  // per worker: bytes its executor holds (in used_)
+  std::vector<bool> idle_;    // per worker: waiting for a request
   size_t budget_ = 0, used_ = 0, peak_used_ = 0;
   int32_t active_ = 0, peak_active_ = 0;
-  int64_t next_id_ = 1, submitted_ = 0, completed_ = 0, overlapped_ = 0;
+  int64_t next_id_ = 1, submitted_ = 0, completed_ = 0, overlapped_ = 0, releases_ = 0;
   bool stopping_ = false;
   std::vector<std::thread> workers_;
 };

@@ -1,12 +1,14 @@
 // Serving: many reconstruction requests of different sizes on one device.
 //
 // Admission and workers come from sched.h: a FIFO queue feeds a fixed number
-// of worker slots; the head request starts when a slot is free and its
-// memory estimate fits in what the budget has left, so requests arriving
-// while others run are admitted as soon as slots and memory free up.  Each
-// slot owns a library context (its device workspace stays resident and is
-// reused by the next request) and its own HIP stream, on which the Newton
-// and PCG work of its request runs.
+// of worker slots.  Each slot owns a library context (its device workspace
+// stays resident and is reused by the next request) and its own HIP stream,
+// on which the Newton and PCG work of its request runs.  The budget is
+// charged with the workspaces the slots hold, idle or not; the head request
+// starts when a slot is free and the holdings with that slot's workspace
+// resized for it fit in the budget (idle slots give their workspace back
+// when no idle slot can take it), so requests arriving while others run are
+// admitted as soon as slots and memory free up.
 //
 // Cell passes go through the pass batcher: a solve that needs one posts it
 // and waits; the batcher thread takes every posted pass at once (with a
@@ -85,7 +87,10 @@ struct PassBatcher final : mak::PassRunner {
   }
 };
 
-// One worker slot: a context and a stream, kept between requests.
+// One worker slot: a context and a stream, kept between requests.  The
+// context's workspace is sized for the largest request it has served (its
+// estimate is what the scheduler charges the slot with) and is given back
+// when a much smaller request comes or when the scheduler asks for it.
 struct SlotExec {
   int device = 0;
   mak_options opt{};
@@ -100,16 +105,27 @@ struct SlotExec {
   }
   ~SlotExec() {
     (void)hipSetDevice(device);
-    if (ctx) mak_destroy(ctx);
+    release();
     if (st) (void)hipStreamDestroy(st);
+  }
+  // What the slot holds after serving a request of estimate est when it held
+  // `held`: a request under half the held size gets a fresh workspace.
+  static size_t hold_after(size_t est, size_t held) {
+    if (held > 0 && est * 2 < held) return est;
+    return est > held ? est : held;
+  }
+  void release() {
+    if (ctx) {
+      (void)hipSetDevice(device);
+      (void)hipStreamSynchronize(st);
+      mak_destroy(ctx);
+    }
+    ctx = nullptr;
+    ctx_est = 0;
   }
   int run(SolveArgs& a, std::string& err, int64_t est) {
     (void)hipSetDevice(device);
-    // a much smaller request releases the workspace sized for a larger one
-    if (ctx && est * 2 < ctx_est) {
-      mak_destroy(ctx);
-      ctx = nullptr;
-    }
+    if (ctx && size_t(hold_after(size_t(est), size_t(ctx_est))) < size_t(ctx_est)) release();
     if (!ctx) {
       if (mak_create(&ctx, device, &opt) != MAK_OK) {
         ctx = nullptr;
@@ -119,7 +135,7 @@ struct SlotExec {
       mak::set_pass_runner(ctx, batcher);
       ctx_est = 0;
     }
-    if (est > ctx_est) ctx_est = est;
+    ctx_est = int64_t(hold_after(size_t(est), size_t(ctx_est)));
     const mak_status s = mak_solve(ctx, a.points, a.N, a.L, a.tol, a.psi, a.cent, a.disp, &a.info, st);
     if (s != MAK_OK) err = mak_last_error(ctx);
     return s;
@@ -241,6 +257,7 @@ mak_status mak_server_stats(mak_server* s, mak_server_info* out) {
   out->used_bytes = st.used;
   out->peak_used_bytes = st.peak_used;
   out->budget_bytes = st.budget;
+  out->releases = st.releases;
   s->batcher.b.counters(&out->pass_batches, &out->batched_passes, &out->max_batch);
   return MAK_OK;
 }

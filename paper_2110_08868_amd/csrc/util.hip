@@ -153,15 +153,27 @@ double reduce_host(const double* x, int64_t n, DevBuf& tmp, hipStream_t st) {
 
 }  // namespace
 
-void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, DevBuf& tmp, hipStream_t st) {
+namespace {
+// The scans write n + 1 entries (the total last): refuse an output buffer
+// that cannot hold them instead of writing past its end.
+void check_scan_out(const DevBuf& out, int64_t n, size_t elem) {
+  if (n < 0 || !out.p || out.cap < size_t(n + 1) * elem)
+    MAK_FAIL(MAK_EHIP, "exclusive scan of " + std::to_string(n) + " entries: output buffer holds " +
+                           std::to_string(out.cap / elem) + " (needs n + 1)");
+}
+}  // namespace
+
+void exclusive_scan_i64(const int64_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st) {
+  check_scan_out(out, n, sizeof(int64_t));
   tmp.ensure(size_t(scan_tmp_elems(n)) * sizeof(int64_t));
-  scan_impl<int64_t, int64_t>(in, out, n, tmp.as<int64_t>(), st);
+  scan_impl<int64_t, int64_t>(in, out.as<int64_t>(), n, tmp.as<int64_t>(), st);
   MAK_HIP(hipGetLastError());
 }
 
-void exclusive_scan_i32(const int32_t* in, int32_t* out, int64_t n, DevBuf& tmp, hipStream_t st) {
+void exclusive_scan_i32(const int32_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st) {
+  check_scan_out(out, n, sizeof(int32_t));
   tmp.ensure(size_t(scan_tmp_elems(n)) * sizeof(int32_t));
-  scan_impl<int32_t, int32_t>(in, out, n, tmp.as<int32_t>(), st);
+  scan_impl<int32_t, int32_t>(in, out.as<int32_t>(), n, tmp.as<int32_t>(), st);
   MAK_HIP(hipGetLastError());
 }
 

@@ -18,11 +18,33 @@ struct Fake {
   int fail = 0;
 };
 
+// Holds a "workspace" like the server's slots: sized for the largest request
+// it has run, given back when a much smaller one comes or when released.
+// `resident` sums what every fake holds at this moment; `resident_peak` is its
+// maximum, the fake's measured counterpart of the scheduler's bookkeeping.
 struct FakeExec {
-  static std::atomic<int> made;
+  static std::atomic<int> made, releases;
+  static std::atomic<long long> resident, resident_peak;
   int slot;
+  size_t holds = 0;
   explicit FakeExec(int s) : slot(s) { ++made; }
-  int run(Fake& f, std::string& err, int64_t) {
+  ~FakeExec() { resident -= (long long)holds; }
+  static size_t hold_after(size_t est, size_t held) {
+    return (held > 0 && est * 2 < held) ? est : (est > held ? est : held);
+  }
+  void grow(size_t to) {
+    resident += (long long)to - (long long)holds;
+    holds = to;
+    long long r = resident.load(), p = resident_peak.load();
+    while (r > p && !resident_peak.compare_exchange_weak(p, r)) {
+    }
+  }
+  void release() {
+    ++releases;
+    grow(0);
+  }
+  int run(Fake& f, std::string& err, int64_t est) {
+    grow(hold_after(size_t(est), holds));
     std::this_thread::sleep_for(std::chrono::milliseconds(f.ms));
     if (f.fail) {
       err = "fake failure";
@@ -32,6 +54,9 @@ struct FakeExec {
   }
 };
 std::atomic<int> FakeExec::made{0};
+std::atomic<int> FakeExec::releases{0};
+std::atomic<long long> FakeExec::resident{0};
+std::atomic<long long> FakeExec::resident_peak{0};
 
 using Sched = RequestScheduler<Fake, FakeExec>;
 
@@ -47,10 +72,10 @@ static void print_ticket(const Ticket<Fake>& t, double t0, bool last) {
 
 static void print_stats(const Stats& s) {
   std::printf("\"stats\": {\"submitted\": %lld, \"completed\": %lld, \"queued\": %lld, \"active\": %d, "
-              "\"peak_active\": %d, \"admitted_while_busy\": %lld, \"used\": %zu, \"peak_used\": %zu, "
-              "\"budget\": %zu}",
+              "\"peak_active\": %d, \"admitted_while_busy\": %lld, \"releases\": %lld, \"used\": %zu, "
+              "\"peak_used\": %zu, \"budget\": %zu}",
               (long long)s.submitted, (long long)s.completed, (long long)s.queued, s.active, s.peak_active,
-              (long long)s.admitted_while_busy, s.used, s.peak_used, s.budget);
+              (long long)s.admitted_while_busy, (long long)s.releases, s.used, s.peak_used, s.budget);
 }
 
 // Requests (est, ms) submitted at the given offsets (ms) into a scheduler.
@@ -76,6 +101,7 @@ static void scenario(size_t budget, int slots, const std::vector<std::vector<int
   }
   const Stats st = s.stats();
   s.shutdown();
+  const Stats after = s.stats();
   std::printf("{\"ids\": [");
   for (size_t k = 0; k < ids.size(); ++k) std::printf("%lld%s", (long long)ids[k], k + 1 < ids.size() ? ", " : "");
   std::printf("], \"rejected_msg\": \"");
@@ -85,7 +111,10 @@ static void scenario(size_t budget, int slots, const std::vector<std::vector<int
   for (size_t k = 0; k < ts.size(); ++k) print_ticket(ts[k], t0, k + 1 == ts.size());
   std::printf("], ");
   print_stats(st);
-  std::printf(", \"executors\": %d}\n", FakeExec::made.load());
+  std::printf(", \"executors\": %d, \"exec_releases\": %d, \"resident_peak\": %lld, "
+              "\"used_after_shutdown\": %zu, \"resident_after_shutdown\": %lld}\n",
+              FakeExec::made.load(), FakeExec::releases.load(), FakeExec::resident_peak.load(), after.used,
+              FakeExec::resident.load());
 }
 
 // Threads post jobs to a Batcher whose run function takes `ms` per batch.
@@ -148,6 +177,16 @@ int main(int argc, char** argv) {
     // FIFO with memory admission: the 2nd (60) waits for the 1st (60); the
     // 3rd (30) stays behind the 2nd (no overtaking)
     scenario(100, 4, {{60, 80, 0}, {60, 40, 5}, {30, 10, 10}});
+  } else if (which == "resident") {
+    // workspaces stay charged after their requests end: the 60 after the
+    // first pair reuses the idle 60 (no release); the 80 fits only once an
+    // idle workspace is given back
+    scenario(100, 2, {{60, 60, 0}, {30, 60, 5}, {60, 20, 150}, {80, 20, 250}});
+  } else if (which == "overcommit") {
+    // the pattern that overcommitted when only running requests counted: a
+    // big request, then another big one while a small one holds the other
+    // slot; idle workspaces keep being charged
+    scenario(100, 3, {{70, 40, 0}, {20, 10, 5}, {70, 40, 10}, {20, 10, 15}, {70, 40, 20}});
   } else if (which == "reject") {
     scenario(100, 2, {{150, 10, 0}, {50, 10, 0}});
   } else if (which == "midflight") {

@@ -47,8 +47,16 @@ def test_default_options_and_estimate(lib):
 
 def test_null_arguments_rejected_without_device(lib):
     # a NULL context is rejected before any device call
-    assert lib.mak_laguerre_cells(None, None, None, 0, 1.0, None, None, None, None) == 1
+    assert lib.mak_laguerre_cells(None, None, None, 0, 1.0, None, None, None, None, None) == 1
     assert lib.mak_solve(None, None, 0, 1.0, 1e-6, None, None, None, None, None) == 1
     out = ctypes.c_void_p()
     # NULL out pointer
     assert lib.mak_create(None, 0, None) == 1
+
+
+def test_device_bytes_counter_without_device(lib):
+    """The library's device-memory counter reads (zero: nothing allocated
+    without a device) and its peak resets to the live value."""
+    import paper_2110_08868_amd as mak
+    live, peak = mak.device_bytes(reset_peak=True)
+    assert live == 0 and peak == 0

@@ -91,8 +91,10 @@ def test_deterministic(ctx):
 def test_full_size_at_solution(ctx):
     """Clustered 128^3 (2.1 M sites) at its solved weights, 128^3 elements on
     a 128^3 mesh: tau = 0 gives density 1 exactly (CIC from cell centres);
-    at tau = 0.5 the mass is conserved and the deposit equals the cloud-in-
-    cell assignment of q + tau disp with disp from mak_legendre_mesh."""
+    at tau = 0.5 the mass is conserved and the deposit equals the oracle's
+    cloud-in-cell assignment of q + tau disp, with disp from
+    mak_legendre_mesh (itself matched to the oracle's brute-force Legendre
+    transform on sampled nodes here)."""
     import torch
     import paper_2110_08868_amd as mak
     n = 128
@@ -106,22 +108,18 @@ def test_full_size_at_solution(ctx):
     tau = 0.5
     r = ctx.za_deposit(xd, psi_d, 1.0, tau, n, n, "cic", 0.5).cpu().numpy()
     assert r.sum() / n ** 3 == pytest.approx(1.0, rel=1e-13)
-    _, _, disp = ctx.legendre_mesh(xd, psi_d, 1.0, n, 0.5)
+    phi, idx, disp = ctx.legendre_mesh(xd, psi_d, 1.0, n, 0.5)
     disp = disp.cpu().numpy()
     q = workloads.mesh_points(n, 1.0, 0.5)
+    # the located displacements on sampled nodes against the oracle's brute force
+    sel = np.random.default_rng(5).choice(n ** 3, 6, replace=False)
+    rphi, ridx, rdisp = oracle.legendre(x, psi_d.cpu().numpy(), 1.0, q[sel])
+    assert np.abs(phi.cpu().numpy()[sel] - rphi).max() <= 1e-13
+    same = idx.cpu().numpy()[sel] == ridx
+    assert np.abs(disp[sel][same] - rdisp[same]).max(initial=0) <= 1e-13
     y = np.mod(q + tau * disp, 1.0)
-    u = y * n
-    i0 = np.floor(u)
-    f = u - i0
-    i0 = i0.astype(np.int64)
-    ref = np.zeros(n ** 3)
-    for dx in (0, 1):
-        for dy in (0, 1):
-            for dz in (0, 1):
-                wgt = ((f[:, 0] if dx else 1 - f[:, 0]) * (f[:, 1] if dy else 1 - f[:, 1])
-                       * (f[:, 2] if dz else 1 - f[:, 2]))
-                j = np.mod(i0 + np.array([dx, dy, dz]), n)
-                np.add.at(ref, (j[:, 0] * n + j[:, 1]) * n + j[:, 2], wgt)
+    y[y >= 1.0] = 0.0
+    ref = oracle.mesh_assign(y, 1.0 / n ** 3, 1.0, n, "cic").ravel()
     err = np.abs(r.ravel() - ref).max()
     print(f"  rho range {r.min():.3f}..{r.max():.1f}, max |drho| {err:.2e}", flush=True)
     assert err <= 4.0 * n ** 3 / units(n) + 1e-10

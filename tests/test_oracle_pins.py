@@ -565,6 +565,71 @@ def test_p11_deposit_tau0_uniform_and_mass():
         assert r.sum() * (L / 7) ** 3 == pytest.approx(L ** 3, rel=1e-13)
 
 
+def test_p11_deposit_cic_one_element_hand_values():
+    """Cloud in cell of one element, worked by hand.  One site at
+    (0.55, 0.45, 0.35) in the unit box (its cell is the whole box), one
+    Lagrangian element (n_lag = 1, offset 0.3) at q = (0.3, 0.3, 0.3), a 4^3
+    mesh (H = 0.25).  At tau = 0.5 the element moves half way to the site's
+    nearest image: y = (0.425, 0.375, 0.325), i.e. (1.7, 1.5, 1.3) in node
+    units.  Cloud in cell gives the node below the weight 1 - f and the node
+    above f: x-axis nodes 1, 2 get 0.3, 0.7; y-axis 0.5, 0.5; z-axis 0.7,
+    0.3.  The density at a node is 64 (the element's mass 1 per node volume
+    1/64) times the product of its three axis weights.  The weights differ
+    per axis and are not symmetric in f <-> 1 - f, so swapping the two
+    weights, an off-by-one node or transposed axes all fail here."""
+    x = np.array([[0.55, 0.45, 0.35]])
+    r = oracle.za_deposit(x, np.zeros(1), 1.0, 0.5, 1, 4, scheme="cic", lag_offset=0.3)
+    wx = {1: 0.3, 2: 0.7}
+    wy = {1: 0.5, 2: 0.5}
+    wz = {1: 0.7, 2: 0.3}
+    want = np.zeros((4, 4, 4))
+    for a, pa in wx.items():
+        for b, pb in wy.items():
+            for c, pc in wz.items():
+                want[a, b, c] = 64.0 * pa * pb * pc
+    assert want[1, 1, 1] == pytest.approx(6.72) and want[2, 2, 2] == pytest.approx(6.72)
+    assert want[2, 1, 1] == pytest.approx(15.68) and want[1, 1, 2] == pytest.approx(2.88)
+    assert np.allclose(r, want, rtol=1e-12, atol=1e-12)
+    # tau = 0: the element stays at (1.2, 1.2, 1.2): weights 0.8 / 0.2 on every axis
+    r0 = oracle.za_deposit(x, np.zeros(1), 1.0, 0.0, 1, 4, scheme="cic", lag_offset=0.3)
+    assert r0[1, 1, 1] == pytest.approx(64 * 0.512, rel=1e-12)
+    assert r0[2, 1, 1] == pytest.approx(64 * 0.128, rel=1e-12)
+    assert r0[2, 2, 1] == pytest.approx(64 * 0.032, rel=1e-12)
+    assert r0[2, 2, 2] == pytest.approx(64 * 0.008, rel=1e-12)
+    assert np.count_nonzero(r0) == 8
+
+
+def test_p11_deposit_cic_first_moment():
+    """Cloud in cell reproduces linear functions: per axis, the mass-weighted
+    mean node position of the deposit equals the mean moved element position
+    for every element whose two nodes do not wrap (none lies in the last
+    node interval [L - H, L)).  The sites sit in the lower part of the box and
+    tau is near 1, so every moved element lies within reach of its site and
+    the precondition holds.  The moved positions come from the Legendre
+    transform of the weights (pinned above, P9); the moment identity itself
+    does not use the deposit's weights.  A weight swap moves an element's
+    moment from u to 2 i0 + 1 - u and fails."""
+    rng = np.random.default_rng(71)
+    n_sites = 9
+    x = rng.uniform(0.05, 0.55, (n_sites, 3))
+    psi = rng.uniform(-1, 1, n_sites) * 1e-3
+    L, tau, n_lag, ng = 1.0, 0.9, 12, 4
+    H = L / ng
+    t = (np.arange(n_lag) + 0.5) * (L / n_lag)
+    A, B, C = np.meshgrid(t, t, t, indexing="ij")
+    q = np.stack([A.ravel(), B.ravel(), C.ravel()], axis=1)
+    _, _, disp = oracle.legendre(x, psi, L, q)
+    y = np.mod(q + tau * disp, L)
+    assert np.all(y < L - H) and np.all(y >= 0)
+    rho = oracle.za_deposit(x, psi, L, tau, n_lag, ng, scheme="cic")
+    mass = rho * H ** 3
+    assert mass.sum() == pytest.approx(L ** 3, rel=1e-13)
+    pos = np.arange(ng) * H
+    for ax in range(3):
+        node_moment = np.tensordot(mass.sum(axis=tuple(a for a in range(3) if a != ax)), pos, 1)
+        assert node_moment == pytest.approx(y[:, ax].sum() * (L / n_lag) ** 3, rel=1e-12)
+
+
 def _layer_setup():
     rng = np.random.default_rng(61)
     L, nl, ny = 1.0, 3, 2

@@ -34,7 +34,34 @@ def test_memory_budget_and_fifo(driver):
     # the 30 does not overtake the queued 60 (it would have fit beside the first)
     assert c["start"] >= b["start"] - 1e-4
     assert [x["status"] for x in (a, b, c)] == [0, 0, 0]
-    assert r["stats"]["completed"] == 3 and r["stats"]["used"] == 0
+    assert r["stats"]["completed"] == 3
+    # the idle workspaces (60 and 30) stay charged until shutdown
+    assert r["stats"]["used"] == 90 and r["used_after_shutdown"] == 0
+    # the second 60 ran on the slot whose workspace already held 60
+    assert b["slot"] == a["slot"]
+
+
+def test_idle_workspaces_are_charged(driver):
+    """A slot's workspace stays charged after its request ends; an idle
+    workspace is given back only when no idle slot can take the head request
+    as things are; what the executors really hold never exceeds the budget."""
+    r = run(driver, "resident")
+    a, b, c, d = r["tickets"]
+    assert [x["status"] for x in r["tickets"]] == [0, 0, 0, 0]
+    assert c["slot"] == a["slot"]            # the idle 60 took the next 60
+    assert r["stats"]["releases"] >= 1 and r["exec_releases"] == r["stats"]["releases"]
+    assert r["stats"]["peak_used"] <= 100
+    assert r["resident_peak"] <= 100
+    # held workspaces are still charged when the last request has ended
+    assert r["stats"]["used"] > 0
+    assert r["used_after_shutdown"] == 0 and r["resident_after_shutdown"] == 0
+
+
+def test_no_overcommit_with_resident_workspaces(driver):
+    r = run(driver, "overcommit")
+    assert all(x["status"] == 0 for x in r["tickets"])
+    assert r["stats"]["completed"] == 5
+    assert r["resident_peak"] <= 100 and r["stats"]["peak_used"] <= 100
 
 
 def test_rejects_what_can_never_fit(driver):
