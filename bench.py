@@ -169,12 +169,22 @@ def roofline(prof, cprof, workload):
                "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_launch_ms": avg_ms,
                "launches": v["launches"]}
     elif dom.startswith("clip"):
+        # flops: the method's arithmetic only (planes that reach the polytope,
+        # vertex tests, new vertices, integrals); the candidate search's
+        # counted flops (site scans, ball updates, box tests) are reported
+        # beside it, not in `achieved`
         achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+        counters = cprof.get("_counters") or {}
+        search_pl = counters.get("search_flops", 0.0) / max(c["launches"], 1)
         out = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS,
                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
                "traffic": measured_traffic(dom, workload),
                "avg_launch_ms": avg_ms, "launches": v["launches"],
                "flops_per_launch": per_launch_flops, "bytes_per_launch": per_launch_bytes,
+               "cells_per_launch": c["units"] / max(c["launches"], 1),
+               "search_flops_per_launch": search_pl,
+               "frac_with_search_flops": (per_launch_flops + search_pl) / (avg_ms * 1e-3) / 1e12
+                                         / PEAK_FP64_VECTOR_TFLOPS,
                "hbm_GBs_algorithmic": per_launch_bytes / (avg_ms * 1e-3) / 1e9}
     else:
         achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9
@@ -184,6 +194,33 @@ def roofline(prof, cprof, workload):
                "bytes_per_launch": per_launch_bytes}
     share = {k: round(kern[k]["total_ms"], 3) for k in kern}
     return out, share
+
+
+def pass_rates(mak, x_dev, psi, L, precision, reps):
+    """Full cell passes (mak_laguerre_cells: volumes, centroids and the CSR
+    Hessian) at psi = 0 and at the solved weights: cells/s = N / median pass
+    time over `reps` passes after one warm-up, each pass bracketed by device
+    synchronisations."""
+    import numpy as np
+    import torch
+    N = x_dev.shape[0]
+    ctx = mak.Context(0, precision)
+    out = {}
+    for name, w in (("psi0", torch.zeros(N, dtype=torch.float64, device=x_dev.device)), ("solved", psi)):
+        _, _, info = ctx.laguerre_cells(x_dev, w, L)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.laguerre_cells(x_dev, w, L)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        med = float(np.median(ts))
+        out[name] = {"cells_per_s": N / med, "ms_median": med * 1e3, "passes": reps,
+                     "nnz": int(info["nnz"]), "max_faces": int(info["max_faces"]),
+                     "fp64_rerun_cells": int(info["fp64_rerun_cells"])}
+    ctx.close()
+    return out
 
 
 def legendre_leg(mak, x_dev, psi, L, ng, reps, workload):
@@ -313,6 +350,7 @@ def accuracy_vs_oracle(mak, x, out, L, sample=64):
     D = L / N ** (1.0 / 3.0)
     ctx = mak.Context(0, "mixed")
     V, C, info = ctx.laguerre_cells(torch.from_numpy(x).cuda(), psi, L)
+    F = {k: v.cpu().numpy() for k, v in ctx.faces().items()}
     ctx.close()
     V = V.cpu().numpy()
     C = C.cpu().numpy()
@@ -323,11 +361,28 @@ def accuracy_vs_oracle(mak, x, out, L, sample=64):
     dc = C[idx] - co
     dc -= L * np.round(dc / L)
     m = L ** 3 / N
+    # adjacency: faces (j, image) of the sampled cells reported by one side
+    # only, split at the mixed path's area threshold tau_A = 1e-6 spacing^2
+    tau_a = 1e-6 * D * D
+    above = below = matched = 0
+    for k, i in enumerate(idx):
+        fo = {key: a for key, (a, _d) in oracle.cell_faces_dict(r, k).items()}
+        fg = {}
+        for f in range(F["face_ptr"][i], F["face_ptr"][i + 1]):
+            fg[(int(F["face_j"][f]),) + tuple(int(t) for t in F["face_shift"][f])] = float(F["face_area"][f])
+        for key in set(fo) ^ set(fg):
+            if fo.get(key, fg.get(key)) >= tau_a:
+                above += 1
+            else:
+                below += 1
+        matched += len(set(fo) & set(fg))
     return {"sample_cells": sample,
             "max_rel_volume_err": float(np.max(np.abs(V[idx] - r["V"]) / r["V"])),
             "centroid_rms_grid": float(np.sqrt(np.mean(np.sum(dc * dc, 1))) / D),
             "disp_rms_grid": float(np.sqrt(np.mean(np.sum(dc * dc, 1))) / D),
             "oracle_max_rel_volume_err_vs_m": float(np.max(np.abs(r["V"] - m)) / m),
+            "faces_matched": matched, "adjacency_diff_above_tau": above,
+            "adjacency_diff_below_tau": below, "tau_A_over_spacing2": 1e-6,
             "fp64_rerun_cells_in_pass": int(info["fp64_rerun_cells"])}
 
 
@@ -352,9 +407,40 @@ def cpu_baseline(x, L, seconds):
     t0 = time.perf_counter()
     oracle.cells(x, psi, L, idx=idx, threads=threads)
     dt = time.perf_counter() - t0
+    # one thread, on an eighth of the time
+    m1 = int(max(4, min(N, seconds / 8 / max(per_cell * threads, 1e-9))))
+    idx1 = rng.choice(N, m1, replace=False)
+    t1 = time.perf_counter()
+    oracle.cells(x, psi, L, idx=idx1, threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": m / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"{m} random cells of the same {N}-site input at psi=0 "
-                      f"(one cell pass, {dt:.1f} s)"}
+                      f"(one cell pass, {dt:.1f} s)",
+            "single_thread_cells_per_s": m1 / dt1, "single_thread_sample_cells": m1}
+
+
+def oracle_small_timings(threads):
+    """The oracle on the small configurations it runs whole: one cell pass at
+    16^3 and at 32^3 (psi = 0), and the full damped-Newton solve of the
+    16^3 input (dense Newton steps) to 1e-6."""
+    import numpy as np
+
+    import oracle
+    import workloads
+    out = {"threads": threads}
+    for n in (16, 32):
+        x = workloads.zeldovich(n, rms=0.3 if n == 16 else 1.0, smooth=2.0 if n == 16 else 1.0,
+                                seed=1 if n == 16 else 2)
+        t0 = time.perf_counter()
+        oracle.cells(x, np.zeros(len(x)), 1.0, threads=threads)
+        dt = time.perf_counter() - t0
+        out[f"pass_{n}"] = {"N": len(x), "seconds": dt, "cells_per_s": len(x) / dt}
+    x = workloads.zeldovich(16, rms=0.3, smooth=2.0, seed=1)
+    t0 = time.perf_counter()
+    r = oracle.solve(x, 1.0, 1e-6, threads=threads)
+    out["solve_16"] = {"N": len(x), "seconds": time.perf_counter() - t0,
+                       "newton_iters": int(r["newton_iters"]), "final_err": float(r["err"])}
+    return out
 
 
 def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, window_us=0, seed=1000):
@@ -372,6 +458,7 @@ def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, window_us=0, 
                                                seed=r["seed"])).cuda() for r in reqs]
     torch.cuda.synchronize()
     budget = int(budget_gb * (1 << 30))
+    live0, _ = mak.device_bytes(reset_peak=True)
     srv = mak.Server(0, precision, mem_budget=budget, max_slots=slots, cg_rtol=cg_rtol,
                      batch_window_us=window_us)
     # closed-loop capacity: the whole mix submitted at once
@@ -396,12 +483,15 @@ def serving(mak, count, slots, budget_gb, precision, tol, cg_rtol, window_us=0, 
     lat = np.array([r.times[2] - r.times[0] for r in sub])
     span = max(r.times[2] for r in sub) - min(r.times[0] for r in sub)
     st = srv.stats()
+    _, peak = mak.device_bytes()
     srv.close()
     ns = np.array([r["n"] ** 3 for r in reqs])
     return {"requests": len(sub), "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)), "requests_per_s": len(sub) / span,
             "arrival_rate_per_s": lam, "closed_loop_capacity_per_s": cap, "slots": slots,
             "mem_budget_gb": budget_gb, "peak_used_gb": st["peak_used_bytes"] / 2 ** 30,
+            "peak_device_gb_measured": (peak - live0) / 2 ** 30,
+            "workspace_releases": st["releases"],
             "peak_active": st["peak_active"], "admitted_while_busy": st["admitted_while_busy"],
             "cell_passes_per_shared_launch": st["batched_passes"] / max(st["pass_batches"], 1),
             "max_passes_in_one_launch": st["max_batch"],
@@ -425,17 +515,21 @@ def main():
                     help="solver log on stderr: 1 per Newton iteration, 2 also per line-search trial")
     ap.add_argument("--no-counting", action="store_true",
                     help="skip the extra solve with the clip kernel's work counters")
+    ap.add_argument("--pass-reps", type=int, default=10,
+                    help="timed full cell passes at psi = 0 and at the solved weights (0 = skip)")
     ap.add_argument("--oracle-sample", type=int, default=64,
                     help="cells of the mixed path checked against the oracle")
-    ap.add_argument("--serving-requests", type=int, default=32,
-                    help="requests of the serving leg (the full serving workload is 256; 0 = skip)")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving leg (0 = skip)")
     ap.add_argument("--legendre-reps", type=int, default=5,
                     help="calls of the Legendre transform, the Zel'dovich deposit and the power "
                          "spectrum on the mesh at the solved weights (0 = skip)")
     ap.add_argument("--serving-slots", type=int, default=4)
     ap.add_argument("--serving-window-us", type=int, default=2000,
                     help="batch window of the serving leg's pass batcher (microseconds)")
-    ap.add_argument("--serving-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serving-budget-gb", type=float, default=6.0,
+                    help="memory budget of the serving leg (the largest request needs ~2.4 GB, "
+                         "so the slots' workspaces bind it)")
     ap.add_argument("--no-oracle-check", action="store_true",
                     help="skip the mixed path's sampled check against the oracle")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -511,6 +605,11 @@ def main():
     if (precision == "mixed" or other == "mixed") and not args.no_oracle_check:
         res["mixed_vs_oracle"] = accuracy_vs_oracle(mak, x, out if precision == "mixed" else out2, L,
                                                     sample=args.oracle_sample)
+    if args.pass_reps > 0:
+        log("[bench] full cell passes at psi = 0 and at the solved weights ...")
+        res["cell_pass"] = {precision: pass_rates(mak, x_dev, out[0], L, precision, args.pass_reps)}
+        if other not in ("none", precision):
+            res["cell_pass"][other] = pass_rates(mak, x_dev, out2[0], L, other, args.pass_reps)
     if args.legendre_reps > 0:
         ng = round(N ** (1.0 / 3.0))
         log(f"[bench] Legendre transform on the {ng}^3 mesh ...")
@@ -526,6 +625,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline ...")
         res["cpu_baseline"] = cpu_baseline(x, L, args.cpu_seconds)
+        res["cpu_baseline"]["small_configs"] = oracle_small_timings(res["cpu_baseline"]["cores"])
     print(json.dumps(res), flush=True)
 
 

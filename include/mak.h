@@ -314,7 +314,8 @@ typedef struct {
   int64_t launches;
   double total_ms;     /* summed event durations */
   double units;        /* work items processed (cells, rows) */
-  double flops;        /* counted arithmetic (work counting only for clip) */
+  double flops;        /* counted arithmetic of the method (work counting only,
+                          clip kernels: see mak_profile_counters) */
   double bytes;        /* compulsory HBM bytes of the algorithm */
 } mak_kernel_profile;
 
@@ -325,12 +326,26 @@ mak_status mak_profile_enable(mak_ctx* ctx, int32_t flags);
 /* Writes up to max_entries entries (HOST array, may be NULL) and returns the
  * number of entries available, or -1 on error.  Waits for pending events. */
 int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entries);
-/* HOST double[16]: summed clip work counters (sites scanned, planes tested,
- * vertex tests, cuts, new vertices, ball-update vertices, box tests, final
- * vertices, faces, cells), then shader-clock cycles summed over waves spent
- * in the candidate search, the serial clipping and the integrals, and within
- * those in the batch pre-filter (part of the search) and in the cuts that
- * removed vertices (part of the clipping); unused entries are zero. */
+/* HOST double[48]: summed clip work counters.
+ *   0-9    sites scanned, planes tested, vertex tests, cuts, new vertices,
+ *          ball-update vertices, box tests, final vertices, faces, cells;
+ *   10-14  shader-clock cycles summed over waves spent in the candidate
+ *          search, the serial clipping and the integrals, and within those
+ *          in the batch pre-filter (part of the search) and in the cuts that
+ *          removed vertices (part of the clipping);
+ *   15     the counted flops of the candidate search (site scans, ball
+ *          updates, box tests), which the clip kernels' `flops` in
+ *          mak_kernel_profile leave out (those count the method's
+ *          arithmetic: plane formation, vertex tests, new vertices and the
+ *          integrals);
+ *   16-19  sites scanned by search phase (warm-start neighbours, the 27
+ *          nearest grid cells, the second ring of cells, the cells of the
+ *          block shells); 20-23 of those, the sites inside the ball bound;
+ *   24-27  planes that removed vertices, by the same phases;
+ *   28-33  box tests and passes: ring-2 cells, blocks, cells of passing
+ *          blocks;
+ *   34     the last block shell reached, summed over cells.
+ * Unused entries are zero. */
 mak_status mak_profile_counters(mak_ctx* ctx, double* out);
 
 /* ---- serving: many reconstruction requests on one device ----

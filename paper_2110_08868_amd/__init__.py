@@ -89,7 +89,12 @@ class _KernelProfile(ctypes.Structure):
 COUNTER_NAMES = ["sites_scanned", "planes_tested", "vertex_tests", "cuts", "new_vertices",
                  "ball_vertices", "box_tests", "final_vertices", "faces", "cells",
                  "cycles_search", "cycles_clip", "cycles_integrals", "cycles_prefilter",
-                 "cycles_cuts"]
+                 "cycles_cuts", "search_flops",
+                 "scan_warm", "scan_near", "scan_ring2", "scan_blocks",
+                 "inball_warm", "inball_near", "inball_ring2", "inball_blocks",
+                 "cut_warm", "cut_near", "cut_ring2", "cut_blocks",
+                 "boxtest_ring2", "boxpass_ring2", "boxtest_blocks", "boxpass_blocks",
+                 "boxtest_blockcells", "boxpass_blockcells", "shell_sum"]
 
 
 class _ServerStats(ctypes.Structure):
@@ -332,7 +337,7 @@ class Context:
         for k in range(n):
             d = _as_dict(arr[k])
             out[d.pop("name").decode()] = d
-        c = (ctypes.c_double * 16)()
+        c = (ctypes.c_double * 48)()
         self._check(self.lib.mak_profile_counters(self._h, c))
         out["_counters"] = {name: c[i] for i, name in enumerate(COUNTER_NAMES)}
         return out

@@ -655,7 +655,7 @@ int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entr
 
 mak_status mak_profile_counters(mak_ctx* ctx, double* out) {
   if (!ctx || !out) return MAK_EINVAL;
-  for (int k = 0; k < 16; ++k) out[k] = ctx->prof.counters[k];
+  for (int k = 0; k < mak::kProfCounters; ++k) out[k] = ctx->prof.counters[k];
   return MAK_OK;
 }
 

@@ -107,8 +107,17 @@ struct ClipBatch {
 // The counting variant also sums shader-clock cycles per wave by phase:
 // candidate search (grid walk, site loads, batch filter and sort), serial
 // clipping, integrals and output.
+// By search phase (w: the warm-start neighbours, n: the 27 nearest cells,
+// r: the second ring of cells, b: the cells of the block shells): sites
+// scanned, sites inside the ball bound, planes that removed vertices; box
+// tests and how many passed (ring-2 cells, blocks, cells of passing blocks);
+// the last block shell reached.  Slot 15 is left for the search flops the
+// host forms from these counts.
 enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS,
-       ST_TSEARCH, ST_TCLIP, ST_TINT, ST_TPRE, ST_TCUT, ST_N };
+       ST_TSEARCH, ST_TCLIP, ST_TINT, ST_TPRE, ST_TCUT, ST_SEARCH_FLOPS,
+       ST_SCAN_W, ST_SCAN_N, ST_SCAN_R, ST_SCAN_B, ST_INBALL_W, ST_INBALL_N, ST_INBALL_R, ST_INBALL_B,
+       ST_CUT_W, ST_CUT_N, ST_CUT_R, ST_CUT_B, ST_BOXT_R, ST_BOXP_R, ST_BOXT_BLK, ST_BOXP_BLK,
+       ST_BOXT_BC, ST_BOXP_BC, ST_SHELL, ST_N };
 
 // Final vertices in float64 (the float32 path recomputes them from their
 // three planes before integrating; the float64 path integrates its own).
@@ -317,6 +326,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   bool dead = false;
   // work counters (compiled in only for the counting variant)
   uint32_t c_cand = 0, c_test = 0, c_vt = 0, c_cut = 0, c_newv = 0, c_ball = 0, c_box = 0, c_pre = 0;
+  uint32_t c_ph[ST_N - ST_SCAN_W] = {};  // the per-phase counters, from ST_SCAN_W on
+  int cur_ph = 0;                        // phase of the list being scanned
+#define CPH(idx, v) CNT(c_ph[(idx) - ST_SCAN_W] += uint32_t(v))
   uint64_t t_begin = 0, t_clip = 0, t_search_end = 0, t_pre = 0, t_cut = 0;
   if (STATS) t_begin = clock_stamp();
 #define CNT(stmt)  \
@@ -659,6 +671,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     }
     __syncthreads();
     CNT(c_cut += 1);
+    CPH(ST_CUT_W + cur_ph, 1);
     CNT(c_newv += uint32_t(nTn - nkept));
     CNT(c_ball += uint32_t(nTn));
     nT = nTn;
@@ -717,7 +730,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   };
 
   // Scan the sites of a list of cells (one cell per lane where `act`).
-  auto process_list = [&](bool act, int32_t start, int32_t cnt, int32_t sh) {
+  auto process_list = [&](bool act, int32_t start, int32_t cnt, int32_t sh, int ph) {
+    cur_ph = ph;
     const bool has = act && cnt > 0;
     const uint64_t am = ballot(has);
     const int ncl = __popcll(am);
@@ -735,6 +749,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     for (int base = 0; base < total && !dead; base += 64) {
       const int t = base + lane;
       CNT(c_cand += uint32_t(min(64, total - base)));
+      CPH(ST_SCAN_W + ph, min(64, total - base));
       refresh_ball();
       int lo = 0, hi = ncl - 1;
       while (lo < hi) {
@@ -767,6 +782,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       }
       if (ballot(coinc)) flags |= CF_COINCIDENT;
       int ns = __popcll(ballot(may));
+      CPH(ST_INBALL_W + ph, ns);
       if (ns == 0) continue;
       // the plane in the working precision (seed-local, so float32 keeps the
       // relative precision of |d|)
@@ -879,7 +895,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           shw = pack_shift(-int(rint((P.x - xi) / L)), -int(rint((P.y - yi) / L)),
                            -int(rint((P.z - zi) / L)));
         }
-        process_list(act, act ? j : 0, 1, shw);
+        process_list(act, act ? j : 0, 1, shw, 0);
       }
     }
     int phase = 0;  // 0: 27 cells, 1 and 2: ring 2 of cells, 3: block shells
@@ -898,6 +914,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       }
       bool act = false;
       int32_t st = 0, cnt = 0, shp = 0;
+      const int lph = phase == 0 ? 1 : (phase <= 2 ? 2 : 3);
       if (phase == 1 || phase == 2) {
         // ring 2 of grid cells (98 cells, two lists), after a reach check
         if (phase == 1) {
@@ -928,6 +945,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           }
         }
         CNT(c_box += 64);
+        CPH(ST_BOXT_R, __popcll(ballot(t < 98 && cnt > 0)));
+        CPH(ST_BOXP_R, __popcll(ballot(act)));
         shp = pack_shift(sx, sy, sz);
       } else if (phase == 0) {
         phase = 1;
@@ -968,6 +987,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           }
           const int t = gbase + lane;
           CNT(c_box += uint32_t(min(64, gcount - gbase)));
+          CPH(ST_BOXT_BLK, min(64, gcount - gbase));
           gbase += 64;
           bool ok = false;
           if (t < gcount) {
@@ -985,6 +1005,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
             ok = box_may_cut(lx, ly, lz, hx, hy, hz, bk, ubx, uby, ubz, A.block_tmax[bk]);
           }
           bmask = ballot(ok);
+          CPH(ST_BOXP_BLK, __popcll(bmask));
         }
         if (done) break;
         refresh_ball();
@@ -1000,6 +1021,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         st = A.cell_start[g];
         cnt = A.cell_start[g + 1] - st;
         act = !inA && cnt > 0;
+        CPH(ST_BOXT_BC, __popcll(ballot(act)));
         if (act) {
           const double lx = ux * h - xi - 1e-12 * L, ly = uy * h - yi - 1e-12 * L,
                        lz = uz * h - zi - 1e-12 * L;
@@ -1010,8 +1032,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         }
         shp = pack_shift(sx, sy, sz);
       }
-      process_list(act, st, cnt, shp);
+      if (lph == 3) CPH(ST_BOXP_BC, __popcll(ballot(act && cnt > 0)));
+      process_list(act, st, cnt, shp, lph);
     }
+    CPH(ST_SHELL, rb);
   }
 
   if (STATS) t_search_end = clock_stamp();
@@ -1034,6 +1058,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       atomicAdd(&st[ST_TRI], (unsigned long long)ntri);
       atomicAdd(&st[ST_FACES], (unsigned long long)nfaces);
       atomicAdd(&st[ST_CELLS], 1ull);
+#pragma unroll
+      for (int k = ST_SCAN_W; k < ST_N; ++k) atomicAdd(&st[k], (unsigned long long)c_ph[k - ST_SCAN_W]);
     }
   };
 
@@ -1248,15 +1274,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   }
 }
 
-// Counted arithmetic per work event (float64 ops, FMA = 2): scanning a site
-// (image offset, |d|^2, plane offset, ball test, sort key) 26; re-testing a
-// plane against the ball 21; one vertex-side test 7; one new vertex (three
-// cross products, determinant, solve) 50; one vertex of a ball update 11;
-// one box test 30; integrals per final vertex (three face triangles:
+// Counted arithmetic per work event (float64 ops, FMA = 2).  The method's
+// own work, the intersection of the half-spaces of Eq. laguerrecell and the
+// integrals of Eq. SDK: forming a candidate plane that reaches the polytope
+// 21; one vertex-side test 7; one new vertex (three cross products,
+// determinant, solve) 50; integrals per final vertex (three face triangles:
 // determinant, moment, area) 135.
 double clip_flops(const unsigned long long* c) {
-  return 26.0 * c[ST_CAND] + 21.0 * c[ST_TEST] + 7.0 * c[ST_VTEST] + 50.0 * c[ST_NEWV] +
-         11.0 * c[ST_BALL] + 30.0 * c[ST_BOX] + 135.0 * c[ST_TRI];
+  return 21.0 * c[ST_TEST] + 7.0 * c[ST_VTEST] + 50.0 * c[ST_NEWV] + 135.0 * c[ST_TRI];
+}
+// The search for the candidates (not the method's arithmetic: a search
+// overhead that a tighter bound would remove): scanning a site (image
+// offset, |d|^2, plane offset, ball test, sort key) 26; one vertex of a ball
+// update 11; one block / cell box test 30.
+double clip_search_flops(const unsigned long long* c) {
+  return 26.0 * c[ST_CAND] + 11.0 * c[ST_BALL] + 30.0 * c[ST_BOX];
 }
 // Compulsory HBM bytes: read own site (32), write volume, moment, flags and
 // face count (40), write the reported faces (16 each).  Neighbour reads are
@@ -1273,7 +1305,7 @@ void launch_clip(ClipBatch& b, CellPass* const* outs, hipStream_t st) {
   for (int j = 0; j < b.njobs; ++j) {
     items += b.job[j].nwork;
     if (counting) {
-      b.job[j].stats = outs[j]->counters.as<unsigned long long>() + 8;
+      b.job[j].stats = outs[j]->counters.as<unsigned long long>() + kCtrStats;
       MAK_HIP(hipMemsetAsync(b.job[j].stats, 0, ST_N * sizeof(unsigned long long), st));
     }
   }
@@ -1299,6 +1331,7 @@ void launch_clip(ClipBatch& b, CellPass* const* outs, hipStream_t st) {
       flops += clip_flops(c);
       bytes += clip_bytes(c);
       for (int k = 0; k < ST_N; ++k) pr->counters[k] += double(c[k]);
+      pr->counters[ST_SEARCH_FLOPS] += clip_search_flops(c);
       b.job[j].stats = nullptr;
     }
     ps.flops = flops;
@@ -1317,13 +1350,13 @@ namespace {
 //   mixed:   <2, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
 // counters of a pass: [0] overflow faces used, [1 + s] cells listed by stage
 // s, [4] doom flag of a line-search trial, [5] a cell that raised it,
-// [8..8 + ST_N) work counters,
-// [32 + 3 s ..] causes (capacity, cut, ambiguity)
+// [kCtrStats ..] work counters,
+// [kCtrCause + 3 s ..] causes (capacity, cut, ambiguity)
 int num_stages(int precision) { return precision == MAK_MIXED ? 3 : 2; }
 
 void job_begin(PassJob& jb, hipStream_t st) {
   CellPass& out = *jb.out;
-  MAK_HIP(hipMemsetAsync(out.counters.p, 0, 64 * sizeof(unsigned long long), st));
+  MAK_HIP(hipMemsetAsync(out.counters.p, 0, kCtrN * sizeof(unsigned long long), st));
   jb.stage = jb.opt.first_stage;
   jb.all_cells = jb.opt.probe_n <= 0;
   jb.listed = jb.all_cells ? jb.ps->N : jb.opt.probe_n;
@@ -1374,7 +1407,7 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.per_xcd = ceil_div(jb.listed, 8);
   a.retry = out.retry.as<int32_t>() + stage * N;
   a.retry_count = ctr + 1 + stage;
-  a.cause = ctr + 32 + 3 * stage;
+  a.cause = ctr + kCtrCause + 3 * stage;
   a.eps_rel = stage == nstage - 1 ? 1e-11 : 1e-13;
   a.doom = jb.opt.doom_vol > 0 ? reinterpret_cast<unsigned int*>(ctr + 4) : nullptr;
   a.doom_cell = ctr + 5;
@@ -1409,7 +1442,8 @@ void launch_stage(PassJob* const* jobs, int n, int stage, int precision, hipStre
 
 int32_t face_slots(int64_t N) { return N <= (int64_t(1) << 24) ? 32 : 20; }
 
-static_assert(8 + ST_N <= 32, "work counters overlap the stage causes");
+static_assert(kCtrStats + ST_N <= kCtrCause, "work counters overlap the stage causes");
+static_assert(ST_N <= kProfCounters, "the profile holds every work counter");
 
 void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t st) {
   const int nstage = num_stages(precision);
@@ -1430,7 +1464,7 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
       out.cflags.ensure(size_t(N) * sizeof(int32_t));
       out.nface.ensure(size_t(N) * sizeof(int32_t));
       out.retry.ensure(size_t(N) * 3 * sizeof(int32_t));
-      out.counters.ensure(64 * sizeof(unsigned long long));
+      out.counters.ensure(kCtrN * sizeof(unsigned long long));
       if (jb.opt.first_stage < 0 || jb.opt.first_stage >= nstage)
         MAK_FAIL(MAK_EINVAL, "first stage out of range");
       if (jb.opt.probe_n > 0 && (!jb.opt.probe_list || jb.opt.probe_n > N || jb.opt.faces ||
@@ -1491,7 +1525,7 @@ void run_cells_batch(PassJob* const* jobs, int njobs, int precision, hipStream_t
           jb->cs.overflow = listed;
           if (jb->opt.tolerate_failure) continue;
           unsigned long long cz[3];
-          MAK_HIP(hipMemcpy(cz, jb->out->counters.as<unsigned long long>() + 32 + 3 * s, sizeof(cz),
+          MAK_HIP(hipMemcpy(cz, jb->out->counters.as<unsigned long long>() + kCtrCause + 3 * s, sizeof(cz),
                             hipMemcpyDeviceToHost));
           MAK_FAIL(MAK_EOVERFLOW, std::to_string(cz[0]) + " cells exceeded the polytope capacity, " +
                                       std::to_string(cz[1]) + " had inconsistent cuts");

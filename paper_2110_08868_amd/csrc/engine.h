@@ -123,13 +123,21 @@ struct FaceStore {
   int64_t ovf_cap = 0;
 };
 
+// Layout of a pass's device counters (uint64): [0] overflow faces used,
+// [1 + s] cells listed by stage s, [4] the doom flag of a line-search trial,
+// [5] a cell that raised it, work counters from kCtrStats, the causes of the
+// stage re-runs from kCtrCause (three per stage).
+constexpr int kCtrStats = 8;
+constexpr int kCtrCause = 64;
+constexpr int kCtrN = 80;
+
 // Output of one cell pass (sorted order).
 struct CellPass {
   DevBuf vol;        // double [N]
   DevBuf mom;        // double [3N] first moment, seed-local
   DevBuf cflags;     // int32 [N]
   DevBuf nface;      // int32 [N]
-  DevBuf counters;   // uint64 [64]: overflow faces used, stage lists, work counters
+  DevBuf counters;   // uint64 [kCtrN]: overflow faces used, stage lists, work counters
   DevBuf retry;      // int32 [3N]: cells listed for the next stage
   DevBuf scan_tmp;
   FaceStore own;
@@ -317,6 +325,8 @@ void dev_max_to(const double* x, int64_t n, double* out, DevBuf& tmp, hipStream_
 // fewer than n + 1 entries.
 void exclusive_scan_i64(const int64_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st);
 void exclusive_scan_i32(const int32_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st);
+// Zero n 32-bit words on the stream (a fill kernel, not a memset node).
+void fill_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 
 struct PcgWork {
   DevBuf r, z, p, q, s, dinv, part, part2, scal;

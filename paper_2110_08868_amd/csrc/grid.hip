@@ -251,8 +251,8 @@ void build_pointset(PointSet& ps, const double* points, const double* psi, int64
   double4* xw = ps.status.as<double4>();
   int32_t* status = reinterpret_cast<int32_t*>(ps.status.as<char>() + size_t(N) * sizeof(double4));
 
-  MAK_HIP(hipMemsetAsync(ps.count.p, 0, size_t(G) * sizeof(int32_t), st));
-  MAK_HIP(hipMemsetAsync(status, 0, sizeof(int32_t), st));
+  fill_zero_i32(ps.count.as<int32_t>(), G, st);
+  fill_zero_i32(status, 1, st);
   const unsigned nb = unsigned(ceil_div(N, 256));
   hipLaunchKernelGGL(k_stage, dim3(nb), dim3(256), 0, st, points, psi, N, L, ps.g.h, ps.g.Gn,
                      ps.g.Gb, xw, ps.key.as<int32_t>(), ps.rank.as<int32_t>(),

@@ -556,7 +556,7 @@ void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, do
     threads = a.nb * a.nb * a.nb * 64;
   }
   if (a.Q == 0) return;
-  if (queries) MAK_HIP(hipMemsetAsync(a.status, 0, sizeof(int32_t), st));
+  if (queries) fill_zero_i32(a.status, 1, st);
   const dim3 grid = queries ? xcd_grid(a, threads) : brick_grid(a);
   ProfScope scope("locate", st, double(a.Q), double(a.Q) * (phi ? 8 : 0) + double(a.Q) * (idx ? 4 : 0) +
                                                  double(a.Q) * (disp ? 24 : 0) +

@@ -10,6 +10,9 @@
 
 namespace mak {
 
+// Entries of the profile's summed clip work counters (mak_profile_counters).
+constexpr int kProfCounters = 48;
+
 struct ProfAcc {
   int64_t launches = 0;
   double ms = 0.0;
@@ -30,7 +33,7 @@ struct Profiler {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::string, ProfAcc> acc;
-  double counters[16] = {0};  // clip work counters summed over launches
+  double counters[kProfCounters] = {0};  // clip work counters summed over launches
 
   hipEvent_t take() {
     if (!pool.empty()) {

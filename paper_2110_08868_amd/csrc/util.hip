@@ -163,6 +163,19 @@ void check_scan_out(const DevBuf& out, int64_t n, size_t elem) {
 }
 }  // namespace
 
+namespace {
+__global__ void k_fill_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+}  // namespace
+
+void fill_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_zero_i32, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, st, p, n);
+  MAK_HIP(hipGetLastError());
+}
+
 void exclusive_scan_i64(const int64_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st) {
   check_scan_out(out, n, sizeof(int64_t));
   tmp.ensure(size_t(scan_tmp_elems(n)) * sizeof(int64_t));

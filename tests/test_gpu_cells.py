@@ -272,3 +272,45 @@ def test_pyramid_identity_on_device(ctx):
     Vp = np.bincount(i, weights=fa * h / 3.0, minlength=n ** 3)
     assert np.abs(Vp - V).max() <= 1e-10 * V.max()
     assert V.sum() == pytest.approx(1.0, rel=1e-12)
+
+
+def test_above_2_24_sites():
+    """257^3 = 16.97 M sites, above 2^24: the range where each cell keeps 20
+    face slots instead of 32, the grid build gives its staging buffers back
+    before the pass, and a launch needs a 2-D grid of workgroups.  One float64
+    and one mixed pass at psi = 0 and at random weights: 32 sampled cells
+    against the oracle (each one clipped against every site and image), the
+    volumes summing to L^3 and zero Hessian row sums over every row."""
+    import torch
+    import paper_2110_08868_amd as mak
+    n = 257
+    N = n ** 3
+    assert N > 2 ** 24
+    x = workloads.zeldovich(n, rms=2.0, smooth=1.0, seed=5)
+    xd = torch.from_numpy(x).cuda()
+    rng = np.random.default_rng(257)
+    idx = np.sort(rng.choice(N, 32, replace=False))
+    psis = [np.zeros(N), rng.uniform(-1, 1, N) * 0.05 / n ** 2]
+    refs = [oracle.cells(x, p, 1.0, idx=idx, threads=16) for p in psis]
+    for prec, bar in (("fp64", 1e-10), ("mixed", 1e-6)):
+        c = mak.Context(0, prec)
+        try:
+            for psi, res in zip(psis, refs):
+                print(f"case 257^3 {prec} psi max {np.abs(psi).max():.1e}", flush=True)
+                V, C, info = c.laguerre_cells(xd, torch.from_numpy(psi).cuda(), 1.0)
+                assert abs(V.sum().item() - 1.0) <= 1e-11
+                F = gpu_faces(c)
+                rep = compare_cells(x, psi, 1.0, V.cpu().numpy(), C.cpu().numpy(), F, res=res,
+                                    vol_rel=bar, cen_rel=bar, area_rel=bar)
+                del F
+                rp, col, val = c.hessian()
+                rows = torch.repeat_interleave(torch.arange(N, device=rp.device), rp[1:] - rp[:-1])
+                rs = torch.zeros(N, dtype=torch.float64, device=rp.device).index_add_(0, rows, val)
+                amax = val.abs().max().item()
+                rmax = rs.abs().max().item()
+                del rows, rs, rp, col, val
+                print(f"  {rep} nnz={info['nnz']} max_faces={info['max_faces']} "
+                      f"row sum {rmax / amax:.1e}", flush=True)
+                assert rmax <= 1e-12 * amax
+        finally:
+            c.close()

@@ -289,3 +289,91 @@ def test_full_size_clustered_128():
         rs = np.add.reduceat(val, rp[:-1])
         assert np.abs(rs).max() <= 1e-12 * np.abs(val).max()
         assert abs(V.sum().item() - 1.0) <= 1e-11
+
+
+def test_above_2_24_sites_solve():
+    """A mixed solve of 257^3 = 16.97 M sites (above 2^24: 20 face slots, the
+    grid staging given back, the solver's SELL slice table of 265,000
+    slices) to 1e-3: certified by the oracle's cells at the returned weights
+    on 32 sampled cells."""
+    import torch
+    import paper_2110_08868_amd as mak
+    n = 257
+    N = n ** 3
+    x = workloads.zeldovich(n, rms=2.0, smooth=1.0, seed=5)
+    sctx = mak.Context(0, "mixed", cg_rtol=1e-3)
+    try:
+        psi_d, C_d, D_d, info = sctx.solve(torch.from_numpy(x).cuda(), 1.0, 1e-3)
+    finally:
+        sctx.close()
+    print(f"  solve 257^3: {info}", flush=True)
+    assert info["final_err"] <= 1e-3
+    idx = np.sort(np.random.default_rng(258).choice(N, 32, replace=False))
+    res = oracle.cells(x, psi_d.cpu().numpy(), 1.0, idx=idx, threads=16)
+    err = float(np.max(np.abs(res["V"] * N - 1.0)))
+    print(f"  oracle volume error at the GPU weights (32 cells): {err:.2e}", flush=True)
+    assert err <= 1e-3
+    co = np.mod(x[idx] + res["M"] / res["V"][:, None], 1.0)
+    dc = C_d.cpu().numpy()[idx] - co
+    dc -= np.round(dc)
+    assert np.abs(dc).max() <= 1e-6 / n
+
+
+def test_c2_fp64_vs_mixed():
+    """The 64^3 comparison of the two precision paths (rms 1 spacing,
+    smoothing 1 spacing, seed 2, tol 1e-6) and its 32^3 sub-run against the
+    oracle: at 64^3 both paths are certified on sampled cells and their
+    centroids agree; at 32^3 the oracle's full cell pass at psi = 0 and at
+    each path's solved weights matches the GPU passes (adjacency, volumes,
+    centroids) and certifies the solves."""
+    import torch
+    import paper_2110_08868_amd as mak
+    from tests.parity import compare_cells, gpu_faces
+    out = {}
+    for n in (64, 32):
+        N = n ** 3
+        sp = 1.0 / n
+        x = workloads.zeldovich(n, rms=1.0, smooth=1.0, seed=2)
+        xd = torch.from_numpy(x).cuda()
+        sol = {}
+        for prec in ("fp64", "mixed"):
+            c = mak.Context(0, prec, cg_rtol=1e-3)
+            try:
+                psi, C, D, info = (t.cpu().numpy() if hasattr(t, "cpu") else t
+                                   for t in c.solve(xd, 1.0, 1e-6))
+            finally:
+                c.close()
+            assert info["final_err"] <= 1e-6
+            sol[prec] = (psi, C, D, info)
+        dc = sol["fp64"][1] - sol["mixed"][1]
+        dc -= np.round(dc)
+        crms = float(np.sqrt(np.mean(np.sum(dc * dc, 1))) / sp)
+        out[n] = {"centroid_rms_grid": crms, "centroid_max_grid": float(np.abs(dc).max() / sp),
+                  "newton": (sol["fp64"][3]["newton_iters"], sol["mixed"][3]["newton_iters"])}
+        # both stop inside the tolerance, at different points of it
+        assert np.abs(dc).max() <= 1e-5 * sp
+        idx = None if n == 32 else np.sort(np.random.default_rng(64).choice(N, 48, replace=False))
+        for prec in ("fp64", "mixed"):
+            psi = sol[prec][0]
+            res = oracle.cells(x, psi, 1.0, idx=idx, threads=16)
+            err = float(np.max(np.abs(res["V"] * N - 1.0)))
+            assert err <= 1e-6 * 1.001
+            k = np.arange(N) if idx is None else idx
+            co = np.mod(x[k] + res["M"] / res["V"][:, None], 1.0)
+            d = sol[prec][1][k] - co
+            d -= np.round(d)
+            assert np.abs(d).max() <= 1e-9 * sp
+            out[n][prec] = {"oracle_err": err}
+            if n == 32:
+                bar = 1e-10 if prec == "fp64" else 1e-6
+                c = mak.Context(0, prec)
+                try:
+                    for name, w in (("psi0", np.zeros(N)), ("solved", psi)):
+                        V, Cc, _ = c.laguerre_cells(xd, torch.from_numpy(w).cuda(), 1.0)
+                        r = res if name == "solved" else oracle.cells(x, w, 1.0, threads=16)
+                        rep = compare_cells(x, w, 1.0, V.cpu().numpy(), Cc.cpu().numpy(), gpu_faces(c),
+                                            res=r, vol_rel=bar, cen_rel=bar, area_rel=bar)
+                        out[n][prec][name] = rep
+                finally:
+                    c.close()
+    print(f"  C2 comparison: {out}", flush=True)
