@@ -372,6 +372,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   float brho = float(0.8660254037844386 * L) * 1.0001f;
   bool ball_dirty = false;
   float rvert = float(0.8660254037844386 * L) * 1.0001f;  // max vertex distance from x_i
+  // axis-aligned bounding box of the vertices (seed-local, widened by far
+  // more than the float rounding): with the ball it bounds what a plane can
+  // cut, h_P(d) <= sum_a max(d_a hi_a, d_a lo_a)
+  float blx = -0.5001f * float(L), bly = blx, blz = blx;
+  float bhx = 0.5001f * float(L), bhy = bhx, bhz = bhx;
   // tie tolerance of the vertex-side test: eps = eps_scale |d| (float64); the
   // float32 path uses tol = tol_rel (rvert |d| + |b|) and treats any vertex
   // with |u.d - b| <= tol as ambiguous (the cell is then re-run in float64)
@@ -427,6 +432,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     const float cn = sqrtf(sx * sx + sy * sy + sz * sz);
     brho = sqrtf(r2) * 1.0001f + 1e-6f * (cn + float(h));
     rvert = sqrtf(v2) * 1.0001f + 1e-6f * float(h);
+    float lx = FLT_MAX, ly = FLT_MAX, lz = FLT_MAX, hx = -FLT_MAX, hy = -FLT_MAX, hz = -FLT_MAX;
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      if (k * 64 + lane < nT) {
+        lx = fminf(lx, float(vx[k]));
+        ly = fminf(ly, float(vy[k]));
+        lz = fminf(lz, float(vz[k]));
+        hx = fmaxf(hx, float(vx[k]));
+        hy = fmaxf(hy, float(vy[k]));
+        hz = fmaxf(hz, float(vz[k]));
+      }
+    }
+    const float slack = 1e-5f * (rvert + float(h));
+    blx = -uniform_f(wave_max_f(-lx)) - slack;
+    bly = -uniform_f(wave_max_f(-ly)) - slack;
+    blz = -uniform_f(wave_max_f(-lz)) - slack;
+    bhx = uniform_f(wave_max_f(hx)) + slack;
+    bhy = uniform_f(wave_max_f(hy)) + slack;
+    bhz = uniform_f(wave_max_f(hz)) + slack;
   };
 
   // Drop the planes no vertex refers to any more (cut away by later planes)
@@ -492,11 +516,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     __syncthreads();
   };
 
+  // Upper bound of max_v v . d over the vertices from their bounding box.
+  auto aabb_support = [&](double dx, double dy, double dz) -> double {
+    return fmax(dx * double(blx), dx * double(bhx)) + fmax(dy * double(bly), dy * double(bhy)) +
+           fmax(dz * double(blz), dz * double(bhz));
+  };
+
   // Clip by u . d <= bb (plane tag jj / ss).
   auto clip_one = [&](double ddx, double ddy, double ddz, double dbb, double dnd, int32_t jj,
                       int32_t ss) {
     const double cd = double(bcx) * ddx + double(bcy) * ddy + double(bcz) * ddz;
     if (cd + double(brho) * dnd <= dbb - mtol) return;  // cannot reach the ball
+    if (aabb_support(ddx, ddy, ddz) <= dbb - mtol) return;  // nor the bounding box
     if (A.warm_rp) {
       // with a warm start the walk meets the warm planes again: a plane
       // already in the table is not applied twice
@@ -726,7 +757,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     const double f = m >= r ? 0.5 * m * m - r * m : -0.5 * r * r;
     const double ex = double(bcx) + gx, ey = double(bcy) + gy, ez = double(bcz) + gz;
     const double cmax = fmax(ex * lx, ex * hx) + fmax(ey * ly, ey * hy) + fmax(ez * lz, ez * hz);
-    return f - cmax < wmax - wi + mtol;
+    const double W = wmax - wi + mtol;
+    if (!(f - cmax < W)) return false;
+    // The same with the bounding box of the vertices: with h_P(d) <=
+    // sum_a max(d_a hi_a, d_a lo_a) the left side is separable per axis, and
+    // on each axis it is the smaller of two parabolas t^2/2 - (g_a + hi_a) t
+    // and t^2/2 - (g_a + lo_a) t, whose minima over [l_a, u_a] are at their
+    // clamped vertices.
+    auto axis_min = [](double l, double u, double g, double lo, double hi) {
+      const double a1 = g + hi, a2 = g + lo;
+      const double t1 = fmin(fmax(a1, l), u), t2 = fmin(fmax(a2, l), u);
+      return fmin(0.5 * t1 * t1 - a1 * t1, 0.5 * t2 * t2 - a2 * t2);
+    };
+    return axis_min(lx, hx, gx, double(blx), double(bhx)) + axis_min(ly, hy, gy, double(bly), double(bhy)) +
+               axis_min(lz, hz, gz, double(blz), double(bhz)) <
+           W;
   };
 
   // Scan the sites of a list of cells (one cell per lane where `act`).
@@ -776,7 +821,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           // tolerances and the sort key
           dn = sqrt(d2);
           const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
-          may = cd + double(brho) * dn > bb - mtol;
+          may = cd + double(brho) * dn > bb - mtol && aabb_support(dx, dy, dz) > bb - mtol;
           if (may) key = (float_key(float((bb - cd) / dn)) & ~63u) | uint32_t(lane);
         }
       }
