@@ -222,6 +222,28 @@ mak_status mak_legendre(mak_ctx* ctx, const double* points, const double* psi, i
                         const double* queries, int64_t Q, double* phi, int32_t* idx, double* disp,
                         void* stream);
 
+/* mak_legendre for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results (bit for bit), but every buffer the
+ * grid build and the location need lives in one static device array of
+ * 64 MiB that the library holds on each device it runs on until the process
+ * ends (its address is resolved by mak_create on that device).  No
+ * hipMalloc, hipFree or allocating library routine is called.
+ *   - The workspace is about 86 bytes per site (sorted sites, staging, grid
+ *     and weight bounds), so N up to roughly 750,000 sites; a larger N gives
+ *     MAK_EINVAL with the bytes it would need (the exact bound depends on the
+ *     neighbour grid of N and the context's grid_occupancy).
+ *   - Every call on one device shares that array: calls that overlap on a
+ *     device (other streams or host threads, any context) race and must be
+ *     serialised by the caller.  Each call leaves its contents behind; what
+ *     must start at zero is cleared by the call's own kernels.
+ *   - Like mak_legendre it synchronises `stream` (the non-finite-coordinate
+ *     checks read a status word on the host).
+ * MAK_EHIP if the array's address could not be resolved on this device. */
+mak_status mak_legendre_noalloc(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
+                                double L, const double* queries, int64_t Q, double* phi, int32_t* idx,
+                                double* disp, void* stream);
+
 /* The same at the ng^3 mesh nodes q_abc = ((a, b, c) + offset) L / ng,
  * a, b, c in [0, ng) (1 <= ng <= 4096; offset in mesh spacings, e.g. 0 or
  * 0.5), generated on the device; outputs in row order (a, b, c), c fastest. */

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "mak_profile_enable", "mak_profile_read",
     "mak_profile_counters", "mak_server_create", "mak_server_submit", "mak_server_poll",
     "mak_server_wait", "mak_server_release", "mak_server_stats", "mak_server_last_error",
-    "mak_server_destroy", "mak_device_bytes",
+    "mak_server_destroy", "mak_device_bytes", "mak_legendre_noalloc",
 ]
 
 STATUS = {0: "MAK_OK", 1: "MAK_EINVAL", 2: "MAK_ENOMEM", 3: "MAK_EDEGENERATE",
@@ -155,6 +155,8 @@ def load_library():
     lib.mak_power_spectrum.restype = ctypes.c_int
     lib.mak_legendre.argtypes = [P, P, P, I64, D, P, I64, P, P, P, P]
     lib.mak_legendre.restype = ctypes.c_int
+    lib.mak_legendre_noalloc.argtypes = [P, P, P, I64, D, P, I64, P, P, P, P]
+    lib.mak_legendre_noalloc.restype = ctypes.c_int
     lib.mak_legendre_mesh.argtypes = [P, P, P, I64, D, I64, D, P, P, P, P]
     lib.mak_legendre_mesh.restype = ctypes.c_int
     lib.mak_solve_masses.argtypes = [P, P, P, I64, D, D, P, P, P, P, P]
@@ -447,6 +449,21 @@ class Context:
         st = self.lib.mak_legendre(self._h, x.data_ptr(), None if w is None else w.data_ptr(),
                                    x.shape[0], float(L), q.data_ptr(), q.shape[0],
                                    phi.data_ptr(), idx.data_ptr(), disp.data_ptr(), self._stream())
+        self._check(st)
+        return phi, idx, disp
+
+    def legendre_noalloc(self, points, psi, L: float, queries, out=None):
+        """mak_legendre_noalloc: the same as legendre() with the library's
+        workspace in its static device array (the library allocates no
+        device memory).  out: optional (phi, idx, disp) tensors to write."""
+        x = self._dev(points, (3,))
+        w = None if psi is None else self._dev(psi)
+        q = self._dev(queries, (3,))
+        phi, idx, disp = out if out is not None else self._legendre_out(q.shape[0])
+        st = self.lib.mak_legendre_noalloc(self._h, x.data_ptr(), None if w is None else w.data_ptr(),
+                                           x.shape[0], float(L), q.data_ptr(), q.shape[0],
+                                           phi.data_ptr(), idx.data_ptr(), disp.data_ptr(),
+                                           self._stream())
         self._check(st)
         return phi, idx, disp
 

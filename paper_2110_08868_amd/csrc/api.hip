@@ -223,6 +223,9 @@ mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
     g_create_error = "invalid options";
     return MAK_EINVAL;
   }
+  // set-up of the no-allocation workspace on this device (once per device,
+  // with the device current); a failure only disables mak_legendre_noalloc
+  if (hipSetDevice(device) != hipSuccess || !mak::noalloc_setup(device)) (void)hipGetLastError();
   *out = c;
   return MAK_OK;
 }
@@ -318,6 +321,32 @@ mak_status mak_legendre(mak_ctx* ctx, const double* points, const double* psi, i
     hipStream_t st = static_cast<hipStream_t>(stream);
     build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
     locate(ctx->lps, queries, Q, 0, 0.0, phi, idx, disp, ctx->lstatus, st);
+  });
+}
+
+mak_status mak_legendre_noalloc(mak_ctx* ctx, const double* points, const double* psi, int64_t N,
+                                double L, const double* queries, int64_t Q, double* phi, int32_t* idx,
+                                double* disp, void* stream) {
+  if (!ctx) return MAK_EINVAL;
+  return guarded(ctx, [&] {
+    check_args(N, L);
+    if (!points || (Q > 0 && !queries)) MAK_FAIL(MAK_EINVAL, "NULL pointer argument");
+    if (Q < 0 || Q >= (int64_t(1) << 40)) MAK_FAIL(MAK_EINVAL, "Q must be in [0, 2^40)");
+    const GridDesc g = make_grid(N, L, ctx->opt.grid_occupancy);
+    const size_t need = pointset_bytes(N, g);
+    if (need > noalloc_capacity())
+      MAK_FAIL(MAK_EINVAL, "N = " + std::to_string(N) + " needs " + std::to_string(need) +
+                               " bytes of workspace; the no-allocation workspace holds " +
+                               std::to_string(noalloc_capacity()) + " bytes");
+    set_device(ctx);
+    char* base = static_cast<char*>(noalloc_scratch(ctx->device));
+    if (!base) MAK_FAIL(MAK_EHIP, "the no-allocation workspace is not available on this device");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PointSet ps;
+    DevBuf status;
+    borrow_pointset(ps, status, base, N, g);
+    build_pointset(ps, points, psi, N, L, ctx->opt.grid_occupancy, st);
+    locate(ps, queries, Q, 0, 0.0, phi, idx, disp, status, st);
   });
 }
 

@@ -27,24 +27,37 @@ struct DevBytes {
 };
 inline DevBytes g_dev_bytes;
 
-// A growable device buffer owned by the engine.
+// A growable device buffer owned by the engine, or a fixed view of memory
+// owned elsewhere (borrow(): never allocated or freed here; a request beyond
+// its size fails instead of allocating).
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool borrowed = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) {
+    if (p && !borrowed) {
       (void)hipFree(p);
       g_dev_bytes.add(-int64_t(cap));
     }
     p = nullptr;
     cap = 0;
+    borrowed = false;
+  }
+  void borrow(void* q, size_t bytes) {
+    release();
+    p = q;
+    cap = bytes;
+    borrowed = true;
   }
   void ensure(size_t bytes) {
     if (bytes <= cap && p) return;
+    if (borrowed)
+      MAK_FAIL(MAK_ENOMEM, "borrowed workspace of " + std::to_string(cap) + " bytes, " +
+                               std::to_string(bytes) + " needed");
     release();
     size_t want = bytes < 256 ? 256 : bytes;
     if (hipMalloc(&p, want) != hipSuccess) {
@@ -184,6 +197,13 @@ struct Lap {
 };
 
 // --- grid.hip
+// Device bytes build_pointset needs for N sites on the grid g, counting each
+// buffer rounded up to 256 bytes (the layout borrow_pointset carves).
+size_t pointset_bytes(int64_t N, const GridDesc& g);
+// Point every buffer of `ps` (and a 4-byte status word) into `base`, which
+// holds pointset_bytes(N, g) + 256 bytes; build_pointset then allocates
+// nothing.
+void borrow_pointset(PointSet& ps, DevBuf& status, char* base, int64_t N, const GridDesc& g);
 // Wrap, validate and sort `points` (original order, device) into `ps`; psi may
 // be NULL (zeros).  Returns MAK_OK / EINVAL through exceptions.
 void build_pointset(PointSet& ps, const double* points, const double* psi, int64_t N, double L,
@@ -290,6 +310,14 @@ void locate(const PointSet& ps, const double* queries, int64_t Q, int64_t ng, do
 void za_deposit(const PointSet& ps, double tau, int64_t n_lag, double lag_offset, int64_t ne, int scheme,
                 double* density, DevBuf& acc, hipStream_t st);
 
+// --- noalloc.hip
+// The device array behind mak_legendre_noalloc: noalloc_setup resolves this
+// device's copy (call with the device current; false on failure),
+// noalloc_scratch returns it (NULL before setup), noalloc_capacity its size.
+bool noalloc_setup(int device);
+void* noalloc_scratch(int device);
+size_t noalloc_capacity();
+
 // --- cells_deposit.hip
 // Exact deposit of the cells moved to growth amplitude tau in [0, 1): each
 // cell of the pass `cp` (float64, with faces, at the weights in ps) shrunk by
@@ -325,6 +353,9 @@ void dev_max_to(const double* x, int64_t n, double* out, DevBuf& tmp, hipStream_
 // fewer than n + 1 entries.
 void exclusive_scan_i64(const int64_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st);
 void exclusive_scan_i32(const int32_t* in, DevBuf& out, int64_t n, DevBuf& tmp, hipStream_t st);
+// Bytes of `tmp` the 32-bit scan of n entries and the reductions above use.
+size_t scan_tmp_bytes_i32(int64_t n);
+size_t reduce_tmp_bytes();
 // Zero n 32-bit words on the stream (a fill kernel, not a memset node).
 void fill_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 

@@ -1,5 +1,6 @@
 // Neighbour grid: wrap + validate + counting sort of the sites into
 // block-major cell order, and the weight bounds used by the search.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -227,6 +228,43 @@ __global__ __launch_bounds__(64) void k_block_tilt(const int32_t* __restrict__ s
 }
 
 }  // namespace
+
+namespace {
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+size_t pointset_bytes(int64_t N, const GridDesc& g) {
+  const size_t n = size_t(N), G = size_t(g.G()), GB = size_t(g.GB());
+  return up256(n * sizeof(double4)) + up256(n * 4) + up256((G + 1) * 4) + 2 * up256(G * 8) +
+         up256(GB * 8) * 2 + up256(GB * (SHELL_MAX + 1) * 8) + up256(GB * 3 * 8) + up256(8 * 8) +
+         2 * up256(n * 4) + up256(G * 4) + up256(n * sizeof(double4) + 64) +
+         up256(std::max(scan_tmp_bytes_i32(int64_t(G)), reduce_tmp_bytes())) + up256(4);
+}
+
+void borrow_pointset(PointSet& ps, DevBuf& status, char* base, int64_t N, const GridDesc& g) {
+  const size_t n = size_t(N), G = size_t(g.G()), GB = size_t(g.GB());
+  size_t off = 0;
+  auto take = [&](DevBuf& b, size_t bytes) {
+    b.borrow(base + off, bytes);
+    off += up256(bytes);
+  };
+  take(ps.pts, n * sizeof(double4));
+  take(ps.perm, n * 4);
+  take(ps.cell_start, (G + 1) * 4);
+  take(ps.cell_psimax, G * 8);
+  take(ps.cell_tmax, G * 8);
+  take(ps.block_psimax, GB * 8);
+  take(ps.block_tmax, GB * 8);
+  take(ps.block_suffix, GB * (SHELL_MAX + 1) * 8);
+  take(ps.block_g, GB * 3 * 8);
+  take(ps.scal, 8 * 8);
+  take(ps.key, n * 4);
+  take(ps.rank, n * 4);
+  take(ps.count, G * 4);
+  take(ps.status, n * sizeof(double4) + 64);
+  take(ps.tmp, std::max(scan_tmp_bytes_i32(int64_t(G)), reduce_tmp_bytes()));
+  take(status, 4);
+}
 
 void build_pointset(PointSet& ps, const double* points, const double* psi, int64_t N, double L,
                     double occupancy, hipStream_t st) {

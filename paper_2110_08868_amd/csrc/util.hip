@@ -163,6 +163,9 @@ void check_scan_out(const DevBuf& out, int64_t n, size_t elem) {
 }
 }  // namespace
 
+size_t scan_tmp_bytes_i32(int64_t n) { return size_t(scan_tmp_elems(n)) * sizeof(int32_t); }
+size_t reduce_tmp_bytes() { return (RED_BLOCKS + 8) * sizeof(double); }
+
 namespace {
 __global__ void k_fill_zero_i32(int32_t* p, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
