@@ -74,7 +74,12 @@ typedef struct {
                               batcher waits up to this long (microseconds) for the
                               passes of the other solves in flight, so they share
                               launches; default 0 (no wait) */
-  int32_t reserved[5];
+  int32_t cg_precond;      /* CG preconditioner of the Newton system: 0 (default)
+                              three-level additive (point Jacobi, Jacobi on the
+                              aggregates of the neighbour-grid blocks, an exact
+                              solve on at most 64 aggregates of those), 1 point
+                              Jacobi alone */
+  int32_t reserved[4];
 } mak_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -331,7 +336,7 @@ mak_status mak_power_spectrum(mak_ctx* ctx, const double* field, int64_t ng, dou
  * launch (this adds a host synchronisation per launch, so time and count in
  * separate runs). */
 typedef struct {
-  char name[32];       /* "clip", "clip_large", "spmv", "pcg_update", "pcg_solve",
+  char name[32];       /* "clip", "clip_large", "spmv", "pcg_update", "pcg_setup", "pcg_solve",
                           "csr_assembly", "grid_build", "locate", "deposit", "cells_deposit", "fft", "shell_bin" */
   int64_t launches;
   double total_ms;     /* summed event durations */
@@ -362,7 +367,8 @@ int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entr
  *          integrals);
  *   16-19  sites scanned by search phase (warm-start neighbours, the 27
  *          nearest grid cells, the second ring of cells, the cells of the
- *          block shells); 20-23 of those, the sites inside the ball bound;
+ *          block shells); 20-23 of those, the sites inside the ball and
+ *          bounding-box bounds;
  *   24-27  planes that removed vertices, by the same phases;
  *   28-33  box tests and passes: ring-2 cells, blocks, cells of passing
  *          blocks;

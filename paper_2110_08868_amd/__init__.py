@@ -56,7 +56,7 @@ class _Options(ctypes.Structure):
         ("cg_rtol", ctypes.c_double), ("grid_occupancy", ctypes.c_double),
         ("mem_budget_bytes", ctypes.c_size_t), ("verbose", ctypes.c_int32),
         ("first_stage", ctypes.c_int32), ("batch_window_us", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("cg_precond", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
     ]
 
 

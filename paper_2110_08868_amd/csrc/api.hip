@@ -218,7 +218,8 @@ mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
   }
   const int nstage = c->opt.precision == MAK_MIXED ? 3 : 2;
   if (!(c->opt.cg_rtol > 0) || c->opt.max_newton < 0 || c->opt.max_cg < 1 || c->opt.max_halvings < 0 ||
-      c->opt.first_stage < 0 || c->opt.first_stage >= nstage) {
+      c->opt.first_stage < 0 || c->opt.first_stage >= nstage || c->opt.cg_precond < 0 ||
+      c->opt.cg_precond > 1) {
     delete c;
     g_create_error = "invalid options";
     return MAK_EINVAL;
@@ -524,8 +525,11 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
       const bool warm = it > 0 && prev_alpha < 1.0;
       if (warm)
         axpy_into(ctx->pstep.as<double>(), ctx->pstep.as<double>(), -prev_alpha, ctx->pstep.as<double>(), N, st);
+      RowBlocks rb;
+      rb.cell_start = ps.cell_start.as<int32_t>();
+      rb.Gb = ps.g.Gb;
       const int cgi = pcg_solve(ctx->sJ, ctx->g.as<double>(), ctx->pstep.as<double>(), N, o.cg_rtol,
-                                o.max_cg, ctx->pw, st, warm);
+                                o.max_cg, ctx->pw, st, warm, o.cg_precond == 0 ? &rb : nullptr);
       si.cg_iters_total += cgi;
       doomed_cells.clear();
       // the smallest cells of the accepted pass follow the doomed ones in the list

@@ -361,6 +361,11 @@ void fill_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 
 struct PcgWork {
   DevBuf r, z, p, q, s, dinv, part, part2, scal;
+  // three-level preconditioner: row -> grid block; per block the residual
+  // sum, the inverse of the weight leaving it and its weights towards the
+  // 26 neighbouring aggregates; per aggregate those weights summed and the
+  // exact level's correction; the inverse of the aggregates' Laplacian
+  DevBuf blk_row, r1, d1inv, a1c, aggw, cc, ainv;
   // host side of the convergence checks: two pinned flags and their events
   double* hflag = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -382,12 +387,20 @@ struct PcgWork {
       if (!e) MAK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
 };
-// Solve J x = b - mean(b) with Jacobi-preconditioned CG to
-// ||r|| <= rtol ||b - mean(b)||; x is overwritten (mean zero on return).  It
-// starts from 0, or with `warm` from the x given when that residual is below
-// ||b - mean(b)||.  Returns the iteration count.
+// The neighbour grid of the rows of J (sites sorted block-major): block b
+// holds rows cell_start[64 b] .. cell_start[64 b + 64) of the Gb^3 blocks.
+struct RowBlocks {
+  const int32_t* cell_start = nullptr;
+  int32_t Gb = 0;
+};
+// Solve J x = b - mean(b) with preconditioned CG to ||r|| <= rtol ||b -
+// mean(b)||; x is overwritten (mean zero on return).  The preconditioner is
+// point Jacobi, or with `blocks` the three-level additive one (point Jacobi,
+// Jacobi on the grid blocks, an exact solve on at most 64 aggregates of
+// blocks).  It starts from 0, or with `warm` from the x given when that
+// residual is below ||b - mean(b)||.  Returns the iteration count.
 int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
-              PcgWork& w, hipStream_t st, bool warm = false);
+              PcgWork& w, hipStream_t st, bool warm = false, const RowBlocks* blocks = nullptr);
 
 // Elementwise helpers for the Newton driver.
 // Target masses: per site (ms, sorted order) or, when ms is NULL, m for all.

@@ -3,6 +3,7 @@
 // as null space; g has zero mean, so CG stays in the range of J), plus the
 // elementwise kernels of the Newton driver.  All reductions use a fixed grid
 // and a fixed tree, so results are reproducible run to run.
+#include <algorithm>
 #include <cfloat>
 
 #include "engine.h"
@@ -17,7 +18,8 @@ constexpr int MAXB = 1024;       // blocks of the grid-stride vector kernels
 constexpr int SPMV_MAXB = 8192;  // blocks of the SpMV (grid-stride over rows)
 
 // scalar slots (device doubles)
-enum { S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6, S_DONE = 7, S_ITER = 8 };
+enum { S_GAMMA = 0, S_ALPHA = 1, S_BETA = 2, S_RR = 3, S_BB = 4, S_MEAN = 5, S_TMP = 6, S_DONE = 7, S_ITER = 8,
+       S_CDOT = 9 };
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   v = wave_sum_d(v);
@@ -217,7 +219,8 @@ __global__ __launch_bounds__(TPB) void k_cg_update(double* __restrict__ x, doubl
 constexpr int SCAL_TPB = 1024;
 __global__ __launch_bounds__(SCAL_TPB) void k_cg_scalars(const double* __restrict__ pu, int nu,
                                                          const double* __restrict__ ps, int nsp,
-                                                         double* __restrict__ scal, int first, double stop) {
+                                                         double* __restrict__ scal, int first, double stop,
+                                                         int coarse) {
   __shared__ double sh[3][SCAL_TPB / WAVE];
   if (scal[S_DONE] != 0.0) return;
   double a = 0.0, b = 0.0, c = 0.0;
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(SCAL_TPB) void k_cg_scalars(const double* __restric
       b += sh[1][k];
       c += sh[2][k];
     }
-    const double gn = a;
+    const double gn = a + (coarse ? scal[S_CDOT] : 0.0);  // r.u with the coarse levels' part
     double beta = 0.0, den = c;
     if (!first) {
       beta = scal[S_GAMMA] > 0.0 ? gn / scal[S_GAMMA] : 0.0;
@@ -329,10 +332,335 @@ __global__ void k_sub_mean(double* __restrict__ x, const double* __restrict__ sc
   x[i] -= scal[slot] / double(n);
 }
 
+// ---------------------------------------------------------------- three-level preconditioner
+// M^-1 r = D^-1 r + P1 D1^-1 P1' r + P1 P2 A2^+ P2' P1' r: point Jacobi, plus
+// Jacobi on the aggregates of the neighbour-grid blocks (P1 sums the rows of
+// a block; D1 is the diagonal of the Galerkin product P1' J P1, the weight
+// leaving the block), plus an exact solve on nd^3 <= 64 aggregates of
+// dv^3 blocks (A2 = P2' P1' J P1 P2, a Laplacian, pinned at aggregate 0).
+// Every term is symmetric positive semi-definite, so M is a valid CG
+// preconditioner.  The sums over a block run in one wavefront in a fixed
+// order: the results are the same bits on every run.
+constexpr int ML_WPB = TPB / WAVE;  // wavefronts (blocks) per workgroup
+constexpr int ML_MAXC = 64;         // aggregates of the exact level
+
+struct MlGeo {
+  const int32_t* cs;  // cell_start: block b rows [cs[64 b], cs[64 b + 64])
+  int32_t Gb, dv, nd;
+  int64_t nblk;
+};
+
+__device__ __forceinline__ int ml_agg(int64_t b, const MlGeo& g) {
+  const int bx = int(b / (int64_t(g.Gb) * g.Gb)), by = int((b / g.Gb) % g.Gb), bz = int(b % g.Gb);
+  return ((bx / g.dv) * g.nd + by / g.dv) * g.nd + bz / g.dv;
+}
+
+__global__ void k_ml_blk_rows(MlGeo g, int32_t* __restrict__ blk_row) {
+  const int64_t b = int64_t(blockIdx.x) * ML_WPB + threadIdx.x / WAVE;
+  if (b >= g.nblk) return;
+  for (int32_t i = g.cs[64 * b] + lane_id(); i < g.cs[64 * b + 64]; i += WAVE) blk_row[i] = int32_t(b);
+}
+
+// Per block: 1 / (weight leaving it) and its weights towards the 26
+// neighbouring aggregates of the exact level (slot (dx+1) 9 + (dy+1) 3 +
+// (dz+1), aggregate offsets wrapped periodically; an edge to an aggregate
+// farther than one step is left out of the exact level only).
+template <typename W>
+__global__ __launch_bounds__(TPB) void k_ml_setup(MlGeo g, const int64_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col, const W* __restrict__ w,
+                                                  const int32_t* __restrict__ blk_row,
+                                                  double* __restrict__ d1inv, double* __restrict__ a1c) {
+  const int64_t b = int64_t(blockIdx.x) * ML_WPB + threadIdx.x / WAVE;
+  if (b >= g.nblk) return;
+  const int G = g.Gb, nd = g.nd, dv = g.dv;
+  const int bx = int(b / (int64_t(G) * G)), by = int((b / G) % G), bz = int(b % G);
+  const int cx = bx / dv, cy = by / dv, cz = bz / dv;
+  double out = 0.0;
+  double acc[27];
+#pragma unroll
+  for (int q = 0; q < 27; ++q) acc[q] = 0.0;
+  for (int32_t i = g.cs[64 * b] + lane_id(); i < g.cs[64 * b + 64]; i += WAVE) {
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+      const int32_t bj = blk_row[col[k]];
+      if (bj == b) continue;
+      const double wt = double(w[k]);
+      out += wt;
+      const int jx = int(bj / (G * G)), jy = (bj / G) % G, jz = bj % G;
+      auto wrap = [nd](int d) {  // aggregate offset in (-nd/2, nd/2]
+        d %= nd;
+        if (d < 0) d += nd;
+        return 2 * d > nd ? d - nd : d;
+      };
+      const int dx = wrap(jx / dv - cx), dy = wrap(jy / dv - cy), dz = wrap(jz / dv - cz);
+      if ((dx | dy | dz) == 0 || dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) continue;
+      const int slot = (dx + 1) * 9 + (dy + 1) * 3 + (dz + 1);
+#pragma unroll
+      for (int q = 0; q < 27; ++q) acc[q] += q == slot ? wt : 0.0;
+    }
+  }
+  out = wave_sum_d(out);
+#pragma unroll
+  for (int q = 0; q < 27; ++q) acc[q] = wave_sum_d(acc[q]);
+  if (lane_id() == 0) {
+    d1inv[b] = out > 0.0 ? 1.0 / out : 0.0;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) a1c[27 * b + q] = acc[q];
+  }
+}
+
+// Block b of aggregate c: the li-th block in x-major order of the
+// aggregate's dv^3 (fewer at the far end when dv does not divide Gb), or -1.
+__device__ __forceinline__ int64_t ml_agg_block(const MlGeo& g, int c, int li) {
+  const int nd = g.nd, dv = g.dv;
+  const int bx = (c / (nd * nd)) * dv + li / (dv * dv), by = ((c / nd) % nd) * dv + (li / dv) % dv,
+            bz = (c % nd) * dv + li % dv;
+  if (bx >= g.Gb || by >= g.Gb || bz >= g.Gb) return -1;
+  return (int64_t(bx) * g.Gb + by) * g.Gb + bz;
+}
+
+// Per aggregate of the exact level (one workgroup each): its blocks' weights
+// towards the 26 neighbouring aggregates summed per slot, nine groups of 27
+// threads each taking every ninth block, then the groups in a fixed order.
+constexpr int ML_AGG_TPB = 256;
+__global__ __launch_bounds__(ML_AGG_TPB) void k_ml_aggsum(MlGeo g, const double* __restrict__ a1c,
+                                                          double* __restrict__ aggw) {
+  __shared__ double part[9][27];
+  const int c = blockIdx.x;
+  const int t = threadIdx.x, grp = t / 27, q = t % 27;
+  const int nblk = g.dv * g.dv * g.dv;
+  if (grp < 9) {
+    double v = 0.0;
+    for (int li = grp; li < nblk; li += 9) {
+      const int64_t b = ml_agg_block(g, c, li);
+      if (b >= 0) v += a1c[27 * b + q];
+    }
+    part[grp][q] = v;
+  }
+  __syncthreads();
+  if (t < 27) {
+    double v = 0.0;
+    for (int k = 0; k < 9; ++k) v += part[k][t];
+    aggw[27 * c + t] = v;
+  }
+}
+
+// The exact level: A2 from the aggregates' neighbour weights, symmetrised,
+// its diagonal the row sums, pinned at aggregate 0, inverted in LDS by
+// Gauss-Jordan elimination (no pivoting: the pinned Laplacian of a
+// connected set of aggregates is positive definite; a zero pivot, from an
+// aggregate with no weight to the others, leaves its row and column zero).
+__global__ __launch_bounds__(256) void k_ml_dense(MlGeo g, const double* __restrict__ aggw,
+                                                   double* __restrict__ ainv) {
+  __shared__ double A[ML_MAXC][ML_MAXC];
+  __shared__ double rowk[ML_MAXC], fcol[ML_MAXC];
+  const int nc = g.nd * g.nd * g.nd;
+  const int t = threadIdx.x;
+  for (int e = t; e < ML_MAXC * ML_MAXC; e += 256) A[e / ML_MAXC][e % ML_MAXC] = 0.0;
+  __syncthreads();
+  if (t < nc) {
+    const int nd = g.nd;
+    const int cx = t / (nd * nd), cy = (t / nd) % nd, cz = t % nd;
+    for (int q = 0; q < 27; ++q) {
+      const double v = aggw[27 * t + q];
+      if (v == 0.0) continue;
+      const int ox = (cx + q / 9 - 1 + nd) % nd, oy = (cy + (q / 3) % 3 - 1 + nd) % nd,
+                oz = (cz + q % 3 - 1 + nd) % nd;
+      const int c2 = (ox * nd + oy) * nd + oz;
+      if (c2 != t) A[t][c2] -= v;
+    }
+  }
+  __syncthreads();
+  // symmetrise the off-diagonal part (the two sides of a face are computed
+  // apart), then the diagonal = minus the off-diagonal row sum
+  double sym[ML_MAXC * ML_MAXC / 256];
+  for (int e = t, k = 0; e < ML_MAXC * ML_MAXC; e += 256, ++k) {
+    const int i = e / ML_MAXC, j = e % ML_MAXC;
+    sym[k] = (i < nc && j < nc && i != j) ? 0.5 * (A[i][j] + A[j][i]) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t, k = 0; e < ML_MAXC * ML_MAXC; e += 256, ++k) A[e / ML_MAXC][e % ML_MAXC] = sym[k];
+  __syncthreads();
+  if (t < nc) {
+    double sum = 0.0;
+    for (int j = 0; j < nc; ++j) sum += A[t][j];
+    fcol[t] = -sum;
+  }
+  __syncthreads();
+  if (t < nc) A[t][t] = fcol[t];
+  __syncthreads();
+  if (t < nc) {  // pin aggregate 0
+    A[0][t] = t == 0 ? 1.0 : 0.0;
+    A[t][0] = t == 0 ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < nc; ++k) {
+    const double piv = A[k][k];
+    const double ip = piv > 0.0 ? 1.0 / piv : 0.0;
+    __syncthreads();
+    if (t < nc) {
+      rowk[t] = (t == k ? 1.0 : A[k][t]) * ip;
+      fcol[t] = t == k ? 0.0 : A[t][k];
+    }
+    __syncthreads();
+    for (int e = t; e < nc * nc; e += 256) {
+      const int i = e / nc, j = e % nc;
+      if (i == k)
+        A[i][j] = rowk[j];
+      else
+        A[i][j] = (j == k ? 0.0 : A[i][j]) - fcol[i] * rowk[j];
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < nc * nc; e += 256) ainv[e] = A[e / nc][e % nc];
+}
+
+// r = b - mean (- q = J x when warm; else x = 0); p = s = 0; per block the
+// sum of r; partials of r.(D^-1 r) and r.r.  One wavefront per block.
+__global__ __launch_bounds__(TPB) void k_ml_init(MlGeo g, const double* __restrict__ b,
+                                                 const double* __restrict__ scal, const double* __restrict__ q,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ p, double* __restrict__ s,
+                                                 const double* __restrict__ dinv, double* __restrict__ r1,
+                                                 const double* __restrict__ d1inv, double* __restrict__ part,
+                                                 int64_t n) {
+  __shared__ double sh[TPB / WAVE];
+  const double mean = scal[S_MEAN] / double(n);
+  double aru = 0.0, arr = 0.0;
+  for (int64_t blk = int64_t(blockIdx.x) * ML_WPB + threadIdx.x / WAVE; blk < g.nblk;
+       blk += int64_t(gridDim.x) * ML_WPB) {
+    double rs = 0.0;
+    for (int32_t i = g.cs[64 * blk] + lane_id(); i < g.cs[64 * blk + 64]; i += WAVE) {
+      double ri = b[i] - mean;
+      if (q)
+        ri -= q[i];
+      else
+        x[i] = 0.0;
+      r[i] = ri;
+      p[i] = 0.0;
+      s[i] = 0.0;
+      aru += ri * dinv[i] * ri;
+      arr += ri * ri;
+      rs += ri;
+    }
+    rs = wave_sum_d(rs);
+    if (lane_id() == 0) {
+      r1[blk] = rs;
+      aru += rs * d1inv[blk] * rs;  // the block level's part of r.u
+    }
+  }
+  aru = block_sum(aru, sh);
+  arr = block_sum(arr, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = aru;
+    part[2 * blockIdx.x + 1] = arr;
+  }
+}
+
+// The CG update of k_cg_update without the preconditioned residual (it
+// needs the coarse levels of the new r): p = u + beta p, s = w + beta s,
+// x += alpha p, r -= alpha s; per block the sum of r; partials of
+// r.(D^-1 r) and r.r.
+__global__ __launch_bounds__(TPB) void k_ml_update(MlGeo g, double* __restrict__ x, double* __restrict__ r,
+                                                   const double* __restrict__ u, double* __restrict__ p,
+                                                   double* __restrict__ s, const double* __restrict__ w,
+                                                   const double* __restrict__ dinv,
+                                                   const double* __restrict__ scal, double* __restrict__ r1,
+                                                   const double* __restrict__ d1inv, double* __restrict__ part) {
+  __shared__ double sh[TPB / WAVE];
+  if (scal[S_DONE] != 0.0) return;
+  const double alpha = scal[S_ALPHA], beta = scal[S_BETA];
+  double aru = 0.0, arr = 0.0;
+  for (int64_t blk = int64_t(blockIdx.x) * ML_WPB + threadIdx.x / WAVE; blk < g.nblk;
+       blk += int64_t(gridDim.x) * ML_WPB) {
+    double rs = 0.0;
+    for (int32_t i = g.cs[64 * blk] + lane_id(); i < g.cs[64 * blk + 64]; i += WAVE) {
+      const double pi = u[i] + beta * p[i];
+      const double si = w[i] + beta * s[i];
+      p[i] = pi;
+      s[i] = si;
+      x[i] += alpha * pi;
+      const double ri = r[i] - alpha * si;
+      r[i] = ri;
+      aru += ri * dinv[i] * ri;
+      arr += ri * ri;
+      rs += ri;
+    }
+    rs = wave_sum_d(rs);
+    if (lane_id() == 0) {
+      r1[blk] = rs;
+      aru += rs * d1inv[blk] * rs;  // the block level's part of r.u
+    }
+  }
+  aru = block_sum(aru, sh);
+  arr = block_sum(arr, sh);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = aru;
+    part[2 * blockIdx.x + 1] = arr;
+  }
+}
+
+// The exact level in one workgroup: the aggregates' residuals (sixteen
+// threads per aggregate, each summing every sixteenth block, then a fixed
+// tree), the solve e = A2^+ r_agg (sixteen threads per row), and its part
+// of r.u, sum_agg r_agg e_agg (the correction is constant over an
+// aggregate).  The block level's part of r.u comes from the update kernel.
+constexpr int ML_CTPB = 1024;
+__global__ __launch_bounds__(ML_CTPB) void k_ml_coarse(MlGeo g, const double* __restrict__ r1,
+                                                       const double* __restrict__ ainv, double* __restrict__ ec,
+                                                       double* __restrict__ scal) {
+  __shared__ double rc[ML_MAXC], es[ML_MAXC];
+  static_assert(ML_CTPB >= 16 * ML_MAXC, "sixteen threads per aggregate");
+  if (scal[S_DONE] != 0.0) return;
+  const int nc = g.nd * g.nd * g.nd;
+  const int t = threadIdx.x, c = t / 16, s16 = t % 16;
+  const int nblk = g.dv * g.dv * g.dv;
+  double v = 0.0;
+  if (c < nc) {
+#pragma unroll 4
+    for (int li = s16; li < nblk; li += 16) {
+      const int64_t b = ml_agg_block(g, c, li);
+      if (b >= 0) v += r1[b];
+    }
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  if (c < nc && s16 == 0) rc[c] = c == 0 ? 0.0 : v;  // pinned aggregate
+  __syncthreads();
+  double e = 0.0;
+  if (c < nc)
+    for (int j = s16; j < nc; j += 16) e += ainv[c * nc + j] * rc[j];
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) e += __shfl_xor(e, o);
+  if (c < nc && s16 == 0) {
+    e = c == 0 ? 0.0 : e;
+    ec[c] = e;
+    es[c] = e;
+  }
+  __syncthreads();
+  if (t == 0) {
+    double d = 0.0;
+    for (int k = 0; k < nc; ++k) d += rc[k] * es[k];
+    scal[S_CDOT] = d;
+  }
+}
+
+// u = D^-1 r + r1_b / D1_b + e_agg(b), the correction constant over block b
+__global__ __launch_bounds__(TPB) void k_ml_apply(MlGeo g, const double* __restrict__ r,
+                                                  const double* __restrict__ dinv, const double* __restrict__ r1,
+                                                  const double* __restrict__ d1inv, const double* __restrict__ ec,
+                                                  double* __restrict__ u, const double* __restrict__ scal) {
+  if (scal[S_DONE] != 0.0) return;
+  for (int64_t blk = int64_t(blockIdx.x) * ML_WPB + threadIdx.x / WAVE; blk < g.nblk;
+       blk += int64_t(gridDim.x) * ML_WPB) {
+    const double c = r1[blk] * d1inv[blk] + ec[ml_agg(blk, g)];
+    for (int32_t i = g.cs[64 * blk] + lane_id(); i < g.cs[64 * blk + 64]; i += WAVE) u[i] = dinv[i] * r[i] + c;
+  }
+}
+
 }  // namespace
 
 int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, int max_iter,
-              PcgWork& w, hipStream_t st, bool warm) {
+              PcgWork& w, hipStream_t st, bool warm, const RowBlocks* blocks) {
   ProfScope whole("pcg_solve", st, double(n));
   w.r.ensure(size_t(n) * sizeof(double));
   w.z.ensure(size_t(n) * sizeof(double));
@@ -373,28 +701,82 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
                          J.col.as<int32_t>(), J.w.as<double>(), J.diag.as<double>(), v, qv, part2,
                          scal + S_DONE, n);
   };
+  // three-level preconditioner: geometry, the blocks' weights and the exact
+  // level's inverse for this J
+  const bool ml = blocks && blocks->cell_start && blocks->Gb >= 1;
+  MlGeo geo{};
+  unsigned nbm = 1;
+  if (ml) {
+    geo.cs = blocks->cell_start;
+    geo.Gb = blocks->Gb;
+    geo.dv = int32_t(ceil_div(geo.Gb, 4));    // at most 4 aggregates per axis
+    geo.nd = int32_t(ceil_div(geo.Gb, geo.dv));
+    geo.nblk = int64_t(geo.Gb) * geo.Gb * geo.Gb;
+    nbm = unsigned(std::min<int64_t>(ceil_div(geo.nblk, ML_WPB), MAXB));
+    w.blk_row.ensure(size_t(n) * sizeof(int32_t));
+    w.r1.ensure(size_t(geo.nblk) * sizeof(double));
+    w.d1inv.ensure(size_t(geo.nblk) * sizeof(double));
+    w.cc.ensure(size_t(ML_MAXC) * sizeof(double));
+    w.a1c.ensure(size_t(geo.nblk) * 27 * sizeof(double));
+    w.ainv.ensure(size_t(ML_MAXC) * ML_MAXC * sizeof(double));
+    w.aggw.ensure(size_t(ML_MAXC) * 27 * sizeof(double));
+    const unsigned nbb = unsigned(ceil_div(geo.nblk, ML_WPB));
+    ProfScope ps("pcg_setup", st, double(n));
+    hipLaunchKernelGGL(k_ml_blk_rows, dim3(nbb), dim3(TPB), 0, st, geo, w.blk_row.as<int32_t>());
+    if (J.f32)
+      hipLaunchKernelGGL(k_ml_setup<float>, dim3(nbb), dim3(TPB), 0, st, geo, J.row_ptr.as<int64_t>(),
+                         J.col.as<int32_t>(), J.w.as<float>(), w.blk_row.as<int32_t>(), w.d1inv.as<double>(),
+                         w.a1c.as<double>());
+    else
+      hipLaunchKernelGGL(k_ml_setup<double>, dim3(nbb), dim3(TPB), 0, st, geo, J.row_ptr.as<int64_t>(),
+                         J.col.as<int32_t>(), J.w.as<double>(), w.blk_row.as<int32_t>(), w.d1inv.as<double>(),
+                         w.a1c.as<double>());
+    const int nc = geo.nd * geo.nd * geo.nd;
+    hipLaunchKernelGGL(k_ml_aggsum, dim3(unsigned(nc)), dim3(ML_AGG_TPB), 0, st, geo, w.a1c.as<double>(),
+                       w.aggw.as<double>());
+    hipLaunchKernelGGL(k_ml_dense, dim3(1), dim3(256), 0, st, geo, w.aggw.as<double>(), w.ainv.as<double>());
+    MAK_HIP(hipGetLastError());
+  }
+  // u = M^-1 r of the three-level preconditioner, from the blocks' sums r1
+  // left by the init / update kernel
+  auto ml_apply = [&]() {
+    hipLaunchKernelGGL(k_ml_coarse, dim3(1), dim3(ML_CTPB), 0, st, geo, w.r1.as<double>(), w.ainv.as<double>(),
+                       w.cc.as<double>(), scal);
+    hipLaunchKernelGGL(k_ml_apply, dim3(nbm), dim3(TPB), 0, st, geo, r, dinv, w.r1.as<double>(),
+                       w.d1inv.as<double>(), w.cc.as<double>(), u, scal);
+  };
   hipLaunchKernelGGL(k_diag_inv, dim3(nbe), dim3(256), 0, st, J.diag.as<double>(), dinv, n);
   hipLaunchKernelGGL(k_sum_part, dim3(nb), dim3(TPB), 0, st, b, part, n);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_MEAN), 0);
   hipLaunchKernelGGL(k_sq_part, dim3(nb), dim3(TPB), 0, st, b, scal, part, n);
   hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 1, scal, int(S_BB), 0);
-  double hb[8];
+  double hb[16];
+  // r0 (from b, or with `q` from b - J x), the first preconditioned residual
+  // and the partials of r.u and r.r
+  const unsigned nbu = ml ? nbm : nb;  // workgroups of the update kernel (its partials)
+  auto init = [&](const double* q) {
+    if (ml) {
+      hipLaunchKernelGGL(k_ml_init, dim3(nbm), dim3(TPB), 0, st, geo, b, scal, q, x, r, p, sv, dinv,
+                         w.r1.as<double>(), w.d1inv.as<double>(), part, n);
+      ml_apply();
+    } else {
+      hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(TPB), 0, st, b, scal, q, x, r, u, p, sv, dinv, part, n);
+    }
+  };
   if (warm) {
     // start from the given x: r0 = b - J x; kept only if |r0| < |b|
     spmv(x, wv);
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(TPB), 0, st, b, scal, wv, x, r, u, p, sv, dinv, part, n);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nb), 2, scal, int(S_TMP), int(S_RR));
+    init(wv);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(TPB), 0, st, part, int(nbu), 2, scal, int(S_TMP), int(S_RR));
     MAK_HIP(hipGetLastError());
     MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
     MAK_HIP(hipStreamSynchronize(st));
     if (!(hb[S_RR] < hb[S_BB])) warm = false;
   }
-  if (!warm)
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(TPB), 0, st, b, scal, nullptr, x, r, u, p, sv, dinv, part,
-                       n);
+  if (!warm) init(nullptr);
   spmv(u, wv);
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 1,
-                     -1.0);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nbu), part2, int(nbs), scal, 1,
+                     -1.0, ml ? 1 : 0);
   MAK_HIP(hipGetLastError());
   MAK_HIP(hipMemcpyAsync(hb, scal, sizeof(hb), hipMemcpyDeviceToHost, st));
   MAK_HIP(hipStreamSynchronize(st));
@@ -411,13 +793,22 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
   bool done = false;
   for (int it = 0; it < max_iter && !done; ++it) {
     {
-      ProfScope ps("pcg_update", st, double(n), 96.0 * double(n));
+      // compulsory bytes: the update reads u, w, p, s, x, r and D^-1 and
+      // writes p, s, x, r and u (the three-level form writes u in its apply
+      // kernel, reading r and D^-1 again)
+      ProfScope ps("pcg_update", st, double(n), (ml ? 112.0 : 96.0) * double(n));
       ps.flops = 14.0 * double(n);
-      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(TPB), 0, st, x, r, u, p, sv, wv, dinv, scal, part, n);
+      if (ml) {
+        hipLaunchKernelGGL(k_ml_update, dim3(nbm), dim3(TPB), 0, st, geo, x, r, u, p, sv, wv, dinv, scal,
+                           w.r1.as<double>(), w.d1inv.as<double>(), part);
+        ml_apply();
+      } else {
+        hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(TPB), 0, st, x, r, u, p, sv, wv, dinv, scal, part, n);
+      }
     }
     spmv(u, wv);
-    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nb), part2, int(nbs), scal, 0,
-                       stop);
+    hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(SCAL_TPB), 0, st, part, int(nbu), part2, int(nbs), scal, 0,
+                       stop, ml ? 1 : 0);
     if ((it & 7) == 7) {
       if (pending >= 0) {
         MAK_HIP(hipEventSynchronize(w.ev[pending]));
