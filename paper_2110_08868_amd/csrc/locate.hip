@@ -56,6 +56,7 @@ struct LocArgs {
   const double* q;         // (Q, 3) query points, or NULL for the mesh
   int64_t Q;               // number of queries (mesh: ng^3)
   int64_t ng, nb;          // mesh nodes and 4-node bricks per axis
+  int64_t nt;              // tiles of kTile^3 bricks per axis (mesh form)
   double mesh_h, mesh_off; // mesh spacing and node offset (in spacings)
   double L, h;
   int Gn, Gb;
@@ -321,6 +322,7 @@ __device__ __forceinline__ void deposit_element(const DepArgs& D, double L, doub
 // candidate values, and a minimum does not depend on the order); only ties
 // may pick another site.  DEP: then deposit the element (Zel'dovich step).
 constexpr int kStage = 256;
+constexpr int64_t kTile = 4;  // bricks per tile side in the mesh form's order
 
 template <bool DEP>
 __global__ __launch_bounds__(64) void k_mesh_coop(LocArgs A, DepArgs D) {
@@ -330,12 +332,20 @@ __global__ __launch_bounds__(64) void k_mesh_coop(LocArgs A, DepArgs D) {
   const int lane = threadIdx.x;
   const int64_t wg = int64_t(blockIdx.y) * gridDim.x + blockIdx.x;
   if ((wg >> 3) >= A.per_xcd) return;
-  const int64_t brick = (wg & 7) * A.per_xcd + (wg >> 3);
-  const int64_t nb = A.nb;
-  if (brick >= nb * nb * nb) return;
-  const int64_t a = 4 * (brick / (nb * nb)) + (lane >> 4);
-  const int64_t b = 4 * ((brick / nb) % nb) + ((lane >> 2) & 3);
-  const int64_t c = 4 * (brick % nb) + (lane & 3);
+  // bricks in tiles of kTile^3 (tiles x-major, bricks x-major within a
+  // tile): the bricks an XCD runs at once form a compact region, whose blocks
+  // its L2 then serves to the neighbouring bricks
+  const int64_t item = (wg & 7) * A.per_xcd + (wg >> 3);
+  const int64_t nb = A.nb, nt = A.nt;
+  const int64_t tile = item / (kTile * kTile * kTile), in = item % (kTile * kTile * kTile);
+  if (tile >= nt * nt * nt) return;
+  const int64_t bxi = kTile * (tile / (nt * nt)) + in / (kTile * kTile);
+  const int64_t byi = kTile * ((tile / nt) % nt) + (in / kTile) % kTile;
+  const int64_t bzi = kTile * (tile % nt) + in % kTile;
+  if (bxi >= nb || byi >= nb || bzi >= nb) return;
+  const int64_t a = 4 * bxi + (lane >> 4);
+  const int64_t b = 4 * byi + ((lane >> 2) & 3);
+  const int64_t c = 4 * bzi + (lane & 3);
   const bool valid = a < A.ng && b < A.ng && c < A.ng;
   const double L = A.L, h = A.h, bh = BLOCK_SIDE * h;
   const double q0x = (double(a) + A.mesh_off) * A.mesh_h, q0y = (double(b) + A.mesh_off) * A.mesh_h,
@@ -507,15 +517,17 @@ LocArgs loc_args(const PointSet& ps) {
 void set_mesh(LocArgs& a, int64_t ng, double offset) {
   a.ng = ng;
   a.nb = ceil_div(ng, 4);
+  a.nt = ceil_div(a.nb, kTile);
   a.Q = ng * ng * ng;
   a.mesh_h = a.L / double(ng);
   a.mesh_off = offset;
 }
 
-// Grid of one 64-lane workgroup per 4^3-node brick of the mesh, dealt to the
-// XCDs in contiguous ranges (2-D above 65536 workgroups).
+// Grid of one 64-lane workgroup per 4^3-node brick of the mesh (the bricks
+// of whole tiles, those past the mesh returning at once), dealt to the XCDs
+// in contiguous ranges (2-D above 65536 workgroups).
 dim3 brick_grid(LocArgs& a) {
-  const int64_t bricks = a.nb * a.nb * a.nb;
+  const int64_t bricks = a.nt * a.nt * a.nt * kTile * kTile * kTile;
   a.per_xcd = ceil_div(bricks, 8);
   const int64_t total = 8 * a.per_xcd;
   const int64_t gx = total < 65536 ? total : 65536;
