@@ -79,7 +79,14 @@ typedef struct {
                               aggregates of the neighbour-grid blocks, an exact
                               solve on at most 64 aggregates of those), 1 point
                               Jacobi alone */
-  int32_t reserved[4];
+  int32_t walk_cert;       /* 1 (default): once the Newton steps are undamped,
+                              one cell pass records for each cell the sites
+                              that can still cut it while the weights move by
+                              less than a margin, and later passes within it
+                              clip those sites only (same cells, shorter
+                              search); 0: every pass searches in full.  Holds
+                              about 250 more bytes per site. */
+  int32_t reserved[3];
 } mak_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -372,7 +379,11 @@ int32_t mak_profile_read(mak_ctx* ctx, mak_kernel_profile* out, int32_t max_entr
  *   24-27  planes that removed vertices, by the same phases;
  *   28-33  box tests and passes: ring-2 cells, blocks, cells of passing
  *          blocks;
- *   34     the last block shell reached, summed over cells.
+ *   34     the last block shell reached, summed over cells;
+ *   35-39  walk certificates of the solver (walk_cert): cells that recorded
+ *          one, the sites they list, cells whose list overflowed; cells
+ *          whose weights stayed within the margin (they clip the listed
+ *          sites first) and, of those, cells whose walk was skipped.
  * Unused entries are zero. */
 mak_status mak_profile_counters(mak_ctx* ctx, double* out);
 

@@ -54,7 +54,8 @@ size_t solve_bytes_per_site(int64_t N) {
   // below that.
   const size_t fslot = size_t(face_slots(N));
   const size_t faces = fslot * sizeof(FaceRec) + 8 + 2 * sizeof(FaceRec);
-  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 24 * 8 + 1 + 48 + 40;
+  //   walk certificates (kCertBytesPerSite, with walk_cert on)
+  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 24 * 8 + 1 + 48 + 40 + kCertBytesPerSite;
 }
 
 namespace {
@@ -123,6 +124,7 @@ struct mak_ctx {
   PcgWork pw;
   DevBuf psi_s, psi_t, g, pstep, mass_s, tmp;
   DevBuf probe_list, probe_tmp;  // probe cells of a trial: earlier rejecting cells + the smallest
+  CertSet scert;                 // walk certificates of the solve
   // Legendre transform / point location
   PointSet lps;
   DevBuf lstatus, dep_acc;
@@ -190,6 +192,7 @@ void mak_default_options(mak_options* opt) {
   opt->grid_occupancy = 2.5;
   opt->mem_budget_bytes = 0;
   opt->verbose = 0;
+  opt->walk_cert = 1;
 }
 
 mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
@@ -219,7 +222,7 @@ mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
   const int nstage = c->opt.precision == MAK_MIXED ? 3 : 2;
   if (!(c->opt.cg_rtol > 0) || c->opt.max_newton < 0 || c->opt.max_cg < 1 || c->opt.max_halvings < 0 ||
       c->opt.first_stage < 0 || c->opt.first_stage >= nstage || c->opt.cg_precond < 0 ||
-      c->opt.cg_precond > 1) {
+      c->opt.cg_precond > 1 || c->opt.walk_cert < 0 || c->opt.walk_cert > 1) {
     delete c;
     g_create_error = "invalid options";
     return MAK_EINVAL;
@@ -469,10 +472,21 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         MAK_FAIL(MAK_EINVAL, "masses must be positive and sum to L^3");
     }
 
+    // Walk certificates (PassOpts::cert_mode): once the Newton steps are
+    // undamped (a full step after a full step), one trial records them;
+    // every later pass uses them.  Margin and widening scale with the mean
+    // site spacing s: 0.05 s^2 in weight, 0.05 s in space.
+    CertSet& ce = ctx->scert;
+    ce.valid = false;
+    const bool certs = o.walk_cert != 0 && N >= 2 && N <= (int64_t(1) << 27);
+    const double spacing = L / std::cbrt(double(N));
+    int cur_cert = 0;
     auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Lap* warm, int64_t probe_n = 0,
                     const int32_t* probe_list = nullptr) {
       PassOpts po;
       po.precision = o.precision;
+      po.cert_mode = cur_cert;
+      po.cert = cur_cert ? &ce : nullptr;
       po.tolerate_failure = tolerate;
       po.doom_vol = doom_vol;
       if (warm && warm->n == N) {
@@ -541,6 +555,11 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         axpy_into(ctx->psi_s.as<double>(), ctx->pstep.as<double>(), alpha, ctx->psi_t.as<double>(), N, st);
         set_psi_sorted(ps, ctx->psi_t.as<double>(), st);
         const auto tp0 = std::chrono::steady_clock::now();
+        cur_cert = 0;
+        if (ce.valid) {
+          cert_dmax(ps, ce, st);
+          cur_cert = 2;
+        }
         const int64_t nd = int64_t(doomed_cells.size());
         if (nd + n_small > 0) {
           // doomed cells fill the slots just before the smallest ones
@@ -564,7 +583,20 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         // a trial with a cell below eps0 is rejected whatever else it gives:
         // the pass stops at the first such cell
         // the accepted pass's neighbours (J) warm-start the trial
+        if (certs && !ce.valid && it > 0 && alpha == 1.0 && prev_alpha == 1.0) {
+          ce.list.ensure(size_t(N) * kCertCap * sizeof(uint32_t));
+          ce.n.ensure(size_t(N) * sizeof(int32_t));
+          ce.vtx.ensure(size_t(N) * kCertVtx * sizeof(uint32_t));
+          ce.scale.ensure(size_t(N) * sizeof(float));
+          ce.psi_ref.ensure(size_t(N) * sizeof(double));
+          ce.dmax.ensure(sizeof(unsigned long long));
+          ce.margin = 0.05 * spacing * spacing;
+          ce.kappa = 0.05 * spacing;
+          cert_snapshot(ps, ce, st);
+          cur_cert = 1;
+        }
         ClipStats ct = pass(ctx->scp_trial, true, eps0, &ctx->sJ);
+        if (cur_cert == 1) ce.valid = !ct.doomed && ct.overflow == 0;
         si.cell_passes += 1;
         si.ls_trials += 1;
         if (ct.doomed) {
@@ -592,9 +624,10 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
         const double g2 =
             residual_stats(ctx->scp_trial.vol.as<double>(), m, ms, N, ctx->tmp, &e2, &v2, st);
         if (o.verbose >= 2)
-          fprintf(stderr, "[mak]   trial alpha=%g pass %.1f ms retried=%lld: err=%.3e |g| %.3e -> %.3e minV/m=%.3e\n",
+          fprintf(stderr,
+                  "[mak]   trial alpha=%g pass %.1f ms retried=%lld cert=%d: err=%.3e |g| %.3e -> %.3e minV/m=%.3e\n",
                   alpha, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count(),
-                  (long long)ct.retried, e2, gn, g2, v2 / m);
+                  (long long)ct.retried, cur_cert, e2, gn, g2, v2 / m);
         if (v2 >= eps0 && g2 <= (1.0 - 0.5 * alpha) * gn) {
           swap_buf(ctx->psi_s, ctx->psi_t);
           swap_pass(ctx->scp, ctx->scp_trial);

@@ -90,6 +90,16 @@ struct ClipArgs {
   unsigned int* doom;
   unsigned long long* doom_cell;  // a cell that raised *doom (sorted index)
   double doom_vol;
+  // Walk certificates (CertSet): 0 off, 1 record, 2 use.
+  int32_t cert_mode;
+  float cert_kappa;
+  double cert_margin;
+  uint32_t* cert_list;
+  int32_t* cert_n;
+  uint32_t* cert_vtx;
+  float* cert_scale;
+  const double* psi_ref;
+  const unsigned long long* cert_dmax;
 };
 
 // One launch carries the cell passes of up to kMaxJobs point sets (the
@@ -112,12 +122,15 @@ struct ClipBatch {
 // scanned, sites inside the ball bound, planes that removed vertices; box
 // tests and how many passed (ring-2 cells, blocks, cells of passing blocks);
 // the last block shell reached.  Slot 15 is left for the search flops the
-// host forms from these counts.
+// host forms from these counts.  Walk certificates: cells that recorded one,
+// the sites they list, cells whose list overflowed; cells that tried one
+// (weights within the margin) and cells whose walk it skipped.
 enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS,
        ST_TSEARCH, ST_TCLIP, ST_TINT, ST_TPRE, ST_TCUT, ST_SEARCH_FLOPS,
        ST_SCAN_W, ST_SCAN_N, ST_SCAN_R, ST_SCAN_B, ST_INBALL_W, ST_INBALL_N, ST_INBALL_R, ST_INBALL_B,
        ST_CUT_W, ST_CUT_N, ST_CUT_R, ST_CUT_B, ST_BOXT_R, ST_BOXP_R, ST_BOXT_BLK, ST_BOXP_BLK,
-       ST_BOXT_BC, ST_BOXP_BC, ST_SHELL, ST_N };
+       ST_BOXT_BC, ST_BOXP_BC, ST_SHELL, ST_CERT_REC, ST_CERT_LEN, ST_CERT_OVF, ST_CERT_TRY,
+       ST_CERT_OK, ST_N };
 
 // Final vertices in float64 (the float32 path recomputes them from their
 // three planes before integrating; the float64 path integrates its own).
@@ -148,6 +161,11 @@ struct ClipLDS {
       double4 cand[64];
       int32_t candj[64];
       int32_t cands[64];
+      // the certificate being recorded (sites, image shifts): alive during
+      // the search only, beside the batch (within the size of `fin` on the
+      // float32 path, so the LDS per wave does not grow)
+      uint32_t clist[kCertCap];
+      int32_t clsh[kCertCap];
     } batch;
   } u;
   uint32_t bits[PCAP * PCAP / 32];   // directed dual edges of removed vertices
@@ -157,6 +175,27 @@ struct ClipLDS {
   int32_t cpre[64];
   int32_t cshift[64];
 };
+static_assert(kCertCap <= 64, "a certificate is clipped as one list of 64 lanes");
+
+// Certificate entry: site j and the image shift (each axis in -1..1); 0xffffffff
+// when a shift lies outside that range (no certificate then).
+__device__ __forceinline__ uint32_t cert_entry(int32_t j, int32_t shv) {
+  const int sx = unpack_shift(shv, 0), sy = unpack_shift(shv, 1), sz = unpack_shift(shv, 2);
+  if (sx < -1 || sx > 1 || sy < -1 || sy > 1 || sz < -1 || sz > 1) return 0xffffffffu;
+  return (uint32_t(j) << 5) | uint32_t((sx + 1) * 9 + (sy + 1) * 3 + (sz + 1));
+}
+__device__ __forceinline__ int32_t cert_shift(uint32_t e) {
+  const int c = int(e & 31u);
+  return pack_shift(c / 9 - 1, (c / 3) % 3 - 1, c % 3 - 1);
+}
+// Order-preserving map of a double onto uint64 (for atomicMax).
+__device__ __forceinline__ unsigned long long ordered_key(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double ordered_value(unsigned long long k) {
+  return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+}
 
 __device__ __forceinline__ uint32_t tri_pack(int a, int b, int c) {
   return uint32_t(a) | (uint32_t(b) << 8) | (uint32_t(c) << 16);
@@ -287,7 +326,9 @@ __constant__ int kNearOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1, 7, 19, 25, 3, 5
 // dependent LDS / memory steps, so more waves per SIMD pay even with some
 // registers spilled: 4 waves per SIMD (128 VGPRs; 10 KB LDS per wave fits 16
 // per CU) for the main kernels, 2 for the large-capacity one.
-template <int TPL, typename R, bool STATS>
+// CERT: the variant that records or uses walk certificates (the extra live
+// state would spill registers in the passes that use neither).
+template <int TPL, typename R, bool STATS, bool CERT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4 : 2))) void k_clip(
     ClipBatch B) {
   constexpr bool kF64 = sizeof(R) == 8;
@@ -321,6 +362,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   const int cx = cell_coord(xi, h, Gn), cy = cell_coord(yi, h, Gn), cz = cell_coord(zi, h, Gn);
   const double gmax = *A.gmax;
   const double mtol = 1e-12 * L * L;
+
+  // Walk certificates (they need the warm start of an earlier pass).
+  const int cmode = CERT && A.warm_rp ? A.cert_mode : 0;
+  bool use_cert = false;
+  if (cmode == 2 && A.cert_n[p] >= 0)  // (the same on every lane: kept in scalar registers)
+    use_cert = uniform_i(ordered_value(*A.cert_dmax) - (wi - A.psi_ref[p]) <= A.cert_margin ? 1 : 0) != 0;
+  // recording: every pruning test allows the weight margin and bounds the
+  // polytope widened by kappa
+  const double wslack = cmode == 1 ? A.cert_margin : 0.0;
+  const float kap = cmode == 1 ? A.cert_kappa : 0.f;
+  int ccount = 0;  // recording: sites listed so far
 
   int32_t flags = 0;
   bool dead = false;
@@ -451,6 +503,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     bhx = uniform_f(wave_max_f(hx)) + slack;
     bhy = uniform_f(wave_max_f(hy)) + slack;
     bhz = uniform_f(wave_max_f(hz)) + slack;
+    if (kap > 0.f) {
+      // recording: the bounds cover the polytope widened by kappa
+      brho += kap;
+      rvert += kap;
+      blx -= kap;
+      bly -= kap;
+      blz -= kap;
+      bhx += kap;
+      bhy += kap;
+      bhz += kap;
+    }
   };
 
   // Drop the planes no vertex refers to any more (cut away by later planes)
@@ -757,7 +820,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     const double f = m >= r ? 0.5 * m * m - r * m : -0.5 * r * r;
     const double ex = double(bcx) + gx, ey = double(bcy) + gy, ez = double(bcz) + gz;
     const double cmax = fmax(ex * lx, ex * hx) + fmax(ey * ly, ey * hy) + fmax(ez * lz, ez * hz);
-    const double W = wmax - wi + mtol;
+    const double W = wmax - wi + mtol + wslack;
     if (!(f - cmax < W)) return false;
     // The same with the bounding box of the vertices: with h_P(d) <=
     // sum_a max(d_a hi_a, d_a lo_a) the left side is separable per axis, and
@@ -821,7 +884,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           // tolerances and the sort key
           dn = sqrt(d2);
           const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
-          may = cd + double(brho) * dn > bb - mtol && aabb_support(dx, dy, dz) > bb - mtol;
+          const double bt = bb - mtol - wslack;
+          may = cd + double(brho) * dn > bt && aabb_support(dx, dy, dz) > bt;
           if (may) key = (float_key(float((bb - cd) / dn)) & ~63u) | uint32_t(lane);
         }
       }
@@ -832,7 +896,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       // the plane in the working precision (seed-local, so float32 keeps the
       // relative precision of |d|)
       const R rx = R(dx), ry = R(dy), rz = R(dz), rbb = R(bb);
-      if (ns > 2) {
+      if (cmode == 1 && ph >= 1) {
+        // recording: the exact support of the current vertices (a superset of
+        // the final polytope) decides both the cut and the listing: listed is
+        // every site whose plane, its weight raised by the margin, reaches
+        // the polytope widened by kappa
+        const R eps = kF64 ? R(eps_scale * dn) : -tol_rel * (R(rvert) * R(dn) + fabs(rbb));
+        R mx = R(-FLT_MAX);
+#pragma unroll 1
+        for (int v = 0; v < nT; ++v) mx = fmax(mx, S.sx[v] * rx + S.sy[v] * ry + S.sz[v] * rz);
+        CNT(c_pre += uint32_t(nT));
+        const bool lst = may && mx + R(kap) * R(dn) > rbb - R(wslack) - fabs(eps);
+        const uint64_t lm = ballot(lst);
+        const int r = ccount + lanes_below(lm);
+        if (lst && r < kCertCap) {
+          S.u.batch.clist[r] = uint32_t(q);
+          S.u.batch.clsh[r] = shv;
+        }
+        ccount += __popcll(lm);
+        may = may && mx - rbb > eps;
+        if (!may) key = 0xffffffffu;
+        ns = __popcll(ballot(may));
+        if (ns == 0) continue;
+      } else if (ns > 2) {
         // Exact filter, one candidate per lane against every current vertex
         // (LDS broadcast reads).  A plane that removes no vertex now cannot
         // remove one from any later, smaller polytope.  (float32: planes with
@@ -907,7 +993,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     // for t >= 0 it is equivalent to t (t - 2R) >= 2 max(0, w - psi_i).
     auto out_of_reach = [&](double t, double w) {
       const double Rv = double(rvert);
-      return t * (t - 2.0 * Rv) >= 2.0 * fmax(0.0, w - wi);
+      return t * (t - 2.0 * Rv) >= 2.0 * fmax(0.0, w + wslack - wi);
     };
     const double* bsuf = A.block_suffix + block_key(bx0, by0, bz0, Gb) * (SHELL_MAX + 1);
     // sites in blocks farther than SHELL_MAX block shells (bounded by the
@@ -926,16 +1012,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       }
       return far_ok();
     };
-    if (A.warm_rp) {
-      // warm start: the earlier neighbours (nearest image), 64 per list
-      const int64_t wb = A.warm_rp[p], we = A.warm_rp[p + 1];
+    if (use_cert || A.warm_rp) {
+      // warm start: the sites of the certificate, or else the earlier
+      // neighbours (nearest image); 64 per list, one call site
+      const int64_t wb = use_cert ? 0 : A.warm_rp[p];
+      const int64_t we = use_cert ? int64_t(A.cert_n[p] & 255) : A.warm_rp[p + 1];
       for (int64_t k0 = wb; k0 < we && !dead; k0 += 64) {
         const int64_t k = k0 + lane;
-        int32_t j = -1;
-        if (k < we) j = A.warm_col[k];
+        int32_t j = -1, shw = 0;
+        if (k < we) {
+          if (use_cert) {
+            const uint32_t e = A.cert_list[int64_t(p) * kCertCap + k];
+            j = int32_t(e >> 5);
+            shw = cert_shift(e);
+          } else {
+            j = A.warm_col[k];
+          }
+        }
         const bool act = j >= 0 && j != p;
-        int32_t shw = 0;
-        if (act) {
+        if (act && !use_cert) {
           const double4 P = A.pts[j];
           shw = pack_shift(-int(rint((P.x - xi) / L)), -int(rint((P.y - yi) / L)),
                            -int(rint((P.z - zi) / L)));
@@ -943,12 +1038,49 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         process_list(act, act ? j : 0, 1, shw, 0);
       }
     }
+    bool skip_walk = false;
+    if (use_cert && uniform_i(dead ? 1 : 0) == 0) {
+      // is every vertex within kappa of a recorded vertex?  (Then the
+      // polytope lies inside the recorded one widened by kappa, which the
+      // recording walk covered.)  The recorded vertices go through LDS.
+      const int nv = (A.cert_n[p] >> 8) & 255;
+      const float sc = uniform_f(A.cert_scale[p]);
+      if (lane < nv) {
+        const uint32_t e = A.cert_vtx[int64_t(p) * kCertVtx + lane];
+        S.u.batch.cand[lane] = make_double4(double(float(int(e & 2047u) - 1024) * (sc / 1023.f)),
+                                            double(float(int((e >> 11) & 2047u) - 1024) * (sc / 1023.f)),
+                                            double(float(int(e >> 22) - 512) * (sc / 511.f)), 0.0);
+      }
+      __syncthreads();
+      // kappa less the rounding of the offsets (half a step per axis) and
+      // of the float arithmetic
+      const float kc = A.cert_kappa - sc * (1.25e-3f + 1e-5f) - 1e-6f * float(h);
+      bool outside = !(kc > 0.f);
+#pragma unroll
+      for (int k = 0; k < TPL; ++k) {
+        if (k * 64 + lane < nT) {
+          const float ux = float(vx[k]), uy = float(vy[k]), uz = float(vz[k]);
+          float dmin = FLT_MAX;
+#pragma unroll 1
+          for (int t = 0; t < nv; ++t) {
+            const double4 U = S.u.batch.cand[t];
+            const float ex = ux - float(U.x), ey = uy - float(U.y), ez = uz - float(U.z);
+            dmin = fminf(dmin, ex * ex + ey * ey + ez * ez);
+          }
+          outside = outside || !(dmin <= kc * kc);
+        }
+      }
+      skip_walk = !ballot(outside);
+      __syncthreads();
+      CPH(ST_CERT_TRY, 1);
+      CPH(ST_CERT_OK, skip_walk ? 1 : 0);
+    }
     int phase = 0;  // 0: 27 cells, 1 and 2: ring 2 of cells, 3: block shells
     int rb = 0, gbase = 0, gcount = 1;
     uint64_t bmask = 0;
     int ubx = 0, uby = 0, ubz = 0;
     int walk_iter = 0;
-    while (!dead) {
+    while (!dead && !skip_walk) {
       // a trial another cell has already rejected: stop the walk (the pass is
       // discarded); checked every 16 lists, a long walk of a far cell would
       // otherwise hold the launch open
@@ -1082,6 +1214,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     }
     CPH(ST_SHELL, rb);
   }
+  bool rec = false;
+  if (cmode == 1) {
+    // recording: the list now (its LDS is reused below), the vertices with
+    // the float64 ones; a cell that dies here is recorded by the stage that
+    // finishes it
+    uint32_t e = 0;
+    if (lane < ccount && lane < kCertCap) e = cert_entry(int32_t(S.u.batch.clist[lane]), S.u.batch.clsh[lane]);
+    rec = !dead && ccount <= kCertCap && nT <= kCertVtx && !ballot(e == 0xffffffffu);
+    if (lane == 0) A.cert_n[p] = rec ? (ccount | (nT << 8)) : -1;
+    if (rec && lane < ccount) A.cert_list[int64_t(p) * kCertCap + lane] = e;
+    CPH(ST_CERT_REC, rec ? 1 : 0);
+    CPH(ST_CERT_LEN, rec ? ccount : 0);
+    CPH(ST_CERT_OVF, (!dead && !rec) ? 1 : 0);
+  }
 
   if (STATS) t_search_end = clock_stamp();
   auto flush_stats = [&](int ntri, int nfaces) {
@@ -1172,6 +1318,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         FZ[slot] = fvz[k];
       }
     }
+  }
+  if (rec) {
+    // the certificate's vertices: 11/11/10-bit offsets from the site in
+    // units of rvert (which bounds every vertex distance)
+    const float sc = rvert;
+    if (lane < nT) {
+      const int qx = min(1023, max(-1023, int(rintf(float(fvx[0]) * (1023.f / sc)))));
+      const int qy = min(1023, max(-1023, int(rintf(float(fvy[0]) * (1023.f / sc)))));
+      const int qz = min(511, max(-511, int(rintf(float(fvz[0]) * (511.f / sc)))));
+      A.cert_vtx[int64_t(p) * kCertVtx + lane] =
+          uint32_t(qx + 1024) | (uint32_t(qy + 1024) << 11) | (uint32_t(qz + 512) << 22);
+    }
+    if (lane == 0) A.cert_scale[p] = sc;
   }
   // membership masks: bit t of mask f is set when triangle t contains plane f
 #pragma unroll
@@ -1362,10 +1521,16 @@ void launch_clip(ClipBatch& b, CellPass* const* outs, hipStream_t st) {
   const int64_t nblk = b.blk_start[b.njobs];
   const int64_t gx = nblk < (int64_t(1) << 16) ? nblk : (int64_t(1) << 16);
   const dim3 grid(unsigned(gx), unsigned(ceil_div(nblk, gx)));
-  if (counting)
-    hipLaunchKernelGGL((k_clip<TPL, R, true>), grid, dim3(64), 0, st, b);
+  bool cert = false;
+  for (int j = 0; j < b.njobs; ++j) cert = cert || b.job[j].cert_mode != 0;
+  if (counting && cert)
+    hipLaunchKernelGGL((k_clip<TPL, R, true, true>), grid, dim3(64), 0, st, b);
+  else if (counting)
+    hipLaunchKernelGGL((k_clip<TPL, R, true, false>), grid, dim3(64), 0, st, b);
+  else if (cert)
+    hipLaunchKernelGGL((k_clip<TPL, R, false, true>), grid, dim3(64), 0, st, b);
   else
-    hipLaunchKernelGGL((k_clip<TPL, R, false>), grid, dim3(64), 0, st, b);
+    hipLaunchKernelGGL((k_clip<TPL, R, false, false>), grid, dim3(64), 0, st, b);
   MAK_HIP(hipGetLastError());
   if (counting) {
     double flops = 0, bytes = 0;
@@ -1457,6 +1622,19 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   a.doom = jb.opt.doom_vol > 0 ? reinterpret_cast<unsigned int*>(ctr + 4) : nullptr;
   a.doom_cell = ctr + 5;
   a.doom_vol = jb.opt.doom_vol;
+  CertSet* ce = jb.opt.cert;
+  a.cert_mode = ce && a.warm_rp ? jb.opt.cert_mode : 0;
+  if (a.cert_mode == 1 && jb.opt.probe_n > 0) a.cert_mode = 0;  // a probe records nothing
+  if (a.cert_mode) {
+    a.cert_kappa = float(ce->kappa);
+    a.cert_margin = ce->margin;
+    a.cert_list = ce->list.as<uint32_t>();
+    a.cert_n = ce->n.as<int32_t>();
+    a.cert_vtx = ce->vtx.as<uint32_t>();
+    a.cert_scale = ce->scale.as<float>();
+    a.psi_ref = ce->psi_ref.as<double>();
+    a.cert_dmax = ce->dmax.as<unsigned long long>();
+  }
   return a;
 }
 
@@ -1484,6 +1662,45 @@ void launch_stage(PassJob* const* jobs, int n, int stage, int precision, hipStre
 }
 
 }  // namespace
+
+namespace {
+
+__global__ void k_cert_snapshot(const double4* __restrict__ pts, double* __restrict__ ref, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) ref[i] = pts[i].w;
+}
+
+__global__ void k_cert_dmax(const double4* __restrict__ pts, const double* __restrict__ ref,
+                            unsigned long long* out, int64_t n) {
+  double m = -DBL_MAX;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    m = fmax(m, pts[i].w - ref[i]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane_id() == 0) atomicMax(out, ordered_key(m));
+}
+
+}  // namespace
+
+void cert_snapshot(const PointSet& ps, CertSet& c, hipStream_t st) {
+  if (c.psi_ref.cap < size_t(ps.N) * sizeof(double)) MAK_FAIL(MAK_EHIP, "certificate weights not sized");
+  if (ps.N == 0) return;
+  hipLaunchKernelGGL(k_cert_snapshot, dim3(unsigned(ceil_div(ps.N, 256))), dim3(256), 0, st,
+                     ps.pts.as<double4>(), c.psi_ref.as<double>(), ps.N);
+  MAK_HIP(hipGetLastError());
+}
+
+void cert_dmax(const PointSet& ps, CertSet& c, hipStream_t st) {
+  if (c.psi_ref.cap < size_t(ps.N) * sizeof(double) || c.dmax.cap < 8)
+    MAK_FAIL(MAK_EHIP, "certificate buffers not sized");
+  fill_zero_i32(c.dmax.as<int32_t>(), 2, st);  // key 0 lies below every value
+  if (ps.N == 0) return;
+  const int64_t nb = std::min<int64_t>(2048, ceil_div(ps.N, 256));
+  hipLaunchKernelGGL(k_cert_dmax, dim3(unsigned(nb)), dim3(256), 0, st, ps.pts.as<double4>(),
+                     c.psi_ref.as<double>(), c.dmax.as<unsigned long long>(), ps.N);
+  MAK_HIP(hipGetLastError());
+}
 
 int32_t face_slots(int64_t N) { return N <= (int64_t(1) << 24) ? 32 : 20; }
 

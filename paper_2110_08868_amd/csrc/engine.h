@@ -219,6 +219,36 @@ struct ClipStats {
   bool doomed = false;  // a cell ended below doom_vol: the pass was abandoned
   int64_t doom_cell = -1;  // one such cell (sorted index)
 };
+// Walk certificates.  A recording pass lists, for each cell, every site whose
+// bisector, with that site's weight raised by `margin` relative to the
+// cell's, could still reach the final polytope P widened by kappa (P + a ball
+// of radius kappa); its walk runs with the search bounds widened the same
+// way, so every site it does not list can cut no polytope inside P + kappa
+// while the weights move by at most `margin`.  It also records P's
+// vertices.  A later pass over the same sites whose weights moved by less
+// (max_j (psi_j - psi_ref_j) - (psi_i - psi_ref_i) <= margin) clips the
+// listed sites only; when every vertex of the result lies within kappa of a
+// recorded vertex, the result lies inside P + kappa and the walk is skipped:
+// the polytope is the walk's.  Otherwise the cell walks.
+constexpr int kCertCap = 48;  // sites a certificate lists
+constexpr int kCertVtx = 48;  // vertices it records
+struct CertSet {
+  DevBuf list;     // uint32 [N][kCertCap]: site << 5 | image code (27 shifts in -1..1)
+  DevBuf n;        // int32 [N]: listed sites | vertices << 8, -1 no certificate
+  DevBuf vtx;      // uint32 [N][kCertVtx]: vertices, 11/11/10-bit offsets from the site
+  DevBuf scale;    // float [N]: scale of those offsets (a bound on the vertex distances)
+  DevBuf psi_ref;  // double [N]: the recording pass's weights (sorted order)
+  DevBuf dmax;     // uint64 [1]: max_j (psi_j - psi_ref_j) of the current weights (ordered key)
+  double margin = 0, kappa = 0;
+  bool valid = false;  // a complete recording pass stands behind the arrays
+};
+// Bytes per site of a CertSet.
+constexpr size_t kCertBytesPerSite = 4 * kCertCap + 4 + 4 * kCertVtx + 4 + 8;
+// psi_ref <- the weights in ps.pts[].w (at a recording pass).
+void cert_snapshot(const PointSet& ps, CertSet& c, hipStream_t st);
+// dmax <- max_j (pts[j].w - psi_ref[j]) (before a pass that uses the set).
+void cert_dmax(const PointSet& ps, CertSet& c, hipStream_t st);
+
 // How one cell pass runs.
 struct PassOpts {
   int precision = MAK_FP64;  // MAK_FP64 or MAK_MIXED
@@ -245,6 +275,11 @@ struct PassOpts {
   // full pass would give it, so a doomed probe means a doomed pass.
   const int32_t* probe_list = nullptr;
   int64_t probe_n = 0;
+  // Walk certificates (with a warm start only): 1 records them (full passes
+  // only; `cert` sized for N sites, psi_ref snapshotted), 2 uses them (dmax
+  // computed for the current weights).
+  int cert_mode = 0;
+  CertSet* cert = nullptr;
 };
 
 // Full cell pass at the psi stored in ps.pts[].w.  Throws on failure.

@@ -402,3 +402,44 @@ def test_preconditioners_reach_the_same_solution():
     D2 = (1.0 / 24) ** 2
     assert np.sqrt(np.mean(d ** 2)) <= 1e-6 * D2
     assert out[0][1]["cg_iters_total"] < out[1][1]["cg_iters_total"]
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_walk_certificates_change_the_search_not_the_cells(precision):
+    """Walk certificates (on by default) shorten the search of the passes
+    after the recording one without changing any cell: a clustered 32^3
+    solve with and without them takes the same Newton steps and cell passes
+    and returns the same weights and centroids to rounding; the work
+    counters show the recording pass and the skipped walks; the result is
+    certified by the oracle's own cells."""
+    import torch
+    import paper_2110_08868_amd as mak
+    n = 32
+    x = workloads.clustered(n, rms=3.0, smooth=1.0, frac=0.2, n_clumps=31, a=0.5, seed=3)
+    N = x.shape[0]
+    out = {}
+    for wc in (0, 1):
+        c = mak.Context(0, precision, cg_rtol=1e-3, walk_cert=wc)
+        try:
+            c.profile_enable(timing=False, counting=True)
+            psi, C, D, info = c.solve(torch.from_numpy(x), 1.0, 1e-6)
+            cnt = c.profile_read()["_counters"]
+        finally:
+            c.close()
+        print(f"  walk_cert {wc}: {info}", flush=True)
+        print("   ", {k: v for k, v in cnt.items() if k.startswith("cert")}, flush=True)
+        out[wc] = (psi.cpu().numpy(), C.cpu().numpy(), info, cnt)
+    (p0, c0, i0, n0), (p1, c1, i1, n1) = out[0], out[1]
+    for k in ("newton_iters", "cell_passes", "abandoned_trials"):
+        assert i0[k] == i1[k], k
+    s = 1.0 / n
+    d = p1 - p0
+    d -= d.mean()
+    assert np.abs(d).max() <= 1e-10 * s * s
+    dc = c1 - c0
+    dc -= np.round(dc)
+    assert np.abs(dc).max() <= 1e-9 * s
+    assert all(v == 0 for k, v in n0.items() if k.startswith("cert"))
+    assert n1["cert_recorded"] >= 0.99 * N
+    assert n1["cert_tried"] > 0 and n1["cert_walk_skipped"] >= 0.9 * n1["cert_tried"]
+    certificate(x, p1, 1.0, 1e-6)
