@@ -86,7 +86,18 @@ typedef struct {
                               clip those sites only (same cells, shorter
                               search); 0: every pass searches in full.  Holds
                               about 250 more bytes per site. */
-  int32_t reserved[3];
+  int32_t topo_reuse;      /* 1 (default): every full cell pass of a solve
+                              records each cell's combinatorics (its vertices
+                              as triples of faces), and the next pass first
+                              rebuilds that polytope from the planes of the
+                              cell's J row at the new weights, keeping it when
+                              every vertex lies strictly inside every other
+                              plane (it is then exactly their intersection)
+                              instead of clipping the row plane by plane; the
+                              search that follows is unchanged, so the cells
+                              are the same to rounding.  0: off.  Holds about
+                              400 more bytes per site. */
+  int32_t reserved[2];
 } mak_options;
 
 /* Fill `opt` with the defaults listed above. */
@@ -329,9 +340,10 @@ mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double
  *   k_mean, power  DEVICE (nbins,) float64 out: mean |k| and mean P per shell
  *                  (NaN for a shell without modes)
  *   modes          DEVICE (nbins,) int64 out: modes per shell (each n and -n counted)
- * The FFT is hipFFT's real-to-complex transform; its plan (for the last ng)
- * and buffers (ng^3 (8 + 8) bytes) stay in the context.  Deterministic:
- * the same bits on every run. */
+ * The transform is the library's own real-to-complex FFT (mixed radix, any
+ * ng: three passes of one-dimensional transforms in LDS); its twiddle table
+ * (for the last ng) and the half spectrum (ng^2 (ng/2 + 1) x 16 bytes) stay
+ * in the context.  Deterministic: the same bits on every run. */
 mak_status mak_power_spectrum(mak_ctx* ctx, const double* field, int64_t ng, double L, int32_t nbins,
                               int32_t window, int32_t contrast, double* k_mean, double* power,
                               int64_t* modes, void* stream);

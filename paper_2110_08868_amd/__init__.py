@@ -56,7 +56,8 @@ class _Options(ctypes.Structure):
         ("cg_rtol", ctypes.c_double), ("grid_occupancy", ctypes.c_double),
         ("mem_budget_bytes", ctypes.c_size_t), ("verbose", ctypes.c_int32),
         ("first_stage", ctypes.c_int32), ("batch_window_us", ctypes.c_int32),
-        ("cg_precond", ctypes.c_int32), ("walk_cert", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+        ("cg_precond", ctypes.c_int32), ("walk_cert", ctypes.c_int32), ("topo_reuse", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -95,7 +96,8 @@ COUNTER_NAMES = ["sites_scanned", "planes_tested", "vertex_tests", "cuts", "new_
                  "cut_warm", "cut_near", "cut_ring2", "cut_blocks",
                  "boxtest_ring2", "boxpass_ring2", "boxtest_blocks", "boxpass_blocks",
                  "boxtest_blockcells", "boxpass_blockcells", "shell_sum",
-                 "cert_recorded", "cert_sites", "cert_overflow", "cert_tried", "cert_walk_skipped"]
+                 "cert_recorded", "cert_sites", "cert_overflow", "cert_tried", "cert_walk_skipped",
+                 "topo_tried", "topo_reused"]
 
 
 class _ServerStats(ctypes.Structure):

@@ -18,8 +18,6 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-fast-math", "-ffp-contract=off",
     "-Wall", "-Wno-unused-function",
-    # plain FFTs of the power spectrum estimator
-    "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

@@ -35,6 +35,8 @@ void swap_pass(CellPass& a, CellPass& b) {
   swap_buf(a.mom, b.mom);
   swap_buf(a.cflags, b.cflags);
   swap_buf(a.nface, b.nface);
+  swap_buf(a.topo_tri, b.topo_tri);
+  swap_buf(a.topo_n, b.topo_n);
 }
 
 size_t solve_bytes_per_site(int64_t N) {
@@ -55,7 +57,9 @@ size_t solve_bytes_per_site(int64_t N) {
   const size_t fslot = size_t(face_slots(N));
   const size_t faces = fslot * sizeof(FaceRec) + 8 + 2 * sizeof(FaceRec);
   //   walk certificates (kCertBytesPerSite, with walk_cert on)
-  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 24 * 8 + 1 + 48 + 40 + kCertBytesPerSite;
+  //   combinatorics of the two passes (2 x kTopoBytesPerSite, with topo_reuse on)
+  return 42 + 2 * 52 + faces + 24 + 16 * 12 + 24 * 8 + 1 + 48 + 40 + kCertBytesPerSite +
+         2 * kTopoBytesPerSite;
 }
 
 namespace {
@@ -193,6 +197,7 @@ void mak_default_options(mak_options* opt) {
   opt->mem_budget_bytes = 0;
   opt->verbose = 0;
   opt->walk_cert = 1;
+  opt->topo_reuse = 1;
 }
 
 mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
@@ -222,7 +227,8 @@ mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
   const int nstage = c->opt.precision == MAK_MIXED ? 3 : 2;
   if (!(c->opt.cg_rtol > 0) || c->opt.max_newton < 0 || c->opt.max_cg < 1 || c->opt.max_halvings < 0 ||
       c->opt.first_stage < 0 || c->opt.first_stage >= nstage || c->opt.cg_precond < 0 ||
-      c->opt.cg_precond > 1 || c->opt.walk_cert < 0 || c->opt.walk_cert > 1) {
+      c->opt.cg_precond > 1 || c->opt.walk_cert < 0 || c->opt.walk_cert > 1 || c->opt.topo_reuse < 0 ||
+      c->opt.topo_reuse > 1) {
     delete c;
     g_create_error = "invalid options";
     return MAK_EINVAL;
@@ -479,6 +485,15 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
     CertSet& ce = ctx->scert;
     ce.valid = false;
     const bool certs = o.walk_cert != 0 && N >= 2 && N <= (int64_t(1) << 27);
+    // Combinatorics records of the accepted pass and of the trial (swapped
+    // with them on acceptance).
+    const bool topo = o.topo_reuse != 0 && N >= 2;
+    if (topo) {
+      for (CellPass* c : {&ctx->scp, &ctx->scp_trial}) {
+        c->topo_tri.ensure(size_t(N) * kTopoTri * sizeof(uint32_t));
+        c->topo_n.ensure(size_t(N) * sizeof(int32_t));
+      }
+    }
     const double spacing = L / std::cbrt(double(N));
     int cur_cert = 0;
     auto pass = [&](CellPass& cp, bool tolerate, double doom_vol, const Lap* warm, int64_t probe_n = 0,
@@ -492,7 +507,11 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
       if (warm && warm->n == N) {
         po.warm_rp = warm->row_ptr.as<int64_t>();
         po.warm_col = warm->col.as<int32_t>();
+        // J (the warm start) was built from the accepted pass's faces, whose
+        // records index its rows
+        if (topo) po.topo_in = &ctx->scp;
       }
+      if (topo && probe_n <= 0) po.topo_out = &cp;
       po.first_stage = o.first_stage;
       if (probe_n > 0) {
         po.faces = false;

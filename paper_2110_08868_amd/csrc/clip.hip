@@ -100,6 +100,12 @@ struct ClipArgs {
   float* cert_scale;
   const double* psi_ref;
   const unsigned long long* cert_dmax;
+  // Combinatorics reuse: the records of the warm start's pass (read) and of
+  // this pass (written); NULL: off.
+  const uint32_t* topo_tri_in;
+  const int32_t* topo_n_in;
+  uint32_t* topo_tri_out;
+  int32_t* topo_n_out;
 };
 
 // One launch carries the cell passes of up to kMaxJobs point sets (the
@@ -124,13 +130,15 @@ struct ClipBatch {
 // the last block shell reached.  Slot 15 is left for the search flops the
 // host forms from these counts.  Walk certificates: cells that recorded one,
 // the sites they list, cells whose list overflowed; cells that tried one
-// (weights within the margin) and cells whose walk it skipped.
+// (weights within the margin) and cells whose walk it skipped.  Reused
+// combinatorics: cells with a record of the warm start's pass, and cells
+// that kept the polytope rebuilt from it.
 enum { ST_CAND, ST_TEST, ST_VTEST, ST_CUT, ST_NEWV, ST_BALL, ST_BOX, ST_TRI, ST_FACES, ST_CELLS,
        ST_TSEARCH, ST_TCLIP, ST_TINT, ST_TPRE, ST_TCUT, ST_SEARCH_FLOPS,
        ST_SCAN_W, ST_SCAN_N, ST_SCAN_R, ST_SCAN_B, ST_INBALL_W, ST_INBALL_N, ST_INBALL_R, ST_INBALL_B,
        ST_CUT_W, ST_CUT_N, ST_CUT_R, ST_CUT_B, ST_BOXT_R, ST_BOXP_R, ST_BOXT_BLK, ST_BOXP_BLK,
        ST_BOXT_BC, ST_BOXP_BC, ST_SHELL, ST_CERT_REC, ST_CERT_LEN, ST_CERT_OVF, ST_CERT_TRY,
-       ST_CERT_OK, ST_N };
+       ST_CERT_OK, ST_TOPO_TRY, ST_TOPO_OK, ST_N };
 
 // Final vertices in float64 (the float32 path recomputes them from their
 // three planes before integrating; the float64 path integrates its own).
@@ -815,7 +823,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     // a lower bound of the distance m to the box (a float root, shrunk by
     // far more than its error): f(m) = m^2/2 - r m is increasing for m >= r,
     // so the bound keeps the test conservative
-    const double m = sqrt(mx * mx + my * my + mz * mz);
+    const double m = double(__builtin_amdgcn_sqrtf(float(mx * mx + my * my + mz * mz))) * (1.0 - 1e-6);
     const double r = double(brho);
     const double f = m >= r ? 0.5 * m * m - r * m : -0.5 * r * r;
     const double ex = double(bcx) + gx, ey = double(bcy) + gy, ez = double(bcz) + gz;
@@ -882,11 +890,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           // |d| from a float root, enlarged by far more than its error: it
           // only scales the ball test (larger = more conservative), the tie
           // tolerances and the sort key
-          dn = sqrt(d2);
+          dn = double(__builtin_amdgcn_sqrtf(float(d2))) * (1.0 + 1e-6);
           const double cd = double(bcx) * dx + double(bcy) * dy + double(bcz) * dz;
           const double bt = bb - mtol - wslack;
           may = cd + double(brho) * dn > bt && aabb_support(dx, dy, dz) > bt;
-          if (may) key = (float_key(float((bb - cd) / dn)) & ~63u) | uint32_t(lane);
+          if (may) key = (float_key(float(bb - cd) * __builtin_amdgcn_rcpf(float(dn))) & ~63u) | uint32_t(lane);
         }
       }
       if (ballot(coinc)) flags |= CF_COINCIDENT;
@@ -1012,7 +1020,111 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       }
       return far_ok();
     };
-    if (use_cert || A.warm_rp) {
+    // Combinatorics of the warm start's pass: the polytope it recorded is
+    // rebuilt from the planes of the cell's J row at the current weights
+    // (one triangle per lane) and kept when every vertex lies strictly
+    // inside every other plane of the row and the box.  A closed set of
+    // simple vertices each inside every half-space is the vertex set of their
+    // intersection (from each vertex, every edge runs to another vertex of the
+    // set and no plane crosses it in between), so the polytope is the one
+    // that clipping the row's planes gives; otherwise the row is clipped.
+    bool reused = false;
+    if (A.topo_n_in && A.warm_rp) {
+      const int ntr = A.topo_n_in[p];
+      const int64_t wb = A.warm_rp[p];
+      const int nw = int(A.warm_rp[p + 1] - wb);
+      CPH(ST_TOPO_TRY, ntr > 0 ? 1 : 0);
+      if (ntr >= 4 && ntr <= kTopoTri && nw <= 57 && 6 + nw <= PCAP) {
+        const int np = 6 + nw;
+        if (lane < nw) {
+          // the planes exactly as the warm list forms them (nearest image)
+          const int32_t j = A.warm_col[wb + lane];
+          const double4 P = A.pts[j];
+          const int32_t shw = pack_shift(-int(rint((P.x - xi) / L)), -int(rint((P.y - yi) / L)),
+                                         -int(rint((P.z - zi) / L)));
+          const double dx = P.x + unpack_shift(shw, 0) * L - xi;
+          const double dy = P.y + unpack_shift(shw, 1) * L - yi;
+          const double dz = P.z + unpack_shift(shw, 2) * L - zi;
+          const double d2 = dx * dx + dy * dy + dz * dz;
+          S.pl[6 + lane] = make_double4(dx, dy, dz, 0.5 * d2 + wi - P.w);
+          S.pj[6 + lane] = j;
+          S.ps[6 + lane] = shw;
+        }
+        __syncthreads();
+        bool bad = false;
+        int ta = 0, tb = 0, tc = 0;
+        double X = 0.0, Y = 0.0, Z = 0.0;
+        if (lane < ntr) {
+          const uint32_t code = A.topo_tri_in[int64_t(p) * kTopoTri + lane];
+          ta = int(code & 63u);
+          tb = int((code >> 6) & 63u);
+          tc = int((code >> 12) & 63u);
+          bad = ta >= np || tb >= np || tc >= np;
+          if (!bad) {
+            const double4 P1 = S.pl[ta], P2 = S.pl[tb], P3 = S.pl[tc];
+            const double c23x = P2.y * P3.z - P2.z * P3.y, c23y = P2.z * P3.x - P2.x * P3.z,
+                         c23z = P2.x * P3.y - P2.y * P3.x;
+            const double c31x = P3.y * P1.z - P3.z * P1.y, c31y = P3.z * P1.x - P3.x * P1.z,
+                         c31z = P3.x * P1.y - P3.y * P1.x;
+            const double c12x = P1.y * P2.z - P1.z * P2.y, c12y = P1.z * P2.x - P1.x * P2.z,
+                         c12z = P1.x * P2.y - P1.y * P2.x;
+            const double inv = recip_d(P1.x * c23x + P1.y * c23y + P1.z * c23z);
+            X = (P1.w * c23x + P2.w * c31x + P3.w * c12x) * inv;
+            Y = (P1.w * c23y + P2.w * c31y + P3.w * c12y) * inv;
+            Z = (P1.w * c23z + P2.w * c31z + P3.w * c12z) * inv;
+            bad = !(isfinite(X) && isfinite(Y) && isfinite(Z));
+          }
+        }
+        // the tie tolerance of each plane (float64: eps = eps_scale |d|;
+        // float32: the ambiguity band tol_rel (rvert |d| + |b|) with rvert
+        // from these vertices), staged in the idle batch slots
+        const double rv = sqrt(wave_max_d(lane < ntr && !bad ? X * X + Y * Y + Z * Z : 0.0)) * 1.0001 + 1e-6 * h;
+        if (lane < np) {
+          const double4 Q = S.pl[lane];
+          const double qn = sqrt(Q.x * Q.x + Q.y * Q.y + Q.z * Q.z);
+          S.u.batch.cand[lane].x = kF64 ? eps_scale * qn : double(tol_rel) * (rv * qn + fabs(Q.w));
+        }
+        __syncthreads();
+        int nvt = 0;  // vertex-side tests made (work counters)
+        if (lane < ntr && !bad) {
+#pragma unroll 1
+          for (int f = 0; f < np; ++f) {
+            if (f == ta || f == tb || f == tc) continue;
+            const double4 Q = S.pl[f];
+            CNT(++nvt);
+            if (!(X * Q.x + Y * Q.y + Z * Q.z - Q.w < -S.u.batch.cand[f].x)) {
+              bad = true;
+              break;
+            }
+          }
+        }
+        // the rebuilt vertices and their tests are the clipping's arithmetic
+        CNT(c_newv += uint32_t(ntr));
+        CNT(c_vt += uint32_t(wave_sum_i(nvt)));
+        CNT(c_test += uint32_t(nw));
+        reused = !ballot(bad);
+        if (reused) {
+          nT = ntr;
+          nP = np;
+          tri[0] = lane < ntr ? tri_pack(ta, tb, tc) : 0u;
+          vx[0] = R(X);
+          vy[0] = R(Y);
+          vz[0] = R(Z);
+#pragma unroll
+          for (int k = 1; k < TPL; ++k) tri[k] = 0;
+          if (lane < ntr) {
+            S.stri[lane] = tri[0];
+            S.sx[lane] = vx[0];
+            S.sy[lane] = vy[0];
+            S.sz[lane] = vz[0];
+          }
+          ball_dirty = true;
+        }
+        CPH(ST_TOPO_OK, reused ? 1 : 0);
+        __syncthreads();
+      }
+    }
+    if (use_cert || (A.warm_rp && !reused)) {
       // warm start: the sites of the certificate, or else the earlier
       // neighbours (nearest image); 64 per list, one call site
       const int64_t wb = use_cert ? 0 : A.warm_rp[p];
@@ -1271,6 +1383,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       A.mom[3 * p] = A.mom[3 * p + 1] = A.mom[3 * p + 2] = 0.0;
       A.nface[p] = 0;
       A.cflags[p] = flags;
+      if (A.topo_n_out) A.topo_n_out[p] = -1;
     }
     return;
   }
@@ -1431,6 +1544,59 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     }
     Af[c] = (real && a > A.area_min) ? a : 0.0;
     nf += __popcll(ballot(Af[c] > 0.0));
+  }
+  if (A.topo_n_out) {
+    // This pass's combinatorics for the next one.  Plane codes: a box plane
+    // 2 axis + (side < 0); a written face 6 + the rank of its site among the
+    // written faces' sites (its position in the cell's row of J); 63 none.
+    // (The cut bitmap is idle now: sites of the written faces, then codes.)
+    uint32_t* wj = S.bits;
+    uint32_t* pcode = S.bits + PCAP;
+#pragma unroll
+    for (int c = 0; c < NPC; ++c) {
+      const int f = c * 64 + lane;
+      if (f < PCAP) wj[f] = (f < nP && Af[c] > 0.0) ? uint32_t(S.pj[f]) : 0xffffffffu;
+    }
+    __syncthreads();
+    bool dup = false;
+#pragma unroll
+    for (int c = 0; c < NPC; ++c) {
+      const int f = c * 64 + lane;
+      uint32_t code = 63u;
+      if (f < nP && S.pj[f] < 0) {
+        const int32_t sh = S.ps[f];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+          if (unpack_shift(sh, ax) != 0) code = uint32_t(2 * ax + (unpack_shift(sh, ax) < 0 ? 1 : 0));
+      } else if (f < nP && wj[f] != 0xffffffffu) {
+        const uint32_t me = wj[f];
+        int rank = 0;
+#pragma unroll 1
+        for (int g = 0; g < nP; ++g) {
+          const uint32_t o = wj[g];
+          if (o == 0xffffffffu) continue;
+          rank += (o < me) ? 1 : 0;
+          dup = dup || (o == me && g != f);
+        }
+        code = rank <= 56 ? uint32_t(6 + rank) : 63u;
+      }
+      if (f < PCAP) pcode[f] = code;
+    }
+    __syncthreads();
+    bool miss = false;
+    uint32_t rec[TPL];
+#pragma unroll
+    for (int k = 0; k < TPL; ++k) {
+      rec[k] = 0;
+      if (k * 64 + lane < nT) {
+        const uint32_t ca = pcode[tri_a(tri[k])], cb = pcode[tri_b(tri[k])], cc = pcode[tri_c(tri[k])];
+        miss = miss || ca == 63u || cb == 63u || cc == 63u;
+        rec[k] = ca | (cb << 6) | (cc << 12);
+      }
+    }
+    const bool ok = nT <= kTopoTri && !ballot(miss || dup);
+    if (ok && lane < nT) A.topo_tri_out[int64_t(p) * kTopoTri + lane] = rec[0];
+    if (lane == 0) A.topo_n_out[p] = ok ? nT : -1;
   }
   if (A.write_faces) {
     FaceRec* dst = A.faces + int64_t(p) * A.fslot;
@@ -1634,6 +1800,19 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
     a.cert_scale = ce->scale.as<float>();
     a.psi_ref = ce->psi_ref.as<double>();
     a.cert_dmax = ce->dmax.as<unsigned long long>();
+  }
+  const CellPass* ti = jb.opt.topo_in;
+  if (ti && a.warm_rp && ti->topo_n.cap >= size_t(N) * sizeof(int32_t) &&
+      ti->topo_tri.cap >= size_t(N) * kTopoTri * sizeof(uint32_t)) {
+    a.topo_tri_in = ti->topo_tri.as<uint32_t>();
+    a.topo_n_in = ti->topo_n.as<int32_t>();
+  }
+  CellPass* to = jb.opt.topo_out;
+  if (to && jb.opt.probe_n <= 0) {  // a probe records nothing
+    if (to->topo_n.cap < size_t(N) * sizeof(int32_t) || to->topo_tri.cap < size_t(N) * kTopoTri * sizeof(uint32_t))
+      MAK_FAIL(MAK_EHIP, "combinatorics records not sized");
+    a.topo_tri_out = to->topo_tri.as<uint32_t>();
+    a.topo_n_out = to->topo_n.as<int32_t>();
   }
   return a;
 }

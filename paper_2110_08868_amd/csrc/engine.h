@@ -157,7 +157,20 @@ struct CellPass {
   FaceStore* shared = nullptr;  // face storage in use (`own` when NULL)
   FaceStore& fs() { return shared ? *shared : own; }
   const FaceStore& fs() const { return shared ? *shared : own; }
+  // Combinatorics of each cell (when the solver asks for them; see PassOpts).
+  DevBuf topo_tri;   // uint32 [N][kTopoTri]
+  DevBuf topo_n;     // int32 [N]: triangles recorded, or -1
 };
+
+// Combinatorics of a cell as a later pass can reuse them: its triangles (the
+// dual of its vertices) with each plane coded in 6 bits as 0..5 (the box of
+// the site's own images) or 6 + r, r the rank of the face's site among the
+// cell's face sites in increasing order, which is its position in the cell's
+// row of J.  A cell with more than kTopoTri triangles, more than 57 faces,
+// two faces with the same site, or a triangle on a plane that wrote no face
+// (area below the pass's threshold) records none.
+constexpr int kTopoTri = 48;
+constexpr size_t kTopoBytesPerSite = 4 * kTopoTri + 4;
 
 // Bytes of device memory per site (and fixed) that one solve holds.
 size_t solve_bytes_per_site(int64_t N);
@@ -280,6 +293,16 @@ struct PassOpts {
   // computed for the current weights).
   int cert_mode = 0;
   CertSet* cert = nullptr;
+  // Combinatorics reuse (with a warm start only).  topo_in: the records of
+  // the pass whose J rows are warm_rp / warm_col; a cell with a record first
+  // rebuilds that polytope from its J row's planes at the current weights
+  // and keeps it when every vertex lies strictly inside every other plane of
+  // the row and the box (then it is exactly the intersection of those
+  // half-spaces), instead of clipping the row's planes one by one; the walk
+  // follows as usual.  topo_out: where this pass records its cells (full
+  // passes only; sized for N sites).
+  const CellPass* topo_in = nullptr;
+  CellPass* topo_out = nullptr;
 };
 
 // Full cell pass at the psi stored in ps.pts[].w.  Throws on failure.
@@ -367,14 +390,8 @@ void za_deposit_cells(const PointSet& ps, const CellPass& cp, double tau, int64_
 // Shell-averaged power spectrum of a field on the periodic ng^3 mesh; the
 // FFT plan (for the last ng) and the buffers are kept between calls.
 struct PowerWork {
-  int64_t ng = 0;
-  uintptr_t plan = 0;  // hipfftHandle
-  DevBuf real, spec, part, sums, tmp;
-  PowerWork() = default;
-  PowerWork(const PowerWork&) = delete;
-  PowerWork& operator=(const PowerWork&) = delete;
-  ~PowerWork() { release_plan(); }
-  void release_plan();
+  int64_t ng = 0;  // length of the twiddle table in `tw`
+  DevBuf tw, spec, part, sums, tmp;
 };
 void power_spectrum(PowerWork& w, const double* field, int64_t ng, double L, int nbins, int window,
                     bool contrast, double* k_mean, double* power, int64_t* modes, hipStream_t st);

@@ -9,8 +9,25 @@
 // contrast f / mean(f) - 1 and divided by the squared Fourier window
 // prod_a sinc(pi n_a / ng)^(2p) of a mass assignment of order p.
 //
-// The transform is a plain real-to-complex FFT (hipFFT); the binning is
-// ours.  The half spectrum (ng x ng x (ng/2 + 1), last index fastest) holds
+// Transform: the unnormalised forward real-to-complex DFT, separable over
+// the three axes, each a batch of one-dimensional transforms of length ng
+// done in LDS by one workgroup per tile of lines.  Pass 1 transforms the
+// rows of the real field (the last axis) and keeps frequencies
+// 0..ng/2 (the rest are their conjugates); passes 2 and 3 transform the
+// half spectrum in place along the middle and the first axis, a tile being
+// a run of consecutive last-axis indices (coalesced rows).  A
+// one-dimensional transform is a self-sorting (Stockham) mixed-radix FFT:
+// with ng = R_1 R_2 ... R_s (radix 4 first, then 2, 3, 5, 7 and any other
+// prime), stage t reads x[j + r ng / R] (r < R = R_t) for j < ng / R,
+// multiplies term r by w^(r k ng / (N_t R)) (k = j mod N_t, N_t = R_1 ...
+// R_(t-1), w = exp(-2 pi i / ng)), takes the length-R DFT and writes
+// output q to y[(j div N_t) N_t R + k + q N_t]: after the last stage the
+// transform sits in natural order.  Twiddles come from a table of w^t,
+// t < ng, made once per ng with sincospi (a root of unity to within an ulp
+// or two).  Radix 4 and 2 have their own butterflies; another radix forms
+// each output as a sum over its R terms with one table twiddle per term.
+//
+// The half spectrum (ng x ng x (ng/2 + 1), last index fastest) holds
 // every mode once or, for 0 < n_c < ng/2, together with its conjugate
 // partner -n, so those elements count twice.  Binning: one wavefront per
 // workgroup takes a contiguous range of rows (a, b) and walks each row in
@@ -20,8 +37,6 @@
 // per shell per step, in program order).  The histograms of the workgroups
 // are then summed per shell in a fixed order, so the result is the same bits
 // on every run.
-#include <hipfft/hipfft.h>
-
 #include <climits>
 #include <cmath>
 
@@ -42,6 +57,207 @@ __device__ __forceinline__ double window_factor(int64_t n, int64_t ng, int p) {
   double w = s;
   for (int k = 1; k < p; ++k) w *= s;
   return w;
+}
+
+// ------------------------------------------------------------------ FFT
+constexpr int kFftThreads = 256;
+constexpr int kFftMaxStages = 24;
+
+struct FftPlan {
+  int n;                       // transform length
+  int nst;                     // stages
+  int radix[kFftMaxStages];    // radix of each stage (product n)
+};
+
+__global__ void k_fft_twiddles(double2* __restrict__ w, int64_t n) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double s, c;
+  sincospi(2.0 * double(t) / double(n), &s, &c);
+  w[t] = make_double2(c, -s);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// One-dimensional transforms of nl lines held in LDS (line t at x + t * ls),
+// in place as far as the caller sees: returns the buffer holding the result.
+__device__ double2* fft_lines_lds(double2* x, double2* y, const double2* __restrict__ W, const FftPlan& P,
+                                  int nl, int ls) {
+  const int n = P.n;
+  int Ns = 1;
+  for (int s = 0; s < P.nst; ++s) {
+    const int R = P.radix[s];
+    const int m = n / R;
+    const int tw = n / (Ns * R);  // twiddle stride
+    for (int idx = threadIdx.x; idx < nl * m; idx += kFftThreads) {
+      const int t = idx / m, j = idx - t * m;
+      const double2* xl = x + t * ls;
+      double2* yl = y + t * ls;
+      const int k = j % Ns;
+      const int o = (j / Ns) * Ns * R + k;
+      const int ts = k * tw;
+      if (R == 4) {
+        const double2 v0 = xl[j];
+        const double2 v1 = cmul(xl[j + m], W[ts]);
+        const double2 v2 = cmul(xl[j + 2 * m], W[2 * ts]);
+        const double2 v3 = cmul(xl[j + 3 * m], W[3 * ts]);
+        const double2 a0 = cadd(v0, v2), a1 = csub(v0, v2), a2 = cadd(v1, v3);
+        const double2 d = csub(v1, v3);
+        const double2 a3 = make_double2(d.y, -d.x);  // -i (v1 - v3)
+        yl[o] = cadd(a0, a2);
+        yl[o + Ns] = cadd(a1, a3);
+        yl[o + 2 * Ns] = csub(a0, a2);
+        yl[o + 3 * Ns] = csub(a1, a3);
+      } else if (R == 2) {
+        const double2 a = xl[j];
+        const double2 b = cmul(xl[j + m], W[ts]);
+        yl[o] = cadd(a, b);
+        yl[o + Ns] = csub(a, b);
+      } else {
+        // output q: sum_r x[j + r m] w^(r (k tw + q m)), exponents mod n
+        for (int q = 0; q < R; ++q) {
+          const int64_t e = int64_t(ts) + int64_t(q) * m;
+          double2 acc = xl[j];
+          for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(xl[j + r * m], W[(int64_t(r) * e) % n]));
+          yl[o + q * Ns] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    double2* t = x;
+    x = y;
+    y = t;
+    Ns *= R;
+  }
+  return x;
+}
+
+// LDS of the line kernels (at most 64 KB): two buffers of nl lines of ls
+// elements (n + 1 when nl > 1: the padding spreads the lines over the
+// banks) and, for n <= 1024, the twiddle table (longer transforms read it
+// from global memory).
+struct FftShape {
+  int nl = 1, ls = 1;
+  bool twl = true;
+  size_t lds = 0;
+};
+FftShape fft_shape(int n) {
+  FftShape f;
+  f.twl = n <= 1024;
+  const int budget = 4096 - (f.twl ? n : 0);  // complex doubles in 64 KB
+  f.nl = budget / (2 * (n + 1));
+  if (f.nl > 16) f.nl = 16;
+  if (f.nl >= 2) {
+    f.ls = n + 1;
+  } else {
+    f.nl = 1;
+    f.ls = n;
+  }
+  f.lds = (size_t(2) * f.nl * f.ls + (f.twl ? n : 0)) * sizeof(double2);
+  return f;
+}
+
+// Pass 1: rows of the real field (ng^2 rows of ng) -> half-spectrum rows
+// (frequencies 0..ng/2).  Workgroup g takes rows [g nl, g nl + nl).
+template <bool TWL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows_r2c(const double* __restrict__ f,
+                                                               double2* __restrict__ spec,
+                                                               const double2* __restrict__ tw, FftPlan P,
+                                                               int nl, int ls, int64_t nrows) {
+  extern __shared__ double2 lds[];
+  const int n = P.n, nzh = n / 2 + 1;
+  double2* X = lds;
+  double2* Y = lds + nl * ls;
+  const double2* W = tw;
+  if (TWL) {
+    double2* Wl = Y + nl * ls;
+    for (int i = threadIdx.x; i < n; i += kFftThreads) Wl[i] = tw[i];
+    W = Wl;
+  }
+  const int64_t row0 = int64_t(blockIdx.x) * nl;
+  for (int idx = threadIdx.x; idx < nl * n; idx += kFftThreads) {
+    const int t = idx / n, i = idx - t * n;
+    const int64_t row = row0 + t;
+    X[t * ls + i] = make_double2(row < nrows ? f[row * n + i] : 0.0, 0.0);
+  }
+  __syncthreads();
+  const double2* Z = fft_lines_lds(X, Y, W, P, nl, ls);
+  for (int idx = threadIdx.x; idx < nl * nzh; idx += kFftThreads) {
+    const int t = idx / nzh, i = idx - t * nzh;
+    const int64_t row = row0 + t;
+    if (row < nrows) spec[row * nzh + i] = Z[t * ls + i];
+  }
+}
+
+// Passes 2 and 3: in-place transforms of the half spectrum along an axis.
+// Workgroup g = (outer, tile): lines c = tile nl + t (t < nl, c < nzh),
+// element i of line c at spec[outer ostride + c + i estride].
+template <bool TWL>
+__global__ __launch_bounds__(kFftThreads) void k_fft_cols(double2* __restrict__ spec,
+                                                           const double2* __restrict__ tw, FftPlan P,
+                                                           int nl, int ls, int64_t ntile, int64_t ostride,
+                                                           int64_t estride) {
+  extern __shared__ double2 lds[];
+  const int n = P.n, nzh = n / 2 + 1;
+  double2* X = lds;
+  double2* Y = lds + nl * ls;
+  const double2* W = tw;
+  if (TWL) {
+    double2* Wl = Y + nl * ls;
+    for (int i = threadIdx.x; i < n; i += kFftThreads) Wl[i] = tw[i];
+    W = Wl;
+  }
+  const int64_t outer = int64_t(blockIdx.x) / ntile;
+  const int c0 = int(int64_t(blockIdx.x) - outer * ntile) * nl;
+  double2* base = spec + outer * ostride + c0;
+  for (int idx = threadIdx.x; idx < nl * n; idx += kFftThreads) {
+    const int i = idx / nl, t = idx - i * nl;
+    X[t * ls + i] = c0 + t < nzh ? base[int64_t(i) * estride + t] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const double2* Z = fft_lines_lds(X, Y, W, P, nl, ls);
+  for (int idx = threadIdx.x; idx < nl * n; idx += kFftThreads) {
+    const int i = idx / nl, t = idx - i * nl;
+    if (c0 + t < nzh) base[int64_t(i) * estride + t] = Z[t * ls + i];
+  }
+}
+
+FftPlan make_fft_plan(int64_t n) {
+  FftPlan P{};
+  P.n = int(n);
+  int64_t r = n;
+  auto take = [&](int f) {
+    while (r % f == 0) {
+      if (P.nst >= kFftMaxStages) MAK_FAIL(MAK_EINVAL, "FFT length with too many factors");
+      P.radix[P.nst++] = f;
+      r /= f;
+    }
+  };
+  take(4);
+  take(2);
+  for (int f = 3; r > 1; f += 2) take(f);
+  return P;
+}
+
+template <bool TWL>
+void fft_r2c_3d(const double* field, double2* spec, const double2* tw, int64_t ng, const FftShape& F,
+                hipStream_t st) {
+  const FftPlan P = make_fft_plan(ng);
+  const int64_t nzh = ng / 2 + 1, rows = ng * ng;
+  hipLaunchKernelGGL(k_fft_rows_r2c<TWL>, dim3(unsigned(ceil_div(rows, F.nl))), dim3(kFftThreads), F.lds, st,
+                     field, spec, tw, P, F.nl, F.ls, rows);
+  const int64_t ntile = ceil_div(nzh, F.nl);
+  // middle axis: lines over b for each (a, c)
+  hipLaunchKernelGGL(k_fft_cols<TWL>, dim3(unsigned(ng * ntile)), dim3(kFftThreads), F.lds, st, spec, tw, P,
+                     F.nl, F.ls, ntile, ng * nzh, nzh);
+  // first axis: lines over a for each (b, c)
+  hipLaunchKernelGGL(k_fft_cols<TWL>, dim3(unsigned(ng * ntile)), dim3(kFftThreads), F.lds, st, spec, tw, P,
+                     F.nl, F.ls, ntile, nzh, ng * nzh);
+  MAK_HIP(hipGetLastError());
 }
 
 __global__ __launch_bounds__(64) void k_shell_bin(const double2* __restrict__ spec, int64_t ng,
@@ -132,30 +348,18 @@ __global__ void k_shell_finish(const double* __restrict__ sums, int nbins, doubl
   k_mean[j] = sums[nbins + j] / m;
 }
 
-void fft_check(hipfftResult r, const char* what) {
-  if (r != HIPFFT_SUCCESS)
-    MAK_FAIL(MAK_EHIP, std::string(what) + " failed (hipFFT status " + std::to_string(int(r)) + ")");
-}
-
 }  // namespace
 
-void PowerWork::release_plan() {
-  if (plan) (void)hipfftDestroy(hipfftHandle(plan));
-  plan = 0;
-  ng = 0;
-}
 
 void power_spectrum(PowerWork& w, const double* field, int64_t ng, double L, int nbins, int window,
                     bool contrast, double* k_mean, double* power, int64_t* modes, hipStream_t st) {
   const int64_t nzh = ng / 2 + 1, rows = ng * ng, n = rows * ng;
   if (w.ng != ng) {
-    w.release_plan();
-    hipfftHandle h;
-    fft_check(hipfftPlan3d(&h, int(ng), int(ng), int(ng), HIPFFT_D2Z), "hipfftPlan3d");
-    w.plan = uintptr_t(h);
+    w.tw.ensure(size_t(ng) * sizeof(double2));
+    hipLaunchKernelGGL(k_fft_twiddles, dim3(unsigned(ceil_div(ng, 256))), dim3(256), 0, st, w.tw.as<double2>(), ng);
+    MAK_HIP(hipGetLastError());
     w.ng = ng;
   }
-  fft_check(hipfftSetStream(hipfftHandle(w.plan), st), "hipfftSetStream");
   double norm = L * L * L / (double(ng) * ng * ng * double(ng) * ng * ng);
   if (contrast) {
     const double mean = dev_reduce_sum(field, n, w.tmp, st) / double(n);
@@ -163,14 +367,14 @@ void power_spectrum(PowerWork& w, const double* field, int64_t ng, double L, int
       MAK_FAIL(MAK_EINVAL, "contrast needs a field with a finite, nonzero mean");
     norm /= mean * mean;
   }
-  w.real.ensure(size_t(n) * sizeof(double));
   w.spec.ensure(size_t(rows) * nzh * sizeof(double2));
-  MAK_HIP(hipMemcpyAsync(w.real.p, field, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, st));
   {
-    ProfScope scope("fft", st, double(n), double(n) * 8 + double(rows * nzh) * 16);
-    fft_check(hipfftExecD2Z(hipfftHandle(w.plan), w.real.as<hipfftDoubleReal>(),
-                            w.spec.as<hipfftDoubleComplex>()),
-              "hipfftExecD2Z");
+    ProfScope scope("fft", st, double(n), double(n) * 8 + 5.0 * double(rows * nzh) * 16);
+    const FftShape F = fft_shape(int(ng));
+    if (F.twl)
+      fft_r2c_3d<true>(field, w.spec.as<double2>(), w.tw.as<double2>(), ng, F, st);
+    else
+      fft_r2c_3d<false>(field, w.spec.as<double2>(), w.tw.as<double2>(), ng, F, st);
   }
   int64_t nwg = rows / 16;
   if (nwg < 1) nwg = 1;
