@@ -96,7 +96,7 @@ typedef struct {
                               instead of clipping the row plane by plane; the
                               search that follows is unchanged, so the cells
                               are the same to rounding.  0: off.  Holds about
-                              400 more bytes per site. */
+                              200 more bytes per site. */
   int32_t reserved[2];
 } mak_options;
 

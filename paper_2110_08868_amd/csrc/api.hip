@@ -490,7 +490,7 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
     const bool topo = o.topo_reuse != 0 && N >= 2;
     if (topo) {
       for (CellPass* c : {&ctx->scp, &ctx->scp_trial}) {
-        c->topo_tri.ensure(size_t(N) * kTopoTri * sizeof(uint32_t));
+        c->topo_tri.ensure(size_t(N) * kTopoTri * sizeof(uint16_t));
         c->topo_n.ensure(size_t(N) * sizeof(int32_t));
       }
     }

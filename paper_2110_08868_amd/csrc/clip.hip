@@ -102,9 +102,9 @@ struct ClipArgs {
   const unsigned long long* cert_dmax;
   // Combinatorics reuse: the records of the warm start's pass (read) and of
   // this pass (written); NULL: off.
-  const uint32_t* topo_tri_in;
+  const uint16_t* topo_tri_in;
   const int32_t* topo_n_in;
-  uint32_t* topo_tri_out;
+  uint16_t* topo_tri_out;
   int32_t* topo_n_out;
 };
 
@@ -1034,7 +1034,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       const int64_t wb = A.warm_rp[p];
       const int nw = int(A.warm_rp[p + 1] - wb);
       CPH(ST_TOPO_TRY, ntr > 0 ? 1 : 0);
-      if (ntr >= 4 && ntr <= kTopoTri && nw <= 57 && 6 + nw <= PCAP) {
+      if (ntr >= 4 && ntr <= kTopoTri && nw <= kTopoFaces && 6 + nw <= PCAP) {
         const int np = 6 + nw;
         if (lane < nw) {
           // the planes exactly as the warm list forms them (nearest image)
@@ -1056,9 +1056,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         double X = 0.0, Y = 0.0, Z = 0.0;
         if (lane < ntr) {
           const uint32_t code = A.topo_tri_in[int64_t(p) * kTopoTri + lane];
-          ta = int(code & 63u);
-          tb = int((code >> 6) & 63u);
-          tc = int((code >> 12) & 63u);
+          ta = int(code & 31u);
+          tb = int((code >> 5) & 31u);
+          tc = int((code >> 10) & 31u);
           bad = ta >= np || tb >= np || tc >= np;
           if (!bad) {
             const double4 P1 = S.pl[ta], P2 = S.pl[tb], P3 = S.pl[tc];
@@ -1548,7 +1548,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   if (A.topo_n_out) {
     // This pass's combinatorics for the next one.  Plane codes: a box plane
     // 2 axis + (side < 0); a written face 6 + the rank of its site among the
-    // written faces' sites (its position in the cell's row of J); 63 none.
+    // written faces' sites (its position in the cell's row of J); 31 none.
     // (The cut bitmap is idle now: sites of the written faces, then codes.)
     uint32_t* wj = S.bits;
     uint32_t* pcode = S.bits + PCAP;
@@ -1562,7 +1562,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
 #pragma unroll
     for (int c = 0; c < NPC; ++c) {
       const int f = c * 64 + lane;
-      uint32_t code = 63u;
+      uint32_t code = 31u;
       if (f < nP && S.pj[f] < 0) {
         const int32_t sh = S.ps[f];
 #pragma unroll
@@ -1578,7 +1578,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           rank += (o < me) ? 1 : 0;
           dup = dup || (o == me && g != f);
         }
-        code = rank <= 56 ? uint32_t(6 + rank) : 63u;
+        code = rank < kTopoFaces ? uint32_t(6 + rank) : 31u;
       }
       if (f < PCAP) pcode[f] = code;
     }
@@ -1590,12 +1590,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       rec[k] = 0;
       if (k * 64 + lane < nT) {
         const uint32_t ca = pcode[tri_a(tri[k])], cb = pcode[tri_b(tri[k])], cc = pcode[tri_c(tri[k])];
-        miss = miss || ca == 63u || cb == 63u || cc == 63u;
-        rec[k] = ca | (cb << 6) | (cc << 12);
+        miss = miss || ca == 31u || cb == 31u || cc == 31u;
+        rec[k] = ca | (cb << 5) | (cc << 10);
       }
     }
     const bool ok = nT <= kTopoTri && !ballot(miss || dup);
-    if (ok && lane < nT) A.topo_tri_out[int64_t(p) * kTopoTri + lane] = rec[0];
+    if (ok && lane < nT) A.topo_tri_out[int64_t(p) * kTopoTri + lane] = uint16_t(rec[0]);
     if (lane == 0) A.topo_n_out[p] = ok ? nT : -1;
   }
   if (A.write_faces) {
@@ -1803,15 +1803,15 @@ ClipArgs job_args(PassJob& jb, int stage, int nstage) {
   }
   const CellPass* ti = jb.opt.topo_in;
   if (ti && a.warm_rp && ti->topo_n.cap >= size_t(N) * sizeof(int32_t) &&
-      ti->topo_tri.cap >= size_t(N) * kTopoTri * sizeof(uint32_t)) {
-    a.topo_tri_in = ti->topo_tri.as<uint32_t>();
+      ti->topo_tri.cap >= size_t(N) * kTopoTri * sizeof(uint16_t)) {
+    a.topo_tri_in = ti->topo_tri.as<uint16_t>();
     a.topo_n_in = ti->topo_n.as<int32_t>();
   }
   CellPass* to = jb.opt.topo_out;
   if (to && jb.opt.probe_n <= 0) {  // a probe records nothing
-    if (to->topo_n.cap < size_t(N) * sizeof(int32_t) || to->topo_tri.cap < size_t(N) * kTopoTri * sizeof(uint32_t))
+    if (to->topo_n.cap < size_t(N) * sizeof(int32_t) || to->topo_tri.cap < size_t(N) * kTopoTri * sizeof(uint16_t))
       MAK_FAIL(MAK_EHIP, "combinatorics records not sized");
-    a.topo_tri_out = to->topo_tri.as<uint32_t>();
+    a.topo_tri_out = to->topo_tri.as<uint16_t>();
     a.topo_n_out = to->topo_n.as<int32_t>();
   }
   return a;

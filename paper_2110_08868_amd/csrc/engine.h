@@ -158,19 +158,21 @@ struct CellPass {
   FaceStore& fs() { return shared ? *shared : own; }
   const FaceStore& fs() const { return shared ? *shared : own; }
   // Combinatorics of each cell (when the solver asks for them; see PassOpts).
-  DevBuf topo_tri;   // uint32 [N][kTopoTri]
+  DevBuf topo_tri;   // uint16 [N][kTopoTri]
   DevBuf topo_n;     // int32 [N]: triangles recorded, or -1
 };
 
 // Combinatorics of a cell as a later pass can reuse them: its triangles (the
-// dual of its vertices) with each plane coded in 6 bits as 0..5 (the box of
-// the site's own images) or 6 + r, r the rank of the face's site among the
-// cell's face sites in increasing order, which is its position in the cell's
-// row of J.  A cell with more than kTopoTri triangles, more than 57 faces,
-// two faces with the same site, or a triangle on a plane that wrote no face
-// (area below the pass's threshold) records none.
+// dual of its vertices, three 5-bit plane codes in 16 bits) with each plane
+// coded as 0..5 (the box of the site's own images) or 6 + r, r the rank of
+// the face's site among the cell's face sites in increasing order, which is
+// its position in the cell's row of J.  A cell with more than kTopoTri
+// triangles or kTopoFaces faces, two faces with the same site, or a triangle
+// on a plane that wrote no face (area below the pass's threshold) records
+// none.
 constexpr int kTopoTri = 48;
-constexpr size_t kTopoBytesPerSite = 4 * kTopoTri + 4;
+constexpr int kTopoFaces = 25;
+constexpr size_t kTopoBytesPerSite = 2 * kTopoTri + 4;
 
 // Bytes of device memory per site (and fixed) that one solve holds.
 size_t solve_bytes_per_site(int64_t N);
