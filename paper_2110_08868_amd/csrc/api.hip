@@ -408,6 +408,11 @@ mak_status mak_za_deposit_cells(mak_ctx* ctx, const double* points, const double
     build_pointset(ctx->lps, points, psi, N, L, ctx->opt.grid_occupancy, st);
     PassOpts po;
     po.precision = MAK_FP64;
+    // the pass records each cell's combinatorics: the deposit builds the
+    // moved cells from them instead of clipping their boxes
+    ctx->dcp.topo_tri.ensure(size_t(N) * kTopoTri * sizeof(uint16_t));
+    ctx->dcp.topo_n.ensure(size_t(N) * sizeof(int32_t));
+    po.topo_out = &ctx->dcp;
     ClipStats cs = run_cells(ctx->lps, ctx->dcp, po, st);
     (void)cs;
     FlagStats fs = flag_stats(ctx->lps, ctx->dcp, ctx->tmp, st);

@@ -19,13 +19,19 @@
 // fall on voxel boundaries cut cleanly), the surviving polygons are
 // compacted, the crossing points are gathered (each face's exit point alone
 // when no vertex lies on the plane, else all of them, duplicates dropped), and
-// the new face is their polygon ordered by angle about their centroid.  S_i is clipped out of its box once; then it is cut
-// into the slabs of voxel columns along x, each slab into the columns along
-// y, and a column's voxels are the differences of the volumes below the
-// successive z boundaries (fans from the first vertex of each face, apex at
-// the site).  Masses are summed in 64-bit fixed point (unit L^3 2^-60), so
-// every run gives the same bits; the rounding is at most half a unit per
-// cell and voxel.
+// the new face is their polygon ordered by angle about their centroid.
+// S_i itself is built from the combinatorics the cell pass recorded (its
+// triangles: the homothety keeps them, so each vertex solves its three
+// scaled planes and each face's polygon is the cycle of triangles around
+// it), or, for a cell without a record, clipped out of its box.  It is then
+// cut into the slabs of voxel columns along x and each slab into the columns
+// along y; a column's voxels are the differences of the volumes below the
+// successive z boundaries, each summed face by face over the polygons
+// clipped on the fly and fanned from a point of the boundary plane (the cap
+// in that plane adds nothing, so the clipped polytope is never built).
+// Masses are summed in 64-bit fixed point (unit L^3 2^-60), so every run
+// gives the same bits; the rounding is at most half a unit per cell and
+// voxel.
 #include <cmath>
 
 #include "../../include/mak.h"
@@ -59,6 +65,10 @@ struct DepCellArgs {
   unsigned long long* acc;  // [ng^3]
   unsigned int* status;     // 1: a cell exceeded the polytope capacity or cut degenerately
   int64_t per_xcd;
+  // combinatorics recorded by the cell pass (NULL: build every moved cell by
+  // clipping its box)
+  const uint16_t* topo_tri;
+  const int32_t* topo_n;
 };
 
 struct PolyLDS {
@@ -109,9 +119,13 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
   const double4 me = A.pts[p];
 
   // the cell's planes, scaled to the moved cell (records of the site's own
-  // images, if any, are covered by the box planes)
+  // images, if any, are covered by the box planes).  With a record of the
+  // cell's combinatorics a face's plane goes to slot 6 + the rank of its
+  // site among the face sites (the record's plane codes).
   const int32_t nf = A.nface[p];
   const FaceRec* fr = nf > A.fslot ? A.ovf + A.fbase[p] : A.faces + p * int64_t(A.fslot);
+  const int ntr = A.topo_n ? A.topo_n[p] : -1;
+  const bool ranked = ntr >= 4 && ntr <= kTopoTri && nf <= kTopoFaces;
   int npl = 6;
   for (int base = 0; base < nf; base += 64) {
     const int f = base + lane;
@@ -119,7 +133,13 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
     if (f < nf) r = fr[f];
     const bool use = f < nf && int64_t(r.j) != p;
     const uint64_t m = ballot(use);
-    const int slot = npl + __popcll(m & ((uint64_t(1) << lane) - 1));
+    int slot = npl + __popcll(m & ((uint64_t(1) << lane) - 1));
+    if (ranked) {
+      // (one list of at most kTopoFaces faces, distinct sites)
+      int rank = 0;
+      for (int g = 0; g < nf; ++g) rank += __shfl(r.j, g) < r.j ? 1 : 0;
+      slot = 6 + rank;
+    }
     if (use && slot < kMaxPlanes) {
       const double4 P = A.pts[r.j];
       const double dx = P.x + unpack_shift(r.shift, 0) * L - me.x;
@@ -380,8 +400,11 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
     __syncthreads();
   };
 
-  // polytope volume: fans from each face's first vertex, apex at the site
-  auto volume = [&](int src) -> double {
+  // volume of the part of polytope src below z = zh (seed-local), without
+  // building it: each face's polygon is clipped on the fly (the side tests
+  // and crossing points of `clip`) and fanned from a point of the plane, so
+  // the cap face, which lies in the plane, adds nothing
+  auto volume_below_z = [&](int src, double zh) -> double {
     const int nfc = S.nfc[src];
     double v = 0.0;
     if (lane < nfc) {
@@ -389,9 +412,42 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
       const double* X = &S.vx[src][o];
       const double* Y = &S.vy[src][o];
       const double* Z = &S.vz[src][o];
-      for (int k = 1; k + 1 < nv; ++k)
-        v += X[0] * (Y[k] * Z[k + 1] - Z[k] * Y[k + 1]) + Y[0] * (Z[k] * X[k + 1] - X[k] * Z[k + 1]) +
-             Z[0] * (X[k] * Y[k + 1] - Y[k] * X[k + 1]);
+      const double tol = kSnap * A.L;
+      auto sd = [&](double x, double y, double z) {
+        const double t = side(x, y, z, 0.0, 0.0, 1.0, zh);
+        return fabs(t) <= tol ? 0.0 : t;
+      };
+      int ne = 0;
+      double ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0;
+      auto emit = [&](double x, double y, double z) {
+        const double rz = z - zh;
+        if (ne >= 2)
+          v += ax * (by * rz - bz * y) + ay * (bz * x - bx * rz) + az * (bx * y - by * x);
+        if (ne == 0) {
+          ax = x;
+          ay = y;
+          az = rz;
+        } else {
+          bx = x;
+          by = y;
+          bz = rz;
+        }
+        ++ne;
+      };
+      for (int k = 0; k < nv; ++k) {
+        const int k2 = k + 1 < nv ? k + 1 : 0;
+        const double Px = X[k], Py = Y[k], Pz = Z[k];
+        const double Qx = X[k2], Qy = Y[k2], Qz = Z[k2];
+        const double sP = sd(Px, Py, Pz), sQ = sd(Qx, Qy, Qz);
+        if (sP <= 0.0) emit(Px, Py, Pz);
+        if (sP < 0.0 && sQ > 0.0) {
+          const double t = sP / (sP - sQ);
+          emit(fma(Qx - Px, t, Px), fma(Qy - Py, t, Py), fma(Qz - Pz, t, Pz));
+        } else if (sP > 0.0 && sQ < 0.0) {
+          const double t = sQ / (sQ - sP);
+          emit(fma(Px - Qx, t, Qx), fma(Py - Qy, t, Qy), fma(Pz - Qz, t, Qz));
+        }
+      }
     }
     return wave_sum_d(v) / 6.0;
   };
@@ -416,21 +472,115 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
     v1 = l <= h ? int64_t(floor((org + h) / H + 0.5)) : v0 - 1;
   };
 
-  // the moved cell, built by clipping its box (ping-pong between 0 and 1)
-  int cur = 0, tmp = 1;
-  init_box(cur, -hb, -hb, -hb, hb, hb, hb);
-  for (int k = 0; k < npl; ++k) {
-    const int r = clip(cur, tmp, S.px[k], S.py[k], S.pz[k], S.pb[k]);
-    if (bad || r < 0) {
-      if (bad && lane == 0) atomicOr(A.status, 1u);
-      return;
+  // The moved cell from the recorded combinatorics: the homothety maps the
+  // cell's polytope onto it with the same triangles (vertex t solves its
+  // three scaled planes), and face f's polygon runs counter-clockwise seen
+  // from outside through the triangles around f: after (f, x, y) comes the
+  // triangle holding f followed by y, i.e. (f, y, z).  Each vertex is
+  // computed once, so the faces sharing it hold the same bits.
+  bool built = false;
+  if (ranked) {
+    bool fail = false;
+    int ta = 0, tb = 0, tc = 0;
+    if (lane < ntr) {
+      const uint32_t code = A.topo_tri[p * kTopoTri + lane];
+      ta = int(code & 31u);
+      tb = int((code >> 5) & 31u);
+      tc = int((code >> 10) & 31u);
+      fail = ta >= npl || tb >= npl || tc >= npl;
+      if (!fail) {
+        const double ax = S.px[ta], ay = S.py[ta], az = S.pz[ta], ab = S.pb[ta];
+        const double bx = S.px[tb], by = S.py[tb], bz = S.pz[tb], bbv = S.pb[tb];
+        const double cx = S.px[tc], cy = S.py[tc], cz = S.pz[tc], cb = S.pb[tc];
+        const double c23x = by * cz - bz * cy, c23y = bz * cx - bx * cz, c23z = bx * cy - by * cx;
+        const double c31x = cy * az - cz * ay, c31y = cz * ax - cx * az, c31z = cx * ay - cy * ax;
+        const double c12x = ay * bz - az * by, c12y = az * bx - ax * bz, c12z = ax * by - ay * bx;
+        const double det = ax * c23x + ay * c23y + az * c23z;
+        const double X = (ab * c23x + bbv * c31x + cb * c12x) / det;
+        const double Y = (ab * c23y + bbv * c31y + cb * c12y) / det;
+        const double Z = (ab * c23z + bbv * c31z + cb * c12z) / det;
+        fail = !(isfinite(X) && isfinite(Y) && isfinite(Z));
+        S.cx[lane] = X;
+        S.cy[lane] = Y;
+        S.cz[lane] = Z;
+        S.off[3][lane] = ta | (tb << 8) | (tc << 16);
+      }
     }
-    if (r == tmp) {
-      tmp = cur;
-      cur = r;
+    fail = ballot(fail) != 0;
+    __syncthreads();
+    if (!fail) {
+      // faces: one plane per lane; degree = triangles holding it
+      int deg = 0, t0 = -1;
+      if (lane < npl) {
+        for (int t = 0; t < ntr; ++t) {
+          const int c = S.off[3][t];
+          if ((c & 255) == lane || ((c >> 8) & 255) == lane || ((c >> 16) & 255) == lane) {
+            ++deg;
+            if (t0 < 0) t0 = t;
+          }
+        }
+      }
+      const bool live = deg >= 3;
+      const int dest = wave_incl_scan_i(live ? 1 : 0) - (live ? 1 : 0);
+      const int nlive = __popcll(ballot(live));
+      const int wincl = wave_incl_scan_i(live ? deg : 0);
+      const int wo = wincl - (live ? deg : 0);
+      if (deg == 1 || deg == 2 || readlane_i(wincl, 63) > kPool || nlive > kMaxF) fail = true;
+      if (live && !fail) {
+        // (f, x, y) of the first triangle, rotated to start at f
+        const int c0 = S.off[3][t0];
+        const int a0 = c0 & 255, b0 = (c0 >> 8) & 255, e0 = (c0 >> 16) & 255;
+        int y = a0 == lane ? e0 : (b0 == lane ? a0 : b0);
+        int t = t0;
+        for (int k = 0; k < deg; ++k) {
+          S.vx[0][wo + k] = S.cx[t];
+          S.vy[0][wo + k] = S.cy[t];
+          S.vz[0][wo + k] = S.cz[t];
+          if (k + 1 == deg) break;
+          // the triangle holding f followed by y
+          int nt = -1, ny = 0;
+          for (int u = 0; u < ntr && nt < 0; ++u) {
+            const int c = S.off[3][u];
+            const int a = c & 255, b = (c >> 8) & 255, e = (c >> 16) & 255;
+            if (a == lane && b == y) { nt = u; ny = e; }
+            else if (b == lane && e == y) { nt = u; ny = a; }
+            else if (e == lane && a == y) { nt = u; ny = b; }
+          }
+          if (nt < 0) {
+            fail = true;
+            break;
+          }
+          t = nt;
+          y = ny;
+        }
+        S.off[0][dest] = wo;
+        S.nvs[0][dest] = deg;
+      }
+      fail = ballot(fail) != 0;
+      if (!fail && nlive >= 4) {
+        if (lane == 0) S.nfc[0] = nlive;
+        built = true;
+      }
     }
+    __syncthreads();
   }
-  if (cur != 0) copy(cur, 0);
+  // otherwise built by clipping its box (ping-pong between 0 and 1)
+  if (!built) {
+    int cur = 0, tmp = 1;
+    init_box(cur, -hb, -hb, -hb, hb, hb, hb);
+    for (int k = 0; k < npl; ++k) {
+      const int r = clip(cur, tmp, S.px[k], S.py[k], S.pz[k], S.pb[k]);
+      if (bad || r < 0) {
+        if (bad && lane == 0) atomicOr(A.status, 1u);
+        return;
+      }
+      if (r == tmp) {
+        tmp = cur;
+        cur = r;
+      }
+    }
+    if (cur != 0) copy(cur, 0);
+  }
   // polytopes: 0 the moved cell, 1 a temporary, 2 an x slab, 3 a y column of it
   const double inv3 = 1.0 / (sc * sc * sc);
   int64_t a0, a1;
@@ -463,9 +613,7 @@ __global__ __launch_bounds__(64) void k_cells_deposit(DepCellArgs A) {
       double below = 0.0;
       for (int64_t c = c0; c <= c1; ++c) {
         const double zh = (double(c) + 0.5) * H - me.z;
-        const int zs = clip(ys, 1, 0.0, 0.0, 1.0, zh);
-        if (bad) break;
-        const double vz = zs < 0 ? 0.0 : volume(zs);
+        const double vz = volume_below_z(ys, zh);
         const double part = vz - below;
         below = vz;
         if (lane == 0 && part > 0.0) {
@@ -512,6 +660,10 @@ void za_deposit_cells(const PointSet& ps, const CellPass& cp, double tau, int64_
   status.ensure(sizeof(unsigned int));
   a.acc = acc.as<unsigned long long>();
   a.status = status.as<unsigned int>();
+  if (cp.topo_n.cap >= size_t(n) * sizeof(int32_t) && cp.topo_tri.cap >= size_t(n) * kTopoTri * sizeof(uint16_t)) {
+    a.topo_tri = cp.topo_tri.as<uint16_t>();
+    a.topo_n = cp.topo_n.as<int32_t>();
+  }
   MAK_HIP(hipMemsetAsync(a.acc, 0, size_t(nv) * sizeof(unsigned long long), st));
   MAK_HIP(hipMemsetAsync(a.status, 0, sizeof(unsigned int), st));
   a.per_xcd = ceil_div(n, 8);

@@ -239,7 +239,11 @@ FftPlan make_fft_plan(int64_t n) {
   };
   take(4);
   take(2);
-  for (int f = 3; r > 1; f += 2) take(f);
+  int f = 3;
+  while (r > 1) {
+    take(f);
+    f += 2;
+  }
   return P;
 }
 
