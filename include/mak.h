@@ -78,7 +78,10 @@ typedef struct {
                               three-level additive (point Jacobi, Jacobi on the
                               aggregates of the neighbour-grid blocks, an exact
                               solve on at most 64 aggregates of those), 1 point
-                              Jacobi alone */
+                              Jacobi alone, 2 the three-level form with the
+                              exact level on up to 512 aggregates (fewer CG
+                              iterations on large problems, a costlier set-up
+                              per Newton step) */
   int32_t walk_cert;       /* 1 (default): once the Newton steps are undamped,
                               one cell pass records for each cell the sites
                               that can still cut it while the weights move by

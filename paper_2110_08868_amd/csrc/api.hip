@@ -227,7 +227,7 @@ mak_status mak_create(mak_ctx** out, int device, const mak_options* opt) {
   const int nstage = c->opt.precision == MAK_MIXED ? 3 : 2;
   if (!(c->opt.cg_rtol > 0) || c->opt.max_newton < 0 || c->opt.max_cg < 1 || c->opt.max_halvings < 0 ||
       c->opt.first_stage < 0 || c->opt.first_stage >= nstage || c->opt.cg_precond < 0 ||
-      c->opt.cg_precond > 1 || c->opt.walk_cert < 0 || c->opt.walk_cert > 1 || c->opt.topo_reuse < 0 ||
+      c->opt.cg_precond > 2 || c->opt.walk_cert < 0 || c->opt.walk_cert > 1 || c->opt.topo_reuse < 0 ||
       c->opt.topo_reuse > 1) {
     delete c;
     g_create_error = "invalid options";
@@ -566,8 +566,9 @@ static mak_status solve_impl(mak_ctx* ctx, const double* points, const double* m
       RowBlocks rb;
       rb.cell_start = ps.cell_start.as<int32_t>();
       rb.Gb = ps.g.Gb;
+      rb.agg_per_axis = o.cg_precond == 2 ? 8 : 0;
       const int cgi = pcg_solve(ctx->sJ, ctx->g.as<double>(), ctx->pstep.as<double>(), N, o.cg_rtol,
-                                o.max_cg, ctx->pw, st, warm, o.cg_precond == 0 ? &rb : nullptr);
+                                o.max_cg, ctx->pw, st, warm, o.cg_precond != 1 ? &rb : nullptr);
       si.cg_iters_total += cgi;
       doomed_cells.clear();
       // the smallest cells of the accepted pass follow the doomed ones in the list

@@ -446,6 +446,8 @@ struct PcgWork {
 struct RowBlocks {
   const int32_t* cell_start = nullptr;
   int32_t Gb = 0;
+  // aggregates per axis of the exact level (at most 8): 0 the default, 4
+  int32_t agg_per_axis = 0;
 };
 // Solve J x = b - mean(b) with preconditioned CG to ||r|| <= rtol ||b -
 // mean(b)||; x is overwritten (mean zero on return).  The preconditioner is

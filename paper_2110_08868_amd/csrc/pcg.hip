@@ -342,7 +342,8 @@ __global__ void k_sub_mean(double* __restrict__ x, const double* __restrict__ sc
 // preconditioner.  The sums over a block run in one wavefront in a fixed
 // order: the results are the same bits on every run.
 constexpr int ML_WPB = TPB / WAVE;  // wavefronts (blocks) per workgroup
-constexpr int ML_MAXC = 64;         // aggregates of the exact level
+constexpr int ML_MAXC = 512;        // aggregates of the exact level (8 per axis)
+constexpr int ML_LDSC = 64;         // at most this many: the exact level is inverted in LDS
 
 struct MlGeo {
   const int32_t* cs;  // cell_start: block b rows [cs[64 b], cs[64 b + 64])
@@ -451,11 +452,11 @@ __global__ __launch_bounds__(ML_AGG_TPB) void k_ml_aggsum(MlGeo g, const double*
 // aggregate with no weight to the others, leaves its row and column zero).
 __global__ __launch_bounds__(256) void k_ml_dense(MlGeo g, const double* __restrict__ aggw,
                                                    double* __restrict__ ainv) {
-  __shared__ double A[ML_MAXC][ML_MAXC];
-  __shared__ double rowk[ML_MAXC], fcol[ML_MAXC];
+  __shared__ double A[ML_LDSC][ML_LDSC];
+  __shared__ double rowk[ML_LDSC], fcol[ML_LDSC];
   const int nc = g.nd * g.nd * g.nd;
   const int t = threadIdx.x;
-  for (int e = t; e < ML_MAXC * ML_MAXC; e += 256) A[e / ML_MAXC][e % ML_MAXC] = 0.0;
+  for (int e = t; e < ML_LDSC * ML_LDSC; e += 256) A[e / ML_LDSC][e % ML_LDSC] = 0.0;
   __syncthreads();
   if (t < nc) {
     const int nd = g.nd;
@@ -472,13 +473,13 @@ __global__ __launch_bounds__(256) void k_ml_dense(MlGeo g, const double* __restr
   __syncthreads();
   // symmetrise the off-diagonal part (the two sides of a face are computed
   // apart), then the diagonal = minus the off-diagonal row sum
-  double sym[ML_MAXC * ML_MAXC / 256];
-  for (int e = t, k = 0; e < ML_MAXC * ML_MAXC; e += 256, ++k) {
-    const int i = e / ML_MAXC, j = e % ML_MAXC;
+  double sym[ML_LDSC * ML_LDSC / 256];
+  for (int e = t, k = 0; e < ML_LDSC * ML_LDSC; e += 256, ++k) {
+    const int i = e / ML_LDSC, j = e % ML_LDSC;
     sym[k] = (i < nc && j < nc && i != j) ? 0.5 * (A[i][j] + A[j][i]) : 0.0;
   }
   __syncthreads();
-  for (int e = t, k = 0; e < ML_MAXC * ML_MAXC; e += 256, ++k) A[e / ML_MAXC][e % ML_MAXC] = sym[k];
+  for (int e = t, k = 0; e < ML_LDSC * ML_LDSC; e += 256, ++k) A[e / ML_LDSC][e % ML_LDSC] = sym[k];
   __syncthreads();
   if (t < nc) {
     double sum = 0.0;
@@ -512,6 +513,74 @@ __global__ __launch_bounds__(256) void k_ml_dense(MlGeo g, const double* __restr
     __syncthreads();
   }
   for (int e = t; e < nc * nc; e += 256) ainv[e] = A[e / nc][e % nc];
+}
+
+// The same for up to ML_MAXC aggregates (more than fit in LDS): the matrix
+// is built and eliminated in global memory (the output buffer) by one
+// workgroup; the pivot row and column of each step are staged in LDS.
+__global__ __launch_bounds__(1024) void k_ml_dense_big(MlGeo g, const double* __restrict__ aggw,
+                                                        double* __restrict__ A) {
+  __shared__ double rowk[ML_MAXC], fcol[ML_MAXC];
+  const int nc = g.nd * g.nd * g.nd;
+  const int t = threadIdx.x;
+  constexpr int nt = 1024;
+  for (int e = t; e < nc * nc; e += nt) A[e] = 0.0;
+  __syncthreads();
+  for (int c = t; c < nc; c += nt) {
+    const int nd = g.nd;
+    const int cx = c / (nd * nd), cy = (c / nd) % nd, cz = c % nd;
+    for (int q = 0; q < 27; ++q) {
+      const double v = aggw[27 * c + q];
+      if (v == 0.0) continue;
+      const int ox = (cx + q / 9 - 1 + nd) % nd, oy = (cy + (q / 3) % 3 - 1 + nd) % nd,
+                oz = (cz + q % 3 - 1 + nd) % nd;
+      const int c2 = (ox * nd + oy) * nd + oz;
+      if (c2 != c) A[c * nc + c2] -= v;
+    }
+  }
+  __syncthreads();
+  // symmetrise the off-diagonal part (each pair by one thread), the
+  // diagonal = minus the off-diagonal row sum, pin aggregate 0
+  for (int e = t; e < nc * nc; e += nt) {
+    const int i = e / nc, j = e % nc;
+    if (i < j) {
+      const double v = 0.5 * (A[i * nc + j] + A[j * nc + i]);
+      A[i * nc + j] = v;
+      A[j * nc + i] = v;
+    }
+  }
+  __syncthreads();
+  for (int c = t; c < nc; c += nt) {
+    double sum = 0.0;
+    for (int j = 0; j < nc; ++j) sum += j == c ? 0.0 : A[c * nc + j];
+    fcol[c] = -sum;
+  }
+  __syncthreads();
+  for (int c = t; c < nc; c += nt) A[c * nc + c] = fcol[c];
+  __syncthreads();
+  for (int c = t; c < nc; c += nt) {
+    A[c] = c == 0 ? 1.0 : 0.0;
+    A[c * nc] = c == 0 ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < nc; ++k) {
+    const double piv = A[k * nc + k];
+    const double ip = piv > 0.0 ? 1.0 / piv : 0.0;
+    __syncthreads();
+    for (int c = t; c < nc; c += nt) {
+      rowk[c] = (c == k ? 1.0 : A[k * nc + c]) * ip;
+      fcol[c] = c == k ? 0.0 : A[c * nc + k];
+    }
+    __syncthreads();
+    for (int e = t; e < nc * nc; e += nt) {
+      const int i = e / nc, j = e % nc;
+      if (i == k)
+        A[e] = rowk[j];
+      else
+        A[e] = (j == k ? 0.0 : A[e]) - fcol[i] * rowk[j];
+    }
+    __syncthreads();
+  }
 }
 
 // r = b - mean (- q = J x when warm; else x = 0); p = s = 0; per block the
@@ -599,39 +668,40 @@ __global__ __launch_bounds__(TPB) void k_ml_update(MlGeo g, double* __restrict__
   }
 }
 
-// The exact level in one workgroup: the aggregates' residuals (sixteen
-// threads per aggregate, each summing every sixteenth block, then a fixed
-// tree), the solve e = A2^+ r_agg (sixteen threads per row), and its part
-// of r.u, sum_agg r_agg e_agg (the correction is constant over an
-// aggregate).  The block level's part of r.u comes from the update kernel.
+// The exact level in one workgroup: the aggregates' residuals (tpa threads
+// per aggregate, sixteen for up to 64 aggregates, two for 512, each summing
+// every tpa-th block, then a fixed tree), the solve e = A2^+ r_agg (tpa
+// threads per row), and its part of r.u, sum_agg r_agg e_agg (the
+// correction is constant over an aggregate).  The block level's part of r.u
+// comes from the update kernel.
 constexpr int ML_CTPB = 1024;
 __global__ __launch_bounds__(ML_CTPB) void k_ml_coarse(MlGeo g, const double* __restrict__ r1,
                                                        const double* __restrict__ ainv, double* __restrict__ ec,
                                                        double* __restrict__ scal) {
   __shared__ double rc[ML_MAXC], es[ML_MAXC];
-  static_assert(ML_CTPB >= 16 * ML_MAXC, "sixteen threads per aggregate");
+  static_assert(ML_CTPB >= 2 * ML_MAXC, "two threads per aggregate at least");
   if (scal[S_DONE] != 0.0) return;
   const int nc = g.nd * g.nd * g.nd;
-  const int t = threadIdx.x, c = t / 16, s16 = t % 16;
+  int tpa = 16;
+  while (tpa * nc > ML_CTPB) tpa >>= 1;
+  const int t = threadIdx.x, c = t / tpa, sl = t % tpa;
   const int nblk = g.dv * g.dv * g.dv;
   double v = 0.0;
   if (c < nc) {
 #pragma unroll 4
-    for (int li = s16; li < nblk; li += 16) {
+    for (int li = sl; li < nblk; li += tpa) {
       const int64_t b = ml_agg_block(g, c, li);
       if (b >= 0) v += r1[b];
     }
   }
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) v += __shfl_xor(v, o);
-  if (c < nc && s16 == 0) rc[c] = c == 0 ? 0.0 : v;  // pinned aggregate
+  for (int o = tpa / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  if (c < nc && sl == 0) rc[c] = c == 0 ? 0.0 : v;  // pinned aggregate
   __syncthreads();
   double e = 0.0;
   if (c < nc)
-    for (int j = s16; j < nc; j += 16) e += ainv[c * nc + j] * rc[j];
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) e += __shfl_xor(e, o);
-  if (c < nc && s16 == 0) {
+    for (int j = sl; j < nc; j += tpa) e += ainv[int64_t(c) * nc + j] * rc[j];
+  for (int o = tpa / 2; o >= 1; o >>= 1) e += __shfl_xor(e, o);
+  if (c < nc && sl == 0) {
     e = c == 0 ? 0.0 : e;
     ec[c] = e;
     es[c] = e;
@@ -709,7 +779,13 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
   if (ml) {
     geo.cs = blocks->cell_start;
     geo.Gb = blocks->Gb;
-    geo.dv = int32_t(ceil_div(geo.Gb, 4));    // at most 4 aggregates per axis
+    // at most 4 aggregates per axis (inverted in LDS) unless the caller asks
+    // for 8 (up to 512 aggregates, eliminated in global memory by one
+    // workgroup, ~50 ms per Newton step at 512^3; there it halves the CG
+    // iterations per Newton step, 143 -> 73, but is not the default: the
+    // solve's damped phase took another path, 11 Newton steps instead of 8)
+    const int per_axis = blocks->agg_per_axis > 0 ? blocks->agg_per_axis : 4;
+    geo.dv = int32_t(ceil_div(geo.Gb, per_axis));
     geo.nd = int32_t(ceil_div(geo.Gb, geo.dv));
     geo.nblk = int64_t(geo.Gb) * geo.Gb * geo.Gb;
     nbm = unsigned(std::min<int64_t>(ceil_div(geo.nblk, ML_WPB), MAXB));
@@ -734,7 +810,11 @@ int pcg_solve(const Lap& J, const double* b, double* x, int64_t n, double rtol, 
     const int nc = geo.nd * geo.nd * geo.nd;
     hipLaunchKernelGGL(k_ml_aggsum, dim3(unsigned(nc)), dim3(ML_AGG_TPB), 0, st, geo, w.a1c.as<double>(),
                        w.aggw.as<double>());
-    hipLaunchKernelGGL(k_ml_dense, dim3(1), dim3(256), 0, st, geo, w.aggw.as<double>(), w.ainv.as<double>());
+    if (nc <= ML_LDSC)
+      hipLaunchKernelGGL(k_ml_dense, dim3(1), dim3(256), 0, st, geo, w.aggw.as<double>(), w.ainv.as<double>());
+    else
+      hipLaunchKernelGGL(k_ml_dense_big, dim3(1), dim3(1024), 0, st, geo, w.aggw.as<double>(),
+                         w.ainv.as<double>());
     MAK_HIP(hipGetLastError());
   }
   // u = M^-1 r of the three-level preconditioner, from the blocks' sums r1
