@@ -101,25 +101,37 @@ constexpr int kRegFaces = 32;
 
 __device__ int32_t lap_row_mem(const FaceRec* f, int32_t nf, int32_t* col, float* wf, double* wd,
                                double* diag) {
+  // first the "first face of its column" flags (rows hold at most 128 faces,
+  // the polytope capacity: a 128-bit mask), so the ranks take O(nf^2)
+  uint64_t first_lo = 0, first_hi = 0;
   int32_t cnt = 0;
-  double d = 0.0;
   for (int32_t k = 0; k < nf; ++k) {
+    const int32_t jk = f[k].j;
     bool first = true;
-    for (int32_t m = 0; m < k && first; ++m) first = f[m].j != f[k].j;
+    for (int32_t m = 0; m < k && first; ++m) first = f[m].j != jk;
     if (!first) continue;
     ++cnt;
-    if (!col) continue;
+    if (k < 64)
+      first_lo |= uint64_t(1) << k;
+    else
+      first_hi |= uint64_t(1) << (k - 64);
+  }
+  if (!col) return cnt;
+  auto is_first = [&](int32_t m) {
+    return m < 64 ? ((first_lo >> m) & 1u) != 0 : ((first_hi >> (m - 64)) & 1u) != 0;
+  };
+  double d = 0.0;
+  for (int32_t k = 0; k < nf; ++k) {
+    if (!is_first(k)) continue;
+    const int32_t jk = f[k].j;
     int32_t rank = 0;
     double s = 0.0;
     for (int32_t m = 0; m < nf; ++m) {
-      if (f[m].j == f[k].j) s += f[m].w;
-      if (f[m].j < f[k].j) {
-        bool fm = true;
-        for (int32_t u = 0; u < m && fm; ++u) fm = f[u].j != f[m].j;
-        rank += fm ? 1 : 0;
-      }
+      const int32_t jm = f[m].j;
+      if (jm == jk) s += f[m].w;
+      rank += (jm < jk && is_first(m)) ? 1 : 0;
     }
-    col[rank] = f[k].j;
+    col[rank] = jk;
     if (wf) {
       wf[rank] = float(s);
       d += double(float(s));
