@@ -430,6 +430,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   int nT = 8, nP = 6;
   float bcx = 0.f, bcy = 0.f, bcz = 0.f;
   float brho = float(0.8660254037844386 * L) * 1.0001f;
+  if (!A.warm_rp) {
+    // Without a warm start the first candidates are ordered by the distance
+    // of their planes from the ball's centre: put it at -g, g the slope of
+    // the weights over the site's block (a linear trend g . x in the weights
+    // moves every cell by -g), so the planes nearest the cell are clipped
+    // first and fewer faces are cut only to be cut away again.  The radius
+    // grows by |g| so the ball still holds the box.
+    const int64_t bk0 = block_key(cx >> 2, cy >> 2, cz >> 2, Gb);
+    const float gx = float(A.block_g[3 * bk0]), gy = float(A.block_g[3 * bk0 + 1]),
+                gz = float(A.block_g[3 * bk0 + 2]);
+    const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+    if (gn < 0.5f * float(L)) {
+      bcx = -gx;
+      bcy = -gy;
+      bcz = -gz;
+      brho += gn * 1.0001f;
+    }
+  }
   bool ball_dirty = false;
   float rvert = float(0.8660254037844386 * L) * 1.0001f;  // max vertex distance from x_i
   // axis-aligned bounding box of the vertices (seed-local, widened by far
