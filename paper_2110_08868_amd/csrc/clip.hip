@@ -614,9 +614,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   // Clip by u . d <= bb (plane tag jj / ss).
   auto clip_one = [&](double ddx, double ddy, double ddz, double dbb, double dnd, int32_t jj,
                       int32_t ss) {
-    const double cd = double(bcx) * ddx + double(bcy) * ddy + double(bcz) * ddz;
-    if (cd + double(brho) * dnd <= dbb - mtol) return;  // cannot reach the ball
-    if (aabb_support(ddx, ddy, ddz) <= dbb - mtol) return;  // nor the bounding box
+    if (cmode == 1) {
+      // (outside recording, the batch's own ball and bounding-box tests used
+      // the same ball and box, which stay fixed until the next batch, with
+      // the same threshold and a smaller |d|: there they always pass)
+      const double cd = double(bcx) * ddx + double(bcy) * ddy + double(bcz) * ddz;
+      if (cd + double(brho) * dnd <= dbb - mtol) return;  // cannot reach the ball
+      if (aabb_support(ddx, ddy, ddz) <= dbb - mtol) return;  // nor the bounding box
+    }
     if (A.warm_rp) {
       // with a warm start the walk meets the warm planes again: a plane
       // already in the table is not applied twice
