@@ -227,14 +227,15 @@ __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
   return key;
 }
 
-// Smallest key of the wave: DPP reductions within each row of 16 lanes,
-// then the four row results.
+// Smallest key of the wave (the DPP reduction of the wave sums).
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   v = min(v, uint32_t(dpp_i<kDppXor1>(int(v))));
   v = min(v, uint32_t(dpp_i<kDppXor2>(int(v))));
   v = min(v, uint32_t(dpp_i<kDppHalfMirror>(int(v))));
   v = min(v, uint32_t(dpp_i<kDppMirror>(int(v))));
-  return min(min(readlane_u(v, 0), readlane_u(v, 16)), min(readlane_u(v, 32), readlane_u(v, 48)));
+  v = min(v, uint32_t(bcast_i<kDppBcast15, 0xA>(int(v))));
+  v = min(v, uint32_t(bcast_i<kDppBcast31, 0xC>(int(v))));
+  return readlane_u(v, 63);
 }
 
 // Offset of the t-th block of the Chebyshev shell of radius r (r >= 1).
