@@ -441,7 +441,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     const int64_t bk0 = block_key(cx >> 2, cy >> 2, cz >> 2, Gb);
     const float gx = float(A.block_g[3 * bk0]), gy = float(A.block_g[3 * bk0 + 1]),
                 gz = float(A.block_g[3 * bk0 + 2]);
-    const float gn = sqrtf(gx * gx + gy * gy + gz * gz);
+    const float gn = __builtin_amdgcn_sqrtf(gx * gx + gy * gy + gz * gz);
     if (gn < 0.5f * float(L)) {
       bcx = -gx;
       bcy = -gy;
@@ -508,9 +508,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
     bcx = sx;
     bcy = sy;
     bcz = sz;
-    const float cn = sqrtf(sx * sx + sy * sy + sz * sz);
-    brho = sqrtf(r2) * 1.0001f + 1e-6f * (cn + float(h));
-    rvert = sqrtf(v2) * 1.0001f + 1e-6f * float(h);
+    // (hardware roots: their error, about an ulp, is far inside the margins)
+    const float cn = __builtin_amdgcn_sqrtf(sx * sx + sy * sy + sz * sz);
+    brho = __builtin_amdgcn_sqrtf(r2) * 1.0001f + 1e-6f * (cn + float(h));
+    rvert = __builtin_amdgcn_sqrtf(v2) * 1.0001f + 1e-6f * float(h);
     float lx = FLT_MAX, ly = FLT_MAX, lz = FLT_MAX, hx = -FLT_MAX, hy = -FLT_MAX, hz = -FLT_MAX;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
@@ -1102,10 +1103,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         // the tie tolerance of each plane (float64: eps = eps_scale |d|;
         // float32: the ambiguity band tol_rel (rvert |d| + |b|) with rvert
         // from these vertices), staged in the idle batch slots
-        const double rv = sqrt(wave_max_d(lane < ntr && !bad ? X * X + Y * Y + Z * Z : 0.0)) * 1.0001 + 1e-6 * h;
+        // (float roots enlarged by far more than their error: the bounds only
+        // grow, which keeps the test conservative)
+        const double rv =
+            double(__builtin_amdgcn_sqrtf(float(wave_max_d(lane < ntr && !bad ? X * X + Y * Y + Z * Z : 0.0)))) *
+                1.0001 +
+            1e-6 * h;
         if (lane < np) {
           const double4 Q = S.pl[lane];
-          const double qn = sqrt(Q.x * Q.x + Q.y * Q.y + Q.z * Q.z);
+          const double qn = double(__builtin_amdgcn_sqrtf(float(Q.x * Q.x + Q.y * Q.y + Q.z * Q.z))) * (1.0 + 1e-6);
           S.u.batch.cand[lane].x = kF64 ? eps_scale * qn : double(tol_rel) * (rv * qn + fabs(Q.w));
         }
         __syncthreads();
@@ -1507,7 +1513,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       }
       const double tx = FX[tw], ty = FY[tw], tz = FZ[tw];
       const double4 P = plane_d(f);
-      const double nn = P.x * P.x + P.y * P.y + P.z * P.z;
       // fan apex: the lowest-slot vertex of face f (on the plane, close to
       // the face, so small faces keep their relative precision)
       int t0 = 0;
@@ -1526,7 +1531,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       const double ax = fvx[k] - px, ay = fvy[k] - py, az = fvz[k] - pz;
       const double bx = tx - px, by = ty - py, bz = tz - pz;
       const double crx = ay * bz - az * by, cry = az * bx - ax * bz, crz = ax * by - ay * bx;
-      ar[k][e] = 0.5 * (crx * P.x + cry * P.y + crz * P.z) / sqrt(nn);
+      // twice the fan triangle's area times |d| (divided once per face below)
+      ar[k][e] = crx * P.x + cry * P.y + crz * P.z;
     }
   }
   v6 = wave_sum_d(v6);
@@ -1547,12 +1553,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
   __syncthreads();
   // per-face areas: one lane per plane (faces of the own-image box, tagged
   // j < 0, are not faces of J)
-  double Af[NPC];
+  double Af[NPC], Dn[NPC];
   int nf = 0;
 #pragma unroll
   for (int c = 0; c < NPC; ++c) {
     const int f = c * 64 + lane;
     double a = 0.0;
+    Dn[c] = 1.0;
     const bool real = f < nP && S.pj[f] >= 0;
     if (real) {
 #pragma unroll
@@ -1565,6 +1572,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
           a += tri_a(tr) == f ? FX[t] : (tri_b(tr) == f ? FY[t] : FZ[t]);
         }
       }
+    }
+    if (real) {
+      const double4 P = plane_d(f);
+      Dn[c] = sqrt(P.x * P.x + P.y * P.y + P.z * P.z);
+      a = 0.5 * a / Dn[c];
     }
     Af[c] = (real && a > A.area_min) ? a : 0.0;
     nf += __popcll(ballot(Af[c] > 0.0));
@@ -1643,11 +1655,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       const bool rep = Af[c] > 0.0;
       const uint64_t rm = ballot(rep);
       if (rep && dst) {
-        const double4 P = plane_d(f);
         FaceRec fr;
         fr.j = S.pj[f];
         fr.shift = S.ps[f];
-        fr.w = Af[c] / sqrt(P.x * P.x + P.y * P.y + P.z * P.z);
+        fr.w = Af[c] / Dn[c];
         dst[run + lanes_below(rm)] = fr;
       }
       run += __popcll(rm);
