@@ -707,8 +707,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       }
     }
     __syncthreads();
-    // 3. clear the marks; each plane may start at most one boundary edge
-    bool nm = false;
+    // 3. clear the marks; each plane may start at most one boundary edge:
+    // the starting planes, or-ed into a set, are as many as the edges
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       if ((om[k] >> lane) & 1ull) {
@@ -718,27 +718,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
         clearword(c, a);
         const int st[3] = {a, b, c};
 #pragma unroll
-        for (int e = 0; e < 3; ++e) {
-          if (bm[k] & (1 << e)) {
-            const int x = st[e];
-            const uint32_t old = atomicOr(&S.sbits[x >> 5], 1u << (x & 31));
-            if ((old >> (x & 31)) & 1u) nm = true;
-          }
-        }
+        for (int e = 0; e < 3; ++e)
+          if (bm[k] & (1 << e)) atomicOr(&S.sbits[st[e] >> 5], 1u << (st[e] & 31));
       }
     }
     __syncthreads();
-    if (lane < PW) S.sbits[lane] = 0u;
-    if (ballot(nm)) {
-      flags |= CF_NONMANIFOLD;
-      dead = true;
-      return;
-    }
+    int starts = 0;
+#pragma unroll
+    for (int w = 0; w < PW; ++w) starts += __popc(uint32_t(__builtin_amdgcn_readfirstlane(int(S.sbits[w]))));
+    if (lane < PW) S.sbits[lane] = 0u;  // (after the reads: one wave, in order)
     const int nkept = nT - nout;
     int mynew = 0;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) mynew += __popc(bm[k]);
-    const int nTn = __builtin_amdgcn_readfirstlane(nkept + wave_sum_i(mynew));
+    const int nedge = wave_sum_i(mynew);
+    if (starts != nedge) {
+      flags |= CF_NONMANIFOLD;
+      dead = true;
+      return;
+    }
+    const int nTn = nkept + nedge;
     if (nTn > TCAP) {
       flags |= CF_CAPACITY;
       dead = true;
