@@ -212,19 +212,39 @@ __device__ __forceinline__ int tri_a(uint32_t t) { return int(t & 255u); }
 __device__ __forceinline__ int tri_b(uint32_t t) { return int((t >> 8) & 255u); }
 __device__ __forceinline__ int tri_c(uint32_t t) { return int((t >> 16) & 255u); }
 
+// Key of lane ^ J: quad permutes for 1 and 2 (DPP, no LDS round trip),
+// swizzles (xor mode within 32 lanes) for 4, 8 and 16, a permute for 32.
+template <int J>
+__device__ __forceinline__ uint32_t lane_xor_u32(uint32_t v) {
+  if constexpr (J == 1) return uint32_t(dpp_i<kDppXor1>(int(v)));
+  else if constexpr (J == 2) return uint32_t(dpp_i<kDppXor2>(int(v)));
+  else if constexpr (J < 32) return uint32_t(__builtin_amdgcn_ds_swizzle(int(v), 0x1F | (J << 10)));
+  else return uint32_t(__shfl_xor(int(v), J));
+}
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_stage(uint32_t key, int lane) {
+  const uint32_t other = lane_xor_u32<J>(key);
+  const bool take_min = ((lane & J) == 0) == ((lane & K) == 0);
+  return take_min ? min(key, other) : max(key, other);
+}
+template <int K>
+__device__ __forceinline__ uint32_t bitonic_merge(uint32_t key, int lane) {
+  if constexpr (K >= 64) key = bitonic_stage<K, 32>(key, lane);
+  if constexpr (K >= 32) key = bitonic_stage<K, 16>(key, lane);
+  if constexpr (K >= 16) key = bitonic_stage<K, 8>(key, lane);
+  if constexpr (K >= 8) key = bitonic_stage<K, 4>(key, lane);
+  if constexpr (K >= 4) key = bitonic_stage<K, 2>(key, lane);
+  return bitonic_stage<K, 1>(key, lane);
+}
 // Ascending bitonic sort of one 32-bit key per lane across the wave.
 __device__ __forceinline__ uint32_t wave_sort_u32(uint32_t key) {
   const int lane = lane_id();
-#pragma unroll
-  for (int k = 2; k <= 64; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t other = uint32_t(__shfl_xor(int(key), j));
-      const bool take_min = ((lane & j) == 0) == ((lane & k) == 0);
-      key = take_min ? min(key, other) : max(key, other);
-    }
-  }
-  return key;
+  key = bitonic_merge<2>(key, lane);
+  key = bitonic_merge<4>(key, lane);
+  key = bitonic_merge<8>(key, lane);
+  key = bitonic_merge<16>(key, lane);
+  key = bitonic_merge<32>(key, lane);
+  return bitonic_merge<64>(key, lane);
 }
 
 // Smallest key of the wave (the DPP reduction of the wave sums).
@@ -624,9 +644,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4
       if (cd + double(brho) * dnd <= dbb - mtol) return;  // cannot reach the ball
       if (aabb_support(ddx, ddy, ddz) <= dbb - mtol) return;  // nor the bounding box
     }
-    if (A.warm_rp) {
+    if (A.warm_rp && (cur_ph != 0 || use_cert)) {
       // with a warm start the walk meets the warm planes again: a plane
-      // already in the table is not applied twice
+      // already in the table is not applied twice (the warm list itself
+      // holds distinct sites and meets only the box planes; a certificate
+      // list may follow the reused combinatorics' planes)
       bool same = false;
 #pragma unroll
       for (int c = 0; c < NPC; ++c) {
