@@ -66,8 +66,9 @@ typedef struct {
                               runs every cell in the first kernel and re-runs the
                               cells it cannot finish in the next: float64 path
                               0 = float64, 1 = float64 with the larger polytope
-                              and a wider tie tolerance; mixed path 0 = float32,
-                              1 = float64, 2 = the larger float64 kernel.  A later
+                              and a wider tie tolerance; mixed path 0 = float32
+                              (up to 64 vertices), 1 = float64, 2 = the larger
+                              float64 kernel.  A later
                               first stage runs all cells in that fallback kernel
                               (for testing it). */
   int32_t batch_window_us; /* server only: after the first cell pass is posted the

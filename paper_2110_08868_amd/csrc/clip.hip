@@ -149,7 +149,7 @@ struct FinalCoords {
 template <int N>
 struct FinalCoords<double, N> {};
 
-template <int TPL, typename R>
+template <int TPL, typename R, bool CERT>
 struct ClipLDS {
   // Live planes of a cell are few (faces plus recently cut-away planes): the
   // table holds 64 (128 for the large kernel) and is compacted when full;
@@ -172,8 +172,8 @@ struct ClipLDS {
       // the certificate being recorded (sites, image shifts): alive during
       // the search only, beside the batch (within the size of `fin` on the
       // float32 path, so the LDS per wave does not grow)
-      uint32_t clist[kCertCap];
-      int32_t clsh[kCertCap];
+      uint32_t clist[CERT ? kCertCap : 1];
+      int32_t clsh[CERT ? kCertCap : 1];
     } batch;
   } u;
   uint32_t bits[PCAP * PCAP / 32];   // directed dual edges of removed vertices
@@ -353,20 +353,22 @@ __constant__ int kNearOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1, 7, 19, 25, 3, 5
 
 // Occupancy: the kernel is bound by instruction issue and the latency of its
 // dependent LDS / memory steps, so more waves per SIMD pay even with some
-// registers spilled: 4 waves per SIMD (128 VGPRs; 10 KB LDS per wave fits 16
-// per CU) for the main kernels, 2 for the large-capacity one.
+// registers spilled: 5 waves per SIMD for the float32 first stage (one
+// vertex per lane: 96 VGPRs, 8 KB of LDS per wave outside the certificate
+// instance, 20 waves per CU), 4 for the float64 kernels (128 VGPRs; 11 KB),
+// 2 for the large-capacity one.
 // CERT: the variant that records or uses walk certificates (the extra live
 // state would spill registers in the passes that use neither).
 template <int TPL, typename R, bool STATS, bool CERT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 2 ? 4 : 2))) void k_clip(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5 : (TPL == 2 ? 4 : 2)))) void k_clip(
     ClipBatch B) {
   constexpr bool kF64 = sizeof(R) == 8;
-  constexpr int PCAP = ClipLDS<TPL, R>::PCAP;
-  constexpr int TCAP = ClipLDS<TPL, R>::TCAP;
+  constexpr int PCAP = ClipLDS<TPL, R, CERT>::PCAP;
+  constexpr int TCAP = ClipLDS<TPL, R, CERT>::TCAP;
   constexpr int TW = TCAP / 32;   // words of one membership mask
   constexpr int PW = PCAP / 32;   // words of one bitmap row
   constexpr int NPC = (PCAP + 63) / 64;  // plane chunks of 64 lanes
-  __shared__ ClipLDS<TPL, R> S;
+  __shared__ ClipLDS<TPL, R, CERT> S;
 
   const int lane = threadIdx.x;
   // linear workgroup id (2-D grid above 2^16 workgroups; gridDim.x and every
@@ -1779,7 +1781,9 @@ namespace {
 // Stages: every cell runs in the first kernel; the cells it could not finish
 // (capacity, inconsistent cut, float32 ambiguity) go to the next.
 //   float64: <2 vertices per lane, f64>  ->  <4, f64, wider tie tolerance>
-//   mixed:   <2, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
+//   mixed:   <1, f32>  ->  <2, f64>  ->  <4, f64, wider tie tolerance>
+// (the float32 stage holds 64 vertices: the few cells that need more, about
+// one in 8,000 at psi = 0 on the clustered input, finish in float64)
 // counters of a pass: [0] overflow faces used, [1 + s] cells listed by stage
 // s, [4] doom flag of a line-search trial, [5] a cell that raised it,
 // [kCtrStats ..] work counters,
@@ -1889,7 +1893,7 @@ void launch_stage(PassJob* const* jobs, int n, int stage, int precision, hipStre
   for (int j = n; j <= kMaxJobs; ++j) b.blk_start[j] = nb;
   const bool mixed = precision == MAK_MIXED;
   if (mixed && stage == 0)
-    launch_clip<2, float>(b, outs, st);
+    launch_clip<1, float>(b, outs, st);
   else if (stage < nstage - 1)
     launch_clip<2, double>(b, outs, st);
   else
