@@ -239,6 +239,29 @@ def test_mixed_precision_parity(mctx, case):
     check(mctx, x, psi, 1.0, vol_rel=1e-6, cen_rel=1e-6, area_rel=1e-6)
 
 
+def test_mixed_large_cells(mctx):
+    """Two hub sites, each ringed by 48 or 110 close sites on a sphere, in a
+    displaced lattice: the hubs' cells have 42 and 110 faces, so 80 and 216
+    vertices, beyond the float32 stage's 64 (and, for the second, the 128 of
+    the next stage): they finish in the float64 fallback kernels; every
+    cell to the float64 oracle's bar."""
+    n = 6
+    h = 1.0 / n
+    x = [workloads.zeldovich(n, rms=0.3, smooth=1.0, seed=31)]
+    for centre, k in (((1.5 * h, 1.5 * h, 1.5 * h), 48), ((3.5 * h, 3.5 * h, 4.5 * h), 110)):
+        i = np.arange(k) + 0.5
+        phi = np.arccos(1.0 - 2.0 * i / k)
+        th = np.pi * (1.0 + 5.0 ** 0.5) * i
+        ring = 0.3 * h * np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+        x += [np.asarray(centre)[None, :], np.asarray(centre)[None, :] + ring]
+    x = np.mod(np.vstack(x), 1.0)
+    workloads.assert_distinct(x)
+    V, C, F, info, rep = check(mctx, x, np.zeros(len(x)), 1.0, vol_rel=1e-6, cen_rel=1e-6, area_rel=1e-6)
+    assert info["max_faces"] >= 100
+    assert info["fp64_rerun_cells"] >= 2
+    assert info["overflow_cells"] == 0
+
+
 # ---------------------------------------------------------------- fallback kernels
 @pytest.mark.parametrize("precision,stage", [("fp64", 1), ("mixed", 1), ("mixed", 2)])
 def test_fallback_kernels_alone(precision, stage):
