@@ -162,9 +162,12 @@ struct ClipLDS {
   uint32_t stri[TCAP];
   R sx[TCAP], sy[TCAP], sz[TCAP];
   // the batch of sites being clipped (by lane) while clipping; the float64
-  // final vertices while integrating
+  // final vertices and the plane -> vertex membership masks while integrating
   union {
-    FinalCoords<R, TCAP> fin;
+    struct {
+      FinalCoords<R, TCAP> fin;
+      uint32_t mem[PCAP * TCAP / 32];
+    } ints;
     struct {
       double4 cand[64];
       int32_t candj[64];
@@ -177,7 +180,6 @@ struct ClipLDS {
     } batch;
   } u;
   uint32_t bits[PCAP * PCAP / 32];   // directed dual edges of removed vertices
-  uint32_t mem[PCAP * TCAP / 32];    // plane -> vertex membership (integrals)
   uint32_t sbits[PCAP / 32];
   int32_t cstart[64];
   int32_t cpre[64];
@@ -484,7 +486,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
   const double eps_scale = A.eps_rel * h;
   const R tol_rel = R(A.tol_rel);
   for (int w = lane; w < PCAP * PW; w += 64) S.bits[w] = 0u;
-  for (int w = lane; w < PCAP * (TCAP / 32); w += 64) S.mem[w] = 0u;
   if (lane < PW) S.sbits[lane] = 0u;
   __syncthreads();
 
@@ -1459,9 +1460,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
       fvz[k] = vz[k];
     }
   } else {
-    FX = S.u.fin.x;
-    FY = S.u.fin.y;
-    FZ = S.u.fin.z;
+    FX = S.u.ints.fin.x;
+    FY = S.u.ints.fin.y;
+    FZ = S.u.ints.fin.z;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       fvx[k] = fvy[k] = fvz[k] = 0.0;
@@ -1499,15 +1500,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
     if (lane == 0) A.cert_scale[p] = sc;
   }
   // membership masks: bit t of mask f is set when triangle t contains plane f
+  // (in the LDS the search's batch used: cleared here)
+  __syncthreads();
+  for (int w = lane; w < PCAP * TW; w += 64) S.u.ints.mem[w] = 0u;
+  __syncthreads();
 #pragma unroll
   for (int k = 0; k < TPL; ++k) {
     const int slot = k * 64 + lane;
     if (slot < nT) {
       const uint32_t bit = 1u << (slot & 31);
       const int w = slot >> 5;
-      atomicOr(&S.mem[tri_a(tri[k]) * TW + w], bit);
-      atomicOr(&S.mem[tri_b(tri[k]) * TW + w], bit);
-      atomicOr(&S.mem[tri_c(tri[k]) * TW + w], bit);
+      atomicOr(&S.u.ints.mem[tri_a(tri[k]) * TW + w], bit);
+      atomicOr(&S.u.ints.mem[tri_b(tri[k]) * TW + w], bit);
+      atomicOr(&S.u.ints.mem[tri_c(tri[k]) * TW + w], bit);
     }
   }
   __syncthreads();
@@ -1526,7 +1531,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
       int tw = -1;
 #pragma unroll
       for (int w = 0; w < TW; ++w) {
-        uint32_t m = S.mem[f * TW + w] & S.mem[pr * TW + w];
+        uint32_t m = S.u.ints.mem[f * TW + w] & S.u.ints.mem[pr * TW + w];
         if (w == (slot >> 5)) m &= ~(1u << (slot & 31));
         if (m && tw < 0) tw = w * 32 + __ffs(int(m)) - 1;
       }
@@ -1541,7 +1546,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
       int t0 = 0;
 #pragma unroll
       for (int w = TW - 1; w >= 0; --w) {
-        const uint32_t m = S.mem[f * TW + w];
+        const uint32_t m = S.u.ints.mem[f * TW + w];
         if (m) t0 = w * 32 + __ffs(int(m)) - 1;
       }
       const double px = FX[t0], py = FY[t0], pz = FZ[t0];
@@ -1587,7 +1592,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
     if (real) {
 #pragma unroll
       for (int w = 0; w < TW; ++w) {
-        uint32_t m = S.mem[f * TW + w];
+        uint32_t m = S.u.ints.mem[f * TW + w];
         while (m) {
           const int t = w * 32 + __ffs(int(m)) - 1;
           m &= m - 1;
