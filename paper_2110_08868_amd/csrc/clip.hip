@@ -356,9 +356,9 @@ __constant__ int kNearOrder[27] = {13, 4, 22, 10, 16, 12, 14, 1, 7, 19, 25, 3, 5
 // Occupancy: the kernel is bound by instruction issue and the latency of its
 // dependent LDS / memory steps, so more waves per SIMD pay even with some
 // registers spilled: 5 waves per SIMD for the float32 first stage (one
-// vertex per lane: 96 VGPRs, 8 KB of LDS per wave outside the certificate
-// instance, 20 waves per CU), 4 for the float64 kernels (128 VGPRs; 11 KB),
-// 2 for the large-capacity one.
+// vertex per lane: 96 VGPRs, 7.5 KB of LDS per wave, 20 waves per CU), 4
+// for the float64 kernels (128 VGPRs; 10 KB of LDS outside the certificate
+// instance), 2 for the large-capacity one.
 // CERT: the variant that records or uses walk certificates (the extra live
 // state would spill registers in the passes that use neither).
 template <int TPL, typename R, bool STATS, bool CERT>
