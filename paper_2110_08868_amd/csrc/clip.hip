@@ -503,31 +503,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
   };
 
   auto update_ball = [&]() {
-    float sx = 0.f, sy = 0.f, sz = 0.f;
+    // the vertices' extent and largest distance from the site first; the
+    // ball is centred on the extent's centre (no sums over the vertices)
+    float lx = FLT_MAX, ly = FLT_MAX, lz = FLT_MAX, hx = -FLT_MAX, hy = -FLT_MAX, hz = -FLT_MAX;
+    float v2 = 0.f;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       if (k * 64 + lane < nT) {
-        sx += float(vx[k]);
-        sy += float(vy[k]);
-        sz += float(vz[k]);
+        const float x = float(vx[k]), y = float(vy[k]), z = float(vz[k]);
+        lx = fminf(lx, x);
+        ly = fminf(ly, y);
+        lz = fminf(lz, z);
+        hx = fmaxf(hx, x);
+        hy = fmaxf(hy, y);
+        hz = fmaxf(hz, z);
+        v2 = fmaxf(v2, float(double(vx[k]) * vx[k] + double(vy[k]) * vy[k] + double(vz[k]) * vz[k]));
       }
     }
-    const float inv = 1.0f / float(nT);
     // wave-uniform results are moved to scalar registers
-    sx = uniform_f(wave_sum_f(sx) * inv);
-    sy = uniform_f(wave_sum_f(sy) * inv);
-    sz = uniform_f(wave_sum_f(sz) * inv);
-    float r2 = 0.f, v2 = 0.f;
+    lx = -uniform_f(wave_max_f(-lx));
+    ly = -uniform_f(wave_max_f(-ly));
+    lz = -uniform_f(wave_max_f(-lz));
+    hx = uniform_f(wave_max_f(hx));
+    hy = uniform_f(wave_max_f(hy));
+    hz = uniform_f(wave_max_f(hz));
+    v2 = uniform_f(wave_max_f(v2));
+    const float sx = uniform_f(0.5f * (lx + hx)), sy = uniform_f(0.5f * (ly + hy)), sz = uniform_f(0.5f * (lz + hz));
+    float r2 = 0.f;
 #pragma unroll
     for (int k = 0; k < TPL; ++k) {
       if (k * 64 + lane < nT) {
         const float ex = float(vx[k]) - sx, ey = float(vy[k]) - sy, ez = float(vz[k]) - sz;
         r2 = fmaxf(r2, ex * ex + ey * ey + ez * ez);
-        v2 = fmaxf(v2, float(double(vx[k]) * vx[k] + double(vy[k]) * vy[k] + double(vz[k]) * vz[k]));
       }
     }
     r2 = uniform_f(wave_max_f(r2));
-    v2 = uniform_f(wave_max_f(v2));
     bcx = sx;
     bcy = sy;
     bcz = sz;
@@ -535,25 +545,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(TPL == 1 ? 5
     const float cn = __builtin_amdgcn_sqrtf(sx * sx + sy * sy + sz * sz);
     brho = __builtin_amdgcn_sqrtf(r2) * 1.0001f + 1e-6f * (cn + float(h));
     rvert = __builtin_amdgcn_sqrtf(v2) * 1.0001f + 1e-6f * float(h);
-    float lx = FLT_MAX, ly = FLT_MAX, lz = FLT_MAX, hx = -FLT_MAX, hy = -FLT_MAX, hz = -FLT_MAX;
-#pragma unroll
-    for (int k = 0; k < TPL; ++k) {
-      if (k * 64 + lane < nT) {
-        lx = fminf(lx, float(vx[k]));
-        ly = fminf(ly, float(vy[k]));
-        lz = fminf(lz, float(vz[k]));
-        hx = fmaxf(hx, float(vx[k]));
-        hy = fmaxf(hy, float(vy[k]));
-        hz = fmaxf(hz, float(vz[k]));
-      }
-    }
     const float slack = 1e-5f * (rvert + float(h));
-    blx = -uniform_f(wave_max_f(-lx)) - slack;
-    bly = -uniform_f(wave_max_f(-ly)) - slack;
-    blz = -uniform_f(wave_max_f(-lz)) - slack;
-    bhx = uniform_f(wave_max_f(hx)) + slack;
-    bhy = uniform_f(wave_max_f(hy)) + slack;
-    bhz = uniform_f(wave_max_f(hz)) + slack;
+    blx = lx - slack;
+    bly = ly - slack;
+    blz = lz - slack;
+    bhx = hx + slack;
+    bhy = hy + slack;
+    bhz = hz + slack;
     if (kap > 0.f) {
       // recording: the bounds cover the polytope widened by kappa
       brho += kap;
