@@ -197,6 +197,16 @@ mak_status mak_faces_copy(mak_ctx* ctx, int64_t* face_ptr, int32_t* face_j, int3
 
 /* Damped Newton maximisation of K(psi) from psi = 0 until
  * max_i |V_i - m_i| / m_i <= tol (m_i = L^3 / N).
+ * K is the semi-discrete Kantorovich dual of Eq. SDK, maximised under the
+ * constraint that no Laguerre cell (Eq. laguerrecell) is empty; Sec. 2's
+ * paragraph on the properties of K (concave, C^2) gives the Newton method on
+ * its first and second derivatives, with convergence as in the damped scheme
+ * of Kitagawa, Merigot and Thibert that it cites.  Each Newton system
+ * J p = m - V is solved by preconditioned CG on the Laplacian of the face
+ * areas over seed distances (the Hessian of K, as returned by
+ * mak_laguerre_cells); the step length alpha = 2^-l is the largest with
+ * min_i V_i >= eps0 = 1/2 min(min_i m_i, min_i V_i(0)) and
+ * ||m - V||_2 <= (1 - alpha/2) ||m - V(psi)||_2.
  *   points         DEVICE (N, 3) float64, read only
  *   psi            DEVICE (N,) float64 out: the weights, mean zero
  *   centroids      DEVICE (N, 3) float64 out: cell centroids (the
